@@ -1,0 +1,173 @@
+"""FP64 CPU oracle for the ball-union correlation (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library never does, and this package never
+imports the product library: the two share no code.  Inputs come from the
+seeded generators in ``synth``.
+
+Two oracles, both written from Behandish & Ilies (CAD 2016):
+
+* ``o1_*`` -- the plain method: the score g(R, t) = <f_A, f_{(R,t)B}>
+  (Sec. 3.1 eq. eq_relg_0) of two unions of balls whose defining functions are
+  weighted sums of ball indicators (Sec. 2.1 eq. eq_un, Sec. 2.2 eq. eq_Psum),
+  summed pair by pair as closed-form lens volumes.
+* ``o2_*`` -- the band-limited Fourier route: per-shape spectra from a direct
+  NDFT of the knots (Sec. 2.5 eq. eq_rhoPhat) weighted by each ball's transform,
+  their correlation spectrum F_A conj(F_RB) (Sec. 3.2 eq. eq_ccghat), and an FP64
+  inverse FFT onto an L-periodic translation grid, keeping |m_d| < N/2.
+
+The heavy loops live in ``oracle.c`` (plain C, OpenMP), built on first use with
+gcc into ``liboracle.so`` next to this file.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (FP64, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        d, p, i64, i32 = ctypes.c_double, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        lib.orc_lens_volume.restype = d
+        lib.orc_lens_volume.argtypes = [d, d, d]
+        lib.orc_ball_ft.restype = d
+        lib.orc_ball_ft.argtypes = [d, d]
+        lib.orc_quat_to_rot.argtypes = [p, p]
+        lib.orc_o1_points.argtypes = [p, i64, p, i64, p, p, i64, p]
+        lib.orc_o1_grid.argtypes = [p, i64, p, i64, p, p, d, i32, p]
+        lib.orc_o2_spectrum.argtypes = [p, i64, p, i32, d, p, p]
+        _lib = lib
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def lens_volume(d, a, b):
+    """Volume of the intersection of balls of radii a and b at centre distance d."""
+    lib = _load()
+    d, a, b = np.broadcast_arrays(np.asarray(d, float), np.asarray(a, float), np.asarray(b, float))
+    out = np.array([lib.orc_lens_volume(x, y, z) for x, y, z in zip(d.ravel(), a.ravel(), b.ravel())])
+    return out.reshape(d.shape) if d.shape else float(out[0])
+
+
+def ball_ft(k, r):
+    """Fourier transform of the indicator of a ball of radius r at |k| (rad / length)."""
+    lib = _load()
+    k, r = np.broadcast_arrays(np.asarray(k, float), np.asarray(r, float))
+    out = np.array([lib.orc_ball_ft(x, y) for x, y in zip(k.ravel(), r.ravel())])
+    return out.reshape(k.shape) if k.shape else float(out[0])
+
+
+def quat_to_rot(q) -> np.ndarray:
+    """Row-major rotation matrix of quaternion (w, x, y, z), Hamilton convention."""
+    lib = _load()
+    q = _f64(q)
+    R = np.empty(9)
+    lib.orc_quat_to_rot(_ptr(q), _ptr(R))
+    return R.reshape(3, 3)
+
+
+def o1_points(A, B, R, t) -> np.ndarray:
+    """Plain score sum_ij c_i d_j V(|x_i - R y_j - t|) at each row of t (non-periodic)."""
+    lib = _load()
+    A, B, R, t = _f64(A), _f64(B), _f64(R), _f64(np.atleast_2d(t))
+    out = np.empty(len(t))
+    lib.orc_o1_points(_ptr(A), len(A), _ptr(B), len(B), _ptr(R), _ptr(t), len(t), _ptr(out))
+    return out
+
+
+def o1_grid(A, B, R, origin, h, n) -> np.ndarray:
+    """Plain score on t = origin + h*(ix, iy, iz), returned as [iz][iy][ix] (non-periodic)."""
+    lib = _load()
+    A, B, R, o = _f64(A), _f64(B), _f64(R), _f64(origin)
+    out = np.empty((n, n, n))
+    lib.orc_o1_grid(_ptr(A), len(A), _ptr(B), len(B), _ptr(R), _ptr(o), float(h), int(n), _ptr(out))
+    return out
+
+
+def o2_spectrum(balls, R, n, L) -> np.ndarray:
+    """F(k_m) = sum_i c_i Bhat(|k_m|; r_i) exp(-i k_m . R x_i), k_m = 2 pi m / L.
+
+    Full cube in FFT order, [mz][my][mx]; modes with some m_d = -n/2 are zero.
+    """
+    lib = _load()
+    balls, R = _f64(balls), _f64(R)
+    re = np.empty((n, n, n))
+    im = np.empty((n, n, n))
+    lib.orc_o2_spectrum(_ptr(balls), len(balls), _ptr(R), int(n), float(L), _ptr(re), _ptr(im))
+    return re + 1j * im
+
+
+def mode_numbers(n) -> np.ndarray:
+    """Signed mode number of each FFT-order index of an n-point axis."""
+    i = np.arange(n)
+    return np.where(i < n // 2, i, i - n)
+
+
+def o2_correlation_spectrum(FA, FB, L, origin) -> np.ndarray:
+    """S_m = F_A conj(F_RB) exp(i k_m . origin) / L^3, so that s(t_n) = sum_m S_m exp(2 pi i m.n / N)."""
+    n = FA.shape[0]
+    k = 2.0 * np.pi * mode_numbers(n) / L
+    ph = (np.exp(1j * k * origin[2])[:, None, None] * np.exp(1j * k * origin[1])[None, :, None]
+          * np.exp(1j * k * origin[0])[None, None, :])
+    return FA * np.conj(FB) * ph / L ** 3
+
+
+def o2_scores_from_spectra(FA, FB, L, origin) -> np.ndarray:
+    n = FA.shape[0]
+    S = o2_correlation_spectrum(FA, FB, L, origin)
+    return np.real(np.fft.ifftn(S)) * n ** 3
+
+
+def o2_scores(A, B, q, n, L, origin) -> np.ndarray:
+    """Band-limited score on t_n = origin + (L/n) idx, [iz][iy][ix], for rotation quaternion q."""
+    FA = o2_spectrum(A, np.eye(3), n, L)
+    FB = o2_spectrum(B, quat_to_rot(q), n, L)
+    return o2_scores_from_spectra(FA, FB, L, origin)
+
+
+def o2_eval_at(FA, FB, L, t) -> np.ndarray:
+    """The same band-limited score evaluated at arbitrary translations (direct mode sum)."""
+    n = FA.shape[0]
+    k = 2.0 * np.pi * mode_numbers(n) / L
+    S = FA * np.conj(FB) / L ** 3
+    out = []
+    for p in np.atleast_2d(t):
+        ph = (np.exp(1j * k * p[2])[:, None, None] * np.exp(1j * k * p[1])[None, :, None]
+              * np.exp(1j * k * p[0])[None, None, :])
+        out.append(np.real(np.sum(S * ph)))
+    return np.array(out)
+
+
+def peak(scores) -> tuple:
+    """Largest score of each rotation and its linear index (lowest index on ties)."""
+    s = np.asarray(scores).reshape(scores.shape[0], -1) if np.ndim(scores) == 4 else np.asarray(scores).reshape(1, -1)
+    idx = np.argmax(s, axis=1)
+    return s[np.arange(len(s)), idx], idx

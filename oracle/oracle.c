@@ -1,0 +1,235 @@
+/*
+ * FP64 CPU oracle for the correlation of two unions of balls.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; only the test suite, the smoke check and the CPU baseline
+ * leg of the benchmark load it.  It shares no code, header or table with the
+ * HIP path.
+ *
+ * What it computes (Behandish & Ilies, "Analytic Methods for Geometric Modeling
+ * via Spherical Decomposition"):
+ *
+ *  - A shape is a union of balls whose defining function is the weighted sum of
+ *    ball indicators (union as a sum, Sec. 2.1 eq. eq_un; weighted knots,
+ *    Sec. 2.2 eq. eq_Psum; closed L2 balls, eq. eq_L2ball; the indicator is the
+ *    alpha -> infinity limit of the bump kernel, eq. eq_psi).
+ *  - The score of B moved by (R, t) against A is the inner product
+ *    g(R, t) = <f_A, f_{(R,t)B}> (Sec. 3.1 eq. eq_relg_0), with the motion
+ *    acting as x -> R x + t (App. B).
+ *
+ * o1_*: the plain method.  The inner product of two ball indicators is the
+ * volume of their intersection (the null-volume lemma, Sec. 2.1 eq. eq_null),
+ * a closed-form lens volume V(d; a, b).  Summing over all pairs gives g.
+ *
+ * o2_*: the band-limited Fourier route.  Each ball's indicator has the radial
+ * Fourier transform Bhat(k; r) = 4 pi (sin kr - kr cos kr) / k^3; the shape
+ * transform is the knot NDFT weighted by it (Sec. 2.5 eq. eq_rhoPhat, with the
+ * CFT convention of App. C eq. eq_CFT_int); the correlation spectrum is
+ * F_A * conj(F_RB) (Sec. 3.2 eq. eq_ccghat).  The modes kept are
+ * k = 2 pi m / L for |m_d| < N/2 on an L-periodic box; the Nyquist planes are
+ * left at zero.  The inverse transform to the translation grid is done in
+ * Python with an FP64 FFT.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* Lens volume: volume of B(0, a) intersected with B(d e, b).
+ * Zero when the balls are apart (d >= a + b); the smaller ball's volume when
+ * one contains the other (d <= |a - b|); otherwise the sum of two spherical
+ * caps, which reduces to pi (a+b-d)^2 (d^2 + 2d(a+b) - 3(a-b)^2) / (12 d). */
+double orc_lens_volume(double d, double a, double b)
+{
+    if (d >= a + b) return 0.0;
+    if (d <= fabs(a - b)) {
+        double m = a < b ? a : b;
+        return 4.0 * M_PI * m * m * m / 3.0;
+    }
+    double s = a + b - d;
+    return M_PI * s * s * (d * d + 2.0 * d * (a + b) - 3.0 * (a - b) * (a - b)) / (12.0 * d);
+}
+
+/* Fourier transform of the indicator of B(0, r) at |k| (angular wavenumber,
+ * transform kernel exp(-i k.x)).  For kr < 0.5 the Taylor series of
+ * sin x - x cos x = sum_{n>=1} (-1)^{n+1} 2n x^{2n+1} / (2n+1)! is summed
+ * instead, since the closed form cancels there. */
+double orc_ball_ft(double k, double r)
+{
+    double x = k * r;
+    if (x < 0.5) {
+        /* (sin x - x cos x) / x^3 = sum_{n>=1} (-1)^{n+1} 2n x^{2n-2} / (2n+1)! */
+        double sum = 0.0, xp = 1.0, fact = 6.0;
+        for (int n = 1; n <= 12; ++n) {
+            double t = 2.0 * n * xp / fact;
+            sum += (n % 2 == 1) ? t : -t;
+            xp *= x * x;
+            fact *= (2.0 * n + 2.0) * (2.0 * n + 3.0);
+        }
+        return 4.0 * M_PI * r * r * r * sum;
+    }
+    return 4.0 * M_PI * (sin(x) - x * cos(x)) / (k * k * k);
+}
+
+/* Rotation matrix (row-major) of the unit quaternion q = (w, x, y, z),
+ * Hamilton convention, normalised here. */
+void orc_quat_to_rot(const double *q, double *R)
+{
+    double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    double w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+static void rotate(const double *R, const double *p, double *out)
+{
+    out[0] = R[0] * p[0] + R[1] * p[1] + R[2] * p[2];
+    out[1] = R[3] * p[0] + R[4] * p[1] + R[5] * p[2];
+    out[2] = R[6] * p[0] + R[7] * p[1] + R[8] * p[2];
+}
+
+/* Plain score at arbitrary translations: for each t,
+ * sum_i sum_j c_i d_j V(|x_i - (R y_j + t)|; r_i, rho_j).
+ * Balls are rows (x, y, z, r, w). */
+void orc_o1_points(const double *A, int64_t nA, const double *B, int64_t nB,
+                   const double *R, const double *t, int64_t nt, double *out)
+{
+    double *rb = (double *)malloc(sizeof(double) * 3 * (size_t)(nB > 0 ? nB : 1));
+    for (int64_t j = 0; j < nB; ++j) rotate(R, B + 5 * j, rb + 3 * j);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < nt; ++p) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < nA; ++i) {
+            const double *a = A + 5 * i;
+            for (int64_t j = 0; j < nB; ++j) {
+                double dx = a[0] - (rb[3 * j + 0] + t[3 * p + 0]);
+                double dy = a[1] - (rb[3 * j + 1] + t[3 * p + 1]);
+                double dz = a[2] - (rb[3 * j + 2] + t[3 * p + 2]);
+                double d = sqrt(dx * dx + dy * dy + dz * dz);
+                acc += a[4] * B[5 * j + 4] * orc_lens_volume(d, a[3], B[5 * j + 3]);
+            }
+        }
+        out[p] = acc;
+    }
+    free(rb);
+}
+
+/* Plain score on the grid t = origin + h * (ix, iy, iz), 0 <= i < n, stored
+ * [iz][iy][ix].  Walks the pairs instead of the translations: pair (i, j)
+ * contributes only where |x_i - R y_j - t| < r_i + rho_j, so only grid points
+ * in that ball's bounding box are visited; every skipped term is zero.
+ * Not periodic.  Work is split over z-slabs so that no two threads write the
+ * same output. */
+void orc_o1_grid(const double *A, int64_t nA, const double *B, int64_t nB,
+                 const double *R, const double *origin, double h, int n, double *out)
+{
+    size_t total = (size_t)n * n * n;
+    memset(out, 0, sizeof(double) * total);
+    double *rb = (double *)malloc(sizeof(double) * 3 * (size_t)(nB > 0 ? nB : 1));
+    for (int64_t j = 0; j < nB; ++j) rotate(R, B + 5 * j, rb + 3 * j);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int iz = 0; iz < n; ++iz) {
+        double tz = origin[2] + h * iz;
+        for (int64_t i = 0; i < nA; ++i) {
+            const double *a = A + 5 * i;
+            for (int64_t j = 0; j < nB; ++j) {
+                double reach = a[3] + B[5 * j + 3];
+                /* centre of the support ball in translation space */
+                double cx = a[0] - rb[3 * j + 0], cy = a[1] - rb[3 * j + 1], cz = a[2] - rb[3 * j + 2];
+                if (fabs(tz - cz) >= reach) continue;
+                int x0 = (int)ceil((cx - reach - origin[0]) / h), x1 = (int)floor((cx + reach - origin[0]) / h);
+                int y0 = (int)ceil((cy - reach - origin[1]) / h), y1 = (int)floor((cy + reach - origin[1]) / h);
+                if (x0 < 0) x0 = 0;
+                if (y0 < 0) y0 = 0;
+                if (x1 > n - 1) x1 = n - 1;
+                if (y1 > n - 1) y1 = n - 1;
+                double w = a[4] * B[5 * j + 4];
+                for (int iy = y0; iy <= y1; ++iy) {
+                    double ty = origin[1] + h * iy;
+                    for (int ix = x0; ix <= x1; ++ix) {
+                        double tx = origin[0] + h * ix;
+                        double dx = cx - tx, dy = cy - ty, dz = cz - tz;
+                        double d = sqrt(dx * dx + dy * dy + dz * dz);
+                        out[((size_t)iz * n + iy) * n + ix] += w * orc_lens_volume(d, a[3], B[5 * j + 3]);
+                    }
+                }
+            }
+        }
+    }
+    free(rb);
+}
+
+/* Signed mode number stored at index i of an n-point axis (FFT order). */
+static int mode_of(int i, int n) { return i < n / 2 ? i : i - n; }
+
+/* Band-limited shape spectrum F(k_m) = sum_i c_i Bhat(|k_m|; r_i) exp(-i k_m . R x_i)
+ * with k_m = 2 pi m / L, for every m with |m_d| < n/2, stored in FFT order as
+ * re/im[mz][my][mx] (n^3 each); entries with some m_d = -n/2 stay zero.
+ * exp(-i k.x) is the product of its three axis factors, each from cos/sin;
+ * Bhat is evaluated once per knot for each distinct |m|^2.  Knots are taken in
+ * chunks only so that these per-knot tables stay small: every mode still adds
+ * the knots' terms in knot order. */
+#define ORC_CHUNK 64
+void orc_o2_spectrum(const double *balls, int64_t nb, const double *R, int n, double L,
+                     double *re, double *im)
+{
+    size_t total = (size_t)n * n * n;
+    memset(re, 0, sizeof(double) * total);
+    memset(im, 0, sizeof(double) * total);
+    int half = n / 2;
+    int m2max = 3 * (half - 1) * (half - 1);
+    double dk = 2.0 * M_PI / L;
+    double *bt = (double *)malloc(sizeof(double) * ORC_CHUNK * (size_t)(m2max + 1));
+    double *ef = (double *)malloc(sizeof(double) * ORC_CHUNK * 6 * (size_t)n); /* [knot][axis][i][re,im] */
+    double *cw = (double *)malloc(sizeof(double) * ORC_CHUNK);
+    for (int64_t b0 = 0; b0 < nb; b0 += ORC_CHUNK) {
+        int cnt = (int)((nb - b0) < ORC_CHUNK ? (nb - b0) : ORC_CHUNK);
+#pragma omp parallel for schedule(static)
+        for (int c = 0; c < cnt; ++c) {
+            const double *ball = balls + 5 * (b0 + c);
+            double p[3];
+            rotate(R, ball, p);
+            cw[c] = ball[4];
+            for (int m2 = 0; m2 <= m2max; ++m2)
+                bt[(size_t)c * (m2max + 1) + m2] = orc_ball_ft(dk * sqrt((double)m2), ball[3]);
+            for (int ax = 0; ax < 3; ++ax)
+                for (int i = 0; i < n; ++i) {
+                    double ph = dk * mode_of(i, n) * p[ax];
+                    double *e = ef + (((size_t)c * 3 + ax) * n + i) * 2;
+                    e[0] = cos(ph);
+                    e[1] = -sin(ph);
+                }
+        }
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int iz = 0; iz < n; ++iz) {
+            int mz = mode_of(iz, n);
+            if (mz == -half) continue;
+            for (int c = 0; c < cnt; ++c) {
+                const double *ex = ef + ((size_t)c * 3 + 0) * n * 2;
+                const double *ey = ef + ((size_t)c * 3 + 1) * n * 2;
+                const double *ez = ef + ((size_t)c * 3 + 2) * n * 2 + 2 * iz;
+                const double *b = bt + (size_t)c * (m2max + 1);
+                for (int iy = 0; iy < n; ++iy) {
+                    int my = mode_of(iy, n);
+                    if (my == -half) continue;
+                    double yr = ez[0] * ey[2 * iy] - ez[1] * ey[2 * iy + 1];
+                    double yi = ez[0] * ey[2 * iy + 1] + ez[1] * ey[2 * iy];
+                    size_t row = ((size_t)iz * n + iy) * n;
+                    for (int ix = 0; ix < n; ++ix) {
+                        int mx = mode_of(ix, n);
+                        if (mx == -half) continue;
+                        double s = cw[c] * b[mx * mx + my * my + mz * mz];
+                        re[row + ix] += s * (yr * ex[2 * ix] - yi * ex[2 * ix + 1]);
+                        im[row + ix] += s * (yr * ex[2 * ix + 1] + yi * ex[2 * ix]);
+                    }
+                }
+            }
+        }
+    }
+    free(bt); free(ef); free(cw);
+}
