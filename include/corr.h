@@ -1,0 +1,159 @@
+/*
+ * corr.h -- C ABI of the MI355X ball-union correlation library (libcorr.so).
+ *
+ * Computes the correlation score of two shapes, each a union of weighted balls,
+ * for every translation of a 3D grid and for many rotations:
+ *
+ *     s(R, t) = < f_A , f_{(R,t)B} >  =  sum_i sum_j c_i d_j vol( B(x_i, r_i) & B(R y_j + t, rho_j) )
+ *
+ * (Behandish & Ilies, CAD 2016: the correlation function of Sec. 3.1
+ * eq. eq_relg_0 for defining functions that are sums of ball indicators,
+ * Sec. 2.1 eq. eq_un and Sec. 2.2 eq. eq_Psum; the motion acts as x -> R x + t,
+ * App. B).  It is evaluated by the Fourier route of Sec. 3.2 eq. eq_ccghat:
+ * per-shape spectra by a nonequispaced FFT of the knots (Sec. 2.5
+ * eq. eq_rhoPhat) weighted by the ball transform, their product, and an inverse
+ * FFT onto the translation grid.  The result is the band-limited score: only
+ * the modes k = 2 pi m / L with |m_d| < n/2 of the L-periodic score are kept.
+ *
+ * Conventions
+ *  - Balls are {x, y, z, r, w}: centre, radius (> 0, finite) and weight
+ *    (finite).  Both sets are copied at create; the caller keeps its arrays.
+ *  - Rotations are unit quaternions (w, x, y, z), Hamilton convention; they are
+ *    normalised here; a quaternion of norm < 1e-12 or with a non-finite entry
+ *    is rejected.  B turns about its own frame origin, then moves by t.
+ *  - Translations t = origin + (box / n) * (ix, iy, iz), 0 <= i < n; scores are
+ *    stored [rot][iz][iy][ix] (ix fastest) as float, in volume units.
+ *  - Device pointers are HIP device memory of the device that was current at
+ *    create; all work is enqueued on the stream given at create (NULL = the
+ *    null stream) and is asynchronous: synchronise that stream before reading.
+ *  - Every call returns CORR_OK or a negative error code; no exception crosses
+ *    this boundary.  After an error the context is still valid (or was not
+ *    created) and corr_last_error() holds a message.
+ *  - Calls on one context must not overlap (one host thread at a time).
+ */
+#ifndef CORR_H
+#define CORR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CORR_OK            0
+#define CORR_EINVAL       -1  /* bad argument: value, size, NULL where not allowed */
+#define CORR_ENOMEM       -2  /* device or host allocation failed                  */
+#define CORR_EHIP         -3  /* a HIP runtime call or kernel launch failed         */
+#define CORR_EUNSUPPORTED -4  /* valid but unsupported parameter (grid size, ...)  */
+
+/* flags of corr_grid */
+#define CORR_DETERMINISTIC 1u /* spreading without floating-point atomics          */
+
+typedef struct {
+    double x, y, z; /* centre                */
+    double r;       /* radius, finite, > 0   */
+    double w;       /* weight, finite        */
+} corr_ball;
+
+typedef struct {
+    int32_t n;         /* translations per axis: 16, 32, 64, 128 or 256           */
+    double box;        /* period L > 0 of the translation grid; h = box / n       */
+    double origin[3];  /* translation at index (0, 0, 0)                          */
+    double sigma;      /* oversampling of the spreading grid; 2.0 (0 = default 2) */
+    int32_t kb_width;  /* Kaiser-Bessel window width in fine cells: even, 4..12
+                          (0 = default 8)                                          */
+    double tol;        /* tolerance of the radius expansion of the ball transform,
+                          relative to the largest ball volume (0 = default 1e-6)   */
+    uint32_t flags;    /* CORR_DETERMINISTIC or 0                                  */
+    int32_t batch;     /* rotations per pipeline pass, 1..256 (0 = largest that
+                          fits a 4 GiB workspace, at most 64)                     */
+} corr_grid;
+
+typedef struct corr_ctx corr_ctx;
+
+/* Plan of a context, for reporting and for byte models. */
+typedef struct {
+    int32_t n;          /* translation grid per axis                        */
+    int32_t m;          /* spreading grid per axis (sigma * n)              */
+    int32_t kb_width;   /* window width                                     */
+    int32_t q_a, q_b;   /* radius-expansion components of A and of B        */
+    int64_t n_a, n_b;   /* ball counts                                       */
+    int32_t batch;      /* rotations processed per pipeline pass            */
+    int64_t workspace_bytes; /* device memory held by the context            */
+    double beta;        /* Kaiser-Bessel shape parameter                    */
+    double radius_err_a, radius_err_b; /* achieved expansion error          */
+} corr_info_t;
+
+/*
+ * Create a context for shapes A (fixed) and B (rotated).  Validates the input,
+ * plans the grids and the radius expansion, copies both ball sets to the
+ * device and computes A's spectrum on `hip_stream` (a hipStream_t, or NULL).
+ * Either set may be empty: its scores are then identically zero.
+ * On success *out owns device memory until corr_destroy.
+ */
+int corr_create(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t nB,
+                const corr_grid* grid, void* hip_stream, corr_ctx** out);
+
+/* Recompute A's spectrum from the device-resident balls of A (the first stage
+ * of corr_create, without any host transfer).  Asynchronous. */
+int corr_prepare_a(corr_ctx* ctx);
+
+/*
+ * Score n_rot rotations of B against A.
+ *   quat_wxyz    host array [n_rot][4] (read before return).
+ *   scores_dev   device float [n_rot][n][n][n], or NULL to skip the scores.
+ *   peak_val_dev device float [n_rot] (largest score of each rotation), or NULL.
+ *   peak_idx_dev device int64 [n_rot] (its linear index iz*n*n + iy*n + ix; the
+ *                lowest index wins ties), or NULL; must be NULL iff peak_val_dev is.
+ * n_rot = 0 is allowed and does nothing.  Asynchronous.
+ */
+int corr_eval(corr_ctx* ctx, const double* quat_wxyz, int64_t n_rot,
+              float* scores_dev, float* peak_val_dev, int64_t* peak_idx_dev);
+
+/*
+ * One shape's band-limited spectrum F(k_m) = sum_i c_i Bhat(|k_m|; r_i) exp(-i k_m . R x_i)
+ * (Sec. 2.5 eq. eq_rhoPhat weighted by the ball transform) on the half cube of
+ * modes: out_dev is device float [n][n][n/2][2] (re, im) indexed
+ * [mz][my][mx] with mx = 0 .. n/2-1 and my, mz in FFT order (index i holds mode
+ * i for i < n/2, i - n otherwise; index n/2 holds zero).  which = 0 gives A
+ * (quat ignored), which = 1 gives B turned by quat_wxyz (host, 4 doubles).
+ * Exposes the first three pipeline stages for per-stage checks.  Asynchronous.
+ */
+int corr_spectrum(corr_ctx* ctx, int32_t which, const double* quat_wxyz, float* out_dev);
+
+int corr_info(const corr_ctx* ctx, corr_info_t* out);
+
+/* Stage ids reported by corr_profile_read. */
+#define CORR_STAGE_ZERO           0  /* clear the spreading grids                     */
+#define CORR_STAGE_ROTATE         1  /* a0: turn and place the knots                  */
+#define CORR_STAGE_SPREAD         2  /* a1: Kaiser-Bessel spreading                   */
+#define CORR_STAGE_FFT_X          3  /* a2: forward x pass (real to half-complex)     */
+#define CORR_STAGE_FFT_Y          4  /* a2: forward y pass                            */
+#define CORR_STAGE_FFT_Z_SPECTRUM 5  /* a2 z pass + a3, for A or corr_spectrum        */
+#define CORR_STAGE_FFT_Z_PRODUCT  6  /* a2 z pass + a3 + a4 + inverse z, for B        */
+#define CORR_STAGE_IFFT_Y         7  /* a5: inverse y pass                            */
+#define CORR_STAGE_IFFT_X         8  /* a5: inverse x pass (to real) + block peaks    */
+#define CORR_STAGE_PEAK           9  /* a5: per-rotation peak                         */
+#define CORR_N_STAGES            10
+
+/* Turn per-stage timing on (enable != 0) or off.  While on, every stage launch
+ * on the context's stream is bracketed by a pair of HIP events. */
+int corr_profile(corr_ctx* ctx, int32_t enable);
+
+/* Wait for the context's stream, then write, per stage id < n_stages, the
+ * summed device time in milliseconds (ms) and the number of launches timed
+ * since the last read; clears the record. */
+int corr_profile_read(corr_ctx* ctx, double* ms, int64_t* launches, int32_t n_stages);
+
+/* Free the context and its device memory (waits for its stream).  NULL is a no-op. */
+int corr_destroy(corr_ctx* ctx);
+
+/* Message of the last failed call on ctx; with ctx = NULL, the last failure of
+ * a call without a context on this thread (e.g. corr_create).  Never NULL. */
+const char* corr_last_error(const corr_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CORR_H */

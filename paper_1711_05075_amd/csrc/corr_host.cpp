@@ -1,0 +1,718 @@
+// Host side of libcorr: the C ABI of include/corr.h, input validation, planning
+// (window, grids, radius expansion), device memory and the stage sequence.
+#include "corr.h"
+#include "corr_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using corr::Geom;
+
+namespace {
+
+thread_local std::string g_thread_error = "no error";
+
+struct CorrError {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw CorrError{code, buf};
+}
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? CORR_ENOMEM : CORR_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Radius expansion of the ball transform.
+//
+// Bhat(k; r) = (4 pi / 3) r^3 Phi(k r), Phi(x) = 3 (sin x - x cos x) / x^3.  Over
+// the radii of one shape, f(k, r) = (r / rhi)^3 Phi(k r) is interpolated in r at
+// p Chebyshev points r_b (barycentric basis l_b), and the interpolant is
+// compressed onto the q leading right singular vectors V of the matrix
+// f(k_a, r_b) over the needed wavenumbers.  Then
+//     Bhat(k; r) ~ (4 pi / 3) rhi^3 sum_c [ sum_b f(k, r_b) V_bc ] [ sum_b l_b(r) V_bc ]
+// so every knot spreads q weights c_i u_c(r_i) and the spectrum is the sum of
+// the q component spectra times the k-factors.  q is the smallest count whose
+// error max |f - approx| over the wavenumbers and a dense set of radii is <= tol.
+// Equal radii give q = 1 exactly.
+// ---------------------------------------------------------------------------
+double ball_shape_host(double x) {
+    if (x < 0.5) {
+        double x2 = x * x;
+        return 3.0 * (1.0 / 3.0 - x2 * (1.0 / 30.0 - x2 * (1.0 / 840.0 - x2 * (1.0 / 45360.0 - x2 * (1.0 / 3991680.0 - x2 * (1.0 / 518918400.0))))));
+    }
+    return 3.0 * (std::sin(x) - x * std::cos(x)) / (x * x * x);
+}
+
+struct Expansion {
+    int p = 1, q = 1;
+    double rlo = 1, rhi = 1, err = 0;
+    std::vector<double> nodes;  // [p]
+    std::vector<double> basis;  // [p][q]
+    std::vector<double> bary;   // barycentric weights [p]
+};
+
+// barycentric Lagrange basis l_b(r) at the nodes
+void lagrange_row(const Expansion& e, double r, double* out) {
+    for (int b = 0; b < e.p; ++b)
+        if (r == e.nodes[b]) {
+            for (int j = 0; j < e.p; ++j) out[j] = (j == b) ? 1.0 : 0.0;
+            return;
+        }
+    double s = 0;
+    for (int b = 0; b < e.p; ++b) {
+        out[b] = e.bary[b] / (r - e.nodes[b]);
+        s += out[b];
+    }
+    for (int b = 0; b < e.p; ++b) out[b] /= s;
+}
+
+// cyclic Jacobi eigen-decomposition of a symmetric p x p matrix (row-major);
+// on return a's diagonal holds the eigenvalues and v the eigenvectors (columns).
+void jacobi_eig(std::vector<double>& a, std::vector<double>& v, int p) {
+    v.assign((size_t)p * p, 0.0);
+    for (int i = 0; i < p; ++i) v[(size_t)i * p + i] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0, tot = 0;
+        for (int i = 0; i < p; ++i)
+            for (int j = 0; j < p; ++j) {
+                double x = a[(size_t)i * p + j] * a[(size_t)i * p + j];
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int i = 0; i < p - 1; ++i)
+            for (int j = i + 1; j < p; ++j) {
+                double aij = a[(size_t)i * p + j];
+                if (std::fabs(aij) < 1e-300) continue;
+                double aii = a[(size_t)i * p + i], ajj = a[(size_t)j * p + j];
+                double theta = (ajj - aii) / (2.0 * aij);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < p; ++k) {
+                    double aki = a[(size_t)k * p + i], akj = a[(size_t)k * p + j];
+                    a[(size_t)k * p + i] = c * aki - s * akj;
+                    a[(size_t)k * p + j] = s * aki + c * akj;
+                }
+                for (int k = 0; k < p; ++k) {
+                    double aik = a[(size_t)i * p + k], ajk = a[(size_t)j * p + k];
+                    a[(size_t)i * p + k] = c * aik - s * ajk;
+                    a[(size_t)j * p + k] = s * aik + c * ajk;
+                }
+                for (int k = 0; k < p; ++k) {
+                    double vki = v[(size_t)k * p + i], vkj = v[(size_t)k * p + j];
+                    v[(size_t)k * p + i] = c * vki - s * vkj;
+                    v[(size_t)k * p + j] = s * vki + c * vkj;
+                }
+            }
+    }
+}
+
+Expansion build_expansion(double rlo, double rhi, double dk, int m2n, double tol) {
+    Expansion e;
+    e.rlo = rlo;
+    e.rhi = rhi;
+    if (!(rhi > rlo * (1.0 + 1e-12))) {
+        e.p = e.q = 1;
+        e.nodes = {rhi};
+        e.basis = {1.0};
+        e.bary = {1.0};
+        // radii within 1e-12 relative: the error is that of using rhi for all
+        double kmax = dk * std::sqrt((double)(m2n - 1));
+        double worst = 0;
+        for (int a = 0; a < 257; ++a) {
+            double k = kmax * a / 256.0;
+            double rr = rlo / rhi;
+            worst = std::max(worst, std::fabs(rr * rr * rr * ball_shape_host(k * rlo) - ball_shape_host(k * rhi)));
+        }
+        e.err = worst;
+        return e;
+    }
+    const int p = 64;
+    e.p = p;
+    e.nodes.resize(p);
+    e.bary.resize(p);
+    for (int b = 0; b < p; ++b) {  // Chebyshev extreme points, barycentric weights (-1)^b, halved at the ends
+        e.nodes[b] = 0.5 * (rlo + rhi) + 0.5 * (rhi - rlo) * std::cos(M_PI * b / (p - 1));
+        e.bary[b] = ((b % 2) ? -1.0 : 1.0) * ((b == 0 || b == p - 1) ? 0.5 : 1.0);
+    }
+    auto f = [&](double k, double r) {
+        double rr = r / rhi;
+        return rr * rr * rr * ball_shape_host(k * r);
+    };
+    // rows: every |m|^2 (all needed wavenumbers)
+    std::vector<double> F((size_t)m2n * p);
+    for (int a = 0; a < m2n; ++a) {
+        double k = dk * std::sqrt((double)a);
+        for (int b = 0; b < p; ++b) F[(size_t)a * p + b] = f(k, e.nodes[b]);
+    }
+    std::vector<double> G((size_t)p * p, 0.0);
+    for (int a = 0; a < m2n; ++a) {
+        const double* row = &F[(size_t)a * p];
+        for (int i = 0; i < p; ++i)
+            for (int j = i; j < p; ++j) G[(size_t)i * p + j] += row[i] * row[j];
+    }
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < i; ++j) G[(size_t)i * p + j] = G[(size_t)j * p + i];
+    std::vector<double> V;
+    jacobi_eig(G, V, p);
+    std::vector<int> order(p);
+    for (int i = 0; i < p; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return G[(size_t)x * p + x] > G[(size_t)y * p + y]; });
+    // test radii: the nodes, the midpoints between them and the ends
+    std::vector<double> rt;
+    for (int b = 0; b < p; ++b) rt.push_back(e.nodes[b]);
+    for (int b = 0; b + 1 < p; ++b) rt.push_back(0.5 * (e.nodes[b] + e.nodes[b + 1]));
+    const int nt = (int)rt.size();
+    std::vector<double> L((size_t)nt * p);
+    for (int t = 0; t < nt; ++t) lagrange_row(e, rt[t], &L[(size_t)t * p]);
+    // residual over (wavenumber, test radius); rows sub-sampled for speed, then
+    // the chosen q is re-checked on every row
+    std::vector<double> resid((size_t)m2n * nt);
+    for (int a = 0; a < m2n; ++a) {
+        double k = dk * std::sqrt((double)a);
+        for (int t = 0; t < nt; ++t) resid[(size_t)a * nt + t] = f(k, rt[t]);
+    }
+    std::vector<double> chosen;  // p x q, column-major build
+    int q = 0;
+    double err = 0;
+    std::vector<double> kf(m2n), uf(nt);
+    while (q < std::min(p, 32)) {
+        int col = order[q];
+        for (int a = 0; a < m2n; ++a) {
+            double s = 0;
+            for (int b = 0; b < p; ++b) s += F[(size_t)a * p + b] * V[(size_t)b * p + col];
+            kf[a] = s;
+        }
+        for (int t = 0; t < nt; ++t) {
+            double s = 0;
+            for (int b = 0; b < p; ++b) s += L[(size_t)t * p + b] * V[(size_t)b * p + col];
+            uf[t] = s;
+        }
+        err = 0;
+        for (int a = 0; a < m2n; ++a)
+            for (int t = 0; t < nt; ++t) {
+                double& r = resid[(size_t)a * nt + t];
+                r -= kf[a] * uf[t];
+                err = std::max(err, std::fabs(r));
+            }
+        for (int b = 0; b < p; ++b) chosen.push_back(V[(size_t)b * p + col]);
+        ++q;
+        if (err <= tol) break;
+    }
+    if (err > tol) fail(CORR_EUNSUPPORTED, "radius expansion reaches only %.3g (tolerance %.3g) with 32 components; radii span [%g, %g]",
+                        err, tol, rlo, rhi);
+    e.q = q;
+    e.err = err;
+    e.basis.assign((size_t)p * q, 0.0);
+    for (int c = 0; c < q; ++c)
+        for (int b = 0; b < p; ++b) e.basis[(size_t)b * q + c] = chosen[(size_t)c * p + b];
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DevMem {
+    std::vector<void*> ptrs;
+    size_t bytes = 0;
+    template <class T>
+    T* alloc(size_t count) {
+        if (count == 0) count = 1;
+        size_t nb = count * sizeof(T);
+        if (const char* cap = std::getenv("CORR_TEST_MAX_BYTES")) {
+            if (bytes + nb > (size_t)std::strtoull(cap, nullptr, 10))
+                fail(CORR_ENOMEM, "device allocation of %zu bytes exceeds the CORR_TEST_MAX_BYTES cap", nb);
+        }
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, nb);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(CORR_ENOMEM, "hipMalloc(%zu): %s", nb, hipGetErrorString(e));
+        }
+        ptrs.push_back(p);
+        bytes += nb;
+        return static_cast<T*>(p);
+    }
+    void release() {
+        for (void* p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+struct Shape {
+    int64_t n = 0;
+    Expansion ex;
+    double* pos = nullptr;  // [n][3]
+    float* wts = nullptr;   // [q][n]
+    float* vtab = nullptr;  // [q][m2n]
+};
+
+}  // namespace
+
+struct corr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Geom g;
+    double box = 0, origin[3] = {0, 0, 0}, sigma = 2, tol = 1e-6;
+    uint32_t flags = 0;
+    int batch = 1;
+    int qmax = 1;
+    Shape A, B;
+    DevMem mem;
+    float2 *twm = nullptr, *twn = nullptr;
+    double* deconv = nullptr;
+    double2* phase = nullptr;
+    float2* fa = nullptr;          // fixed shape's spectrum [n][n][half]
+    float* buf0 = nullptr;         // [batch][qmax][m^3] floats (fine grid, reused)
+    float2* buf1 = nullptr;        // [batch][qmax][m^2][half]
+    float4* knots = nullptr;       // [batch][max(nA, nB)]
+    double* quats = nullptr;       // [batch][4]
+    float* pval = nullptr;         // [batch][blocks]
+    int* pidx = nullptr;
+    float* peak_tmp_v = nullptr;   // [batch] when the caller wants no peaks
+    int64_t* peak_tmp_i = nullptr;
+    double* host_quats = nullptr;  // pinned [batch][4]
+    hipEvent_t quat_done = nullptr;
+    // stage timing (corr_profile): event pairs recorded around each launch
+    bool profiling = false;
+    struct Mark { int stage; hipEvent_t a, b; };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> spare;
+    std::string err = "no error";
+};
+
+namespace {
+
+size_t buf0_floats(const corr_ctx* c) { return (size_t)c->qmax * c->g.m * c->g.m * c->g.m; }
+size_t buf1_float2(const corr_ctx* c) { return (size_t)c->qmax * c->g.m * c->g.m * c->g.half; }
+
+void upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync H2D");
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
+void validate_balls(const corr_ball* p, int64_t n, const char* name) {
+    if (n < 0) fail(CORR_EINVAL, "%s: negative ball count %lld", name, (long long)n);
+    if (n > 0 && !p) fail(CORR_EINVAL, "%s: NULL ball array with count %lld", name, (long long)n);
+    if (n > (int64_t)1 << 31) fail(CORR_EUNSUPPORTED, "%s: more than 2^31 balls", name);
+    for (int64_t i = 0; i < n; ++i) {
+        const corr_ball& b = p[i];
+        if (!std::isfinite(b.x) || !std::isfinite(b.y) || !std::isfinite(b.z))
+            fail(CORR_EINVAL, "%s[%lld]: non-finite centre", name, (long long)i);
+        if (!std::isfinite(b.r) || !(b.r > 0)) fail(CORR_EINVAL, "%s[%lld]: radius must be finite and > 0", name, (long long)i);
+        if (!std::isfinite(b.w)) fail(CORR_EINVAL, "%s[%lld]: non-finite weight", name, (long long)i);
+    }
+}
+
+void setup_shape(corr_ctx* c, Shape& s, const corr_ball* balls, int64_t n, double dk) {
+    s.n = n;
+    double rlo = 1.0, rhi = 1.0;
+    if (n > 0) {
+        rlo = rhi = balls[0].r;
+        for (int64_t i = 1; i < n; ++i) {
+            rlo = std::min(rlo, balls[i].r);
+            rhi = std::max(rhi, balls[i].r);
+        }
+    }
+    s.ex = build_expansion(rlo, rhi, dk, c->g.m2n, c->tol);
+}
+
+void upload_shape(corr_ctx* c, Shape& s, const corr_ball* balls, double dk) {
+    const Expansion& e = s.ex;
+    const int64_t n = s.n;
+    s.pos = c->mem.alloc<double>((size_t)3 * std::max<int64_t>(n, 1));
+    s.wts = c->mem.alloc<float>((size_t)e.q * std::max<int64_t>(n, 1));
+    s.vtab = c->mem.alloc<float>((size_t)e.q * c->g.m2n);
+    if (n > 0) {
+        std::vector<double> pos((size_t)3 * n);
+        std::vector<float> w((size_t)e.q * n);
+        std::vector<double> lrow(e.p);
+        for (int64_t i = 0; i < n; ++i) {
+            pos[3 * i] = balls[i].x;
+            pos[3 * i + 1] = balls[i].y;
+            pos[3 * i + 2] = balls[i].z;
+            lagrange_row(e, std::min(std::max(balls[i].r, e.rlo), e.rhi), lrow.data());
+            if (e.p == 1) lrow[0] = std::pow(balls[i].r / e.rhi, 3.0);  // equal radii: exact volume ratio
+            for (int q = 0; q < e.q; ++q) {
+                double u = 0;
+                for (int b = 0; b < e.p; ++b) u += lrow[b] * e.basis[(size_t)b * e.q + q];
+                w[(size_t)q * n + i] = (float)(balls[i].w * u);
+            }
+        }
+        upload(s.pos, pos.data(), sizeof(double) * pos.size(), c->stream);
+        upload(s.wts, w.data(), sizeof(float) * w.size(), c->stream);
+    }
+    double* d_nodes = c->mem.alloc<double>(e.p);
+    double* d_basis = c->mem.alloc<double>((size_t)e.p * e.q);
+    upload(d_nodes, e.nodes.data(), sizeof(double) * e.p, c->stream);
+    upload(d_basis, e.basis.data(), sizeof(double) * e.p * e.q, c->stream);
+    hip_check(corr::launch_ball_table(c->g, dk, d_nodes, d_basis, e.p, e.q, e.rhi, s.vtab, c->stream), "ball table");
+}
+
+hipEvent_t take_event(corr_ctx* c) {
+    if (!c->spare.empty()) {
+        hipEvent_t e = c->spare.back();
+        c->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "hipEventCreate");
+    return e;
+}
+
+// Launch one stage, bracketed by timing events when profiling is on.
+template <class L>
+void stage(corr_ctx* c, int id, const char* what, L&& launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->profiling) {
+        a = take_event(c);
+        b = take_event(c);
+        hip_check(hipEventRecord(a, c->stream), "hipEventRecord");
+    }
+    hip_check(launch(), what);
+    if (c->profiling) {
+        hip_check(hipEventRecord(b, c->stream), "hipEventRecord");
+        c->marks.push_back({id, a, b});
+    }
+}
+
+// Stages a0..a3 for S rotations of one shape; quats are device [S][4].
+void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int S) {
+    const Geom& g = c->g;
+    const int q = s.ex.q;
+    stage(c, CORR_STAGE_ZERO, "zero", [&] { return corr::launch_zero(c->buf0, (size_t)S * q * g.m * g.m * g.m, c->stream); });
+    stage(c, CORR_STAGE_ROTATE, "rotate", [&] { return corr::launch_rotate(g, d_quats, S, s.pos, s.n, c->knots, c->stream); });
+    stage(c, CORR_STAGE_SPREAD, "spread", [&] { return corr::launch_spread(g, c->knots, S, s.n, s.wts, q, c->buf0, c->stream); });
+    stage(c, CORR_STAGE_FFT_X, "fft x", [&] { return corr::launch_fft_x(g, c->buf0, S * q, c->buf1, c->twm, c->stream); });
+    stage(c, CORR_STAGE_FFT_Y, "fft y", [&] {
+        return corr::launch_fft_y(g, c->buf1, S * q, reinterpret_cast<float2*>(c->buf0), c->twm, c->stream);
+    });
+}
+
+void stage_quats(corr_ctx* c, const double* q, int S);
+
+void prepare_a(corr_ctx* c) {
+    static const double ident[4] = {1, 0, 0, 0};
+    stage_quats(c, ident, 1);
+    run_spectrum_stages(c, c->A, c->quats, 1);
+    stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z (A)", [&] {
+        return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->buf0), 1, c->A.ex.q, c->A.vtab, c->deconv,
+                                           c->fa, c->twm, c->stream);
+    });
+}
+
+// host quaternions -> pinned staging -> device, S at a time
+void stage_quats(corr_ctx* c, const double* q, int S) {
+    hip_check(hipEventSynchronize(c->quat_done), "event sync");
+    std::memcpy(c->host_quats, q, sizeof(double) * 4 * S);
+    hip_check(hipMemcpyAsync(c->quats, c->host_quats, sizeof(double) * 4 * S, hipMemcpyHostToDevice, c->stream), "quat H2D");
+    hip_check(hipEventRecord(c->quat_done, c->stream), "event");
+}
+
+void validate_quats(const double* q, int64_t n) {
+    if (n > 0 && !q) fail(CORR_EINVAL, "NULL quaternion array");
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0;
+        for (int k = 0; k < 4; ++k) {
+            if (!std::isfinite(q[4 * i + k])) fail(CORR_EINVAL, "quaternion %lld has a non-finite entry", (long long)i);
+            s += q[4 * i + k] * q[4 * i + k];
+        }
+        if (std::sqrt(s) < 1e-12) fail(CORR_EINVAL, "quaternion %lld has norm < 1e-12", (long long)i);
+    }
+}
+
+template <class F>
+int guarded(corr_ctx* c, F&& body) {
+    try {
+        body();
+        return CORR_OK;
+    } catch (const CorrError& e) {
+        if (c) c->err = e.msg;
+        else g_thread_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (c) c->err = "host allocation failed";
+        else g_thread_error = "host allocation failed";
+        return CORR_ENOMEM;
+    } catch (...) {
+        if (c) c->err = "unexpected internal error";
+        else g_thread_error = "unexpected internal error";
+        return CORR_EHIP;
+    }
+}
+
+void destroy_ctx(corr_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    c->mem.release();
+    if (c->host_quats) (void)hipHostFree(c->host_quats);
+    if (c->quat_done) (void)hipEventDestroy(c->quat_done);
+    for (auto& mk : c->marks) {
+        (void)hipEventDestroy(mk.a);
+        (void)hipEventDestroy(mk.b);
+    }
+    for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int corr_create(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t nB, const corr_grid* grid,
+                void* hip_stream, corr_ctx** out) {
+    corr_ctx* c = nullptr;
+    int rc = guarded(nullptr, [&] {
+        if (!out) fail(CORR_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!grid) fail(CORR_EINVAL, "grid is NULL");
+        validate_balls(A, nA, "A");
+        validate_balls(B, nB, "B");
+        const corr_grid& gr = *grid;
+        if (gr.n != 16 && gr.n != 32 && gr.n != 64 && gr.n != 128 && gr.n != 256)
+            fail(CORR_EUNSUPPORTED, "grid n = %d; supported: 16, 32, 64, 128, 256", gr.n);
+        if (!std::isfinite(gr.box) || !(gr.box > 0)) fail(CORR_EINVAL, "grid box must be finite and > 0");
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(gr.origin[d])) fail(CORR_EINVAL, "grid origin must be finite");
+        double sigma = gr.sigma == 0 ? 2.0 : gr.sigma;
+        if (sigma != 2.0) fail(CORR_EUNSUPPORTED, "sigma = %g; supported: 2", sigma);
+        int w = gr.kb_width == 0 ? 8 : gr.kb_width;
+        if (w < 4 || w > 12 || (w & 1)) fail(CORR_EUNSUPPORTED, "kb_width = %d; supported: even 4..12", w);
+        double tol = gr.tol == 0 ? 1e-6 : gr.tol;
+        if (!std::isfinite(tol) || !(tol > 0) || tol >= 1) fail(CORR_EINVAL, "tol must be in (0, 1)");
+        if (gr.flags & ~CORR_DETERMINISTIC) fail(CORR_EINVAL, "unknown flag bits 0x%x", gr.flags);
+        if (gr.flags & CORR_DETERMINISTIC) fail(CORR_EUNSUPPORTED, "CORR_DETERMINISTIC spreading is not available yet");
+        if (gr.batch < 0 || gr.batch > 256) fail(CORR_EINVAL, "batch = %d; allowed 0..256", gr.batch);
+
+        c = new corr_ctx();
+        hip_check(hipGetDevice(&c->device), "hipGetDevice");
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        c->box = gr.box;
+        std::memcpy(c->origin, gr.origin, sizeof c->origin);
+        c->sigma = sigma;
+        c->tol = tol;
+        c->flags = gr.flags;
+        Geom& g = c->g;
+        g.n = gr.n;
+        g.m = (int)std::lround(sigma * gr.n);
+        g.w = w;
+        g.half = gr.n / 2;
+        g.m2n = 3 * (g.half - 1) * (g.half - 1) + 1;
+        // window shape for oversampling sigma (Beatty, Nishimura & Pauly, 2005)
+        double beta = M_PI * std::sqrt((w / sigma) * (w / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8);
+        g.beta = (float)beta;
+        g.inv_i0beta = (float)(1.0 / std::cyl_bessel_i(0.0, (double)g.beta));
+        g.inv_hf = g.m / gr.box;
+        const double dk = 2.0 * M_PI / gr.box;
+
+        setup_shape(c, c->A, A, nA, dk);
+        setup_shape(c, c->B, B, nB, dk);
+        c->qmax = std::max(c->A.ex.q, c->B.ex.q);
+
+        // batch: rotations per pass, bounded by a 4 GiB workspace
+        size_t per_slot = sizeof(float) * buf0_floats(c) + sizeof(float2) * buf1_float2(c) +
+                          sizeof(float4) * (size_t)std::max<int64_t>(std::max(nA, nB), 1);
+        int batch = gr.batch;
+        if (batch == 0) batch = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 30) / per_slot));
+        c->batch = batch;
+
+        hipDeviceProp_t prop;
+        hip_check(hipGetDeviceProperties(&prop, c->device), "hipGetDeviceProperties");
+        // largest dynamic LDS any stage asks for
+        {
+            int cx = corr::fft_cols_for(g.m, g.m * g.m / 2);
+            int cy = corr::fft_cols_for(g.m, g.half);
+            size_t need = std::max(sizeof(float2) * 2 * (size_t)cx * (g.m + 1),
+                                   sizeof(float2) * ((size_t)2 * cy * g.m + (size_t)cy * g.n));
+            if (need > prop.sharedMemPerBlock)
+                fail(CORR_EUNSUPPORTED, "grid n = %d needs %zu bytes of LDS per workgroup; device has %zu", g.n, need,
+                     (size_t)prop.sharedMemPerBlock);
+        }
+
+        // tables
+        std::vector<float2> tw(g.m);
+        for (int j = 0; j < g.m; ++j) tw[j] = make_float2((float)std::cos(2 * M_PI * j / g.m), (float)-std::sin(2 * M_PI * j / g.m));
+        c->twm = c->mem.alloc<float2>(g.m);
+        upload(c->twm, tw.data(), sizeof(float2) * g.m, c->stream);
+        tw.resize(g.n);
+        for (int j = 0; j < g.n; ++j) tw[j] = make_float2((float)std::cos(2 * M_PI * j / g.n), (float)-std::sin(2 * M_PI * j / g.n));
+        c->twn = c->mem.alloc<float2>(g.n);
+        upload(c->twn, tw.data(), sizeof(float2) * g.n, c->stream);
+        c->deconv = c->mem.alloc<double>(g.n);
+        c->phase = c->mem.alloc<double2>((size_t)3 * g.n);
+        hip_check(corr::launch_deconv_tables(g, c->box, c->origin, c->deconv, c->phase, c->stream), "deconv tables");
+
+        upload_shape(c, c->A, A, dk);
+        upload_shape(c, c->B, B, dk);
+
+        c->fa = c->mem.alloc<float2>((size_t)g.n * g.n * g.half);
+        c->buf0 = c->mem.alloc<float>((size_t)batch * buf0_floats(c));
+        c->buf1 = c->mem.alloc<float2>((size_t)batch * buf1_float2(c));
+        c->knots = c->mem.alloc<float4>((size_t)batch * std::max<int64_t>(std::max(nA, nB), 1));
+        c->quats = c->mem.alloc<double>((size_t)4 * batch);
+        c->pval = c->mem.alloc<float>((size_t)batch * corr::ifft_x_blocks(g));
+        c->pidx = c->mem.alloc<int>((size_t)batch * corr::ifft_x_blocks(g));
+        c->peak_tmp_v = c->mem.alloc<float>(batch);
+        c->peak_tmp_i = c->mem.alloc<int64_t>(batch);
+        hip_check(hipHostMalloc((void**)&c->host_quats, sizeof(double) * 4 * batch, hipHostMallocDefault), "hipHostMalloc");
+        hip_check(hipEventCreateWithFlags(&c->quat_done, hipEventDisableTiming), "hipEventCreate");
+        hip_check(hipEventRecord(c->quat_done, c->stream), "event");
+
+        prepare_a(c);
+        *out = c;
+    });
+    if (rc != CORR_OK && c) destroy_ctx(c);
+    return rc;
+}
+
+int corr_prepare_a(corr_ctx* c) {
+    if (!c) {
+        g_thread_error = "corr_prepare_a: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] { prepare_a(c); });
+}
+
+int corr_eval(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* scores_dev, float* peak_val_dev,
+              int64_t* peak_idx_dev) {
+    if (!c) {
+        g_thread_error = "corr_eval: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] {
+        if (n_rot < 0) fail(CORR_EINVAL, "n_rot < 0");
+        if ((peak_val_dev == nullptr) != (peak_idx_dev == nullptr))
+            fail(CORR_EINVAL, "peak_val_dev and peak_idx_dev must both be set or both be NULL");
+        validate_quats(quat_wxyz, n_rot);
+        const Geom& g = c->g;
+        const size_t n3 = (size_t)g.n * g.n * g.n;
+        const int nb = corr::ifft_x_blocks(g);
+        for (int64_t r0 = 0; r0 < n_rot; r0 += c->batch) {
+            int S = (int)std::min<int64_t>(c->batch, n_rot - r0);
+            stage_quats(c, quat_wxyz + 4 * r0, S);
+            run_spectrum_stages(c, c->B, c->quats, S);
+            stage(c, CORR_STAGE_FFT_Z_PRODUCT, "fft z product", [&] {
+                return corr::launch_fft_z_product(g, reinterpret_cast<float2*>(c->buf0), S, c->B.ex.q, c->B.vtab,
+                                                  c->phase, c->fa, c->buf1, c->twm, c->twn, c->stream);
+            });
+            stage(c, CORR_STAGE_IFFT_Y, "ifft y", [&] {
+                return corr::launch_ifft_y(g, c->buf1, S, reinterpret_cast<float2*>(c->buf0), c->twn, c->stream);
+            });
+            stage(c, CORR_STAGE_IFFT_X, "ifft x", [&] {
+                return corr::launch_ifft_x(g, reinterpret_cast<float2*>(c->buf0), S,
+                                           scores_dev ? scores_dev + (size_t)r0 * n3 : nullptr, c->pval, c->pidx,
+                                           c->twn, c->stream);
+            });
+            if (peak_val_dev)
+                stage(c, CORR_STAGE_PEAK, "peak", [&] {
+                    return corr::launch_peak_final(c->pval, c->pidx, S, nb, peak_val_dev + r0, peak_idx_dev + r0,
+                                                   c->stream);
+                });
+        }
+    });
+}
+
+int corr_spectrum(corr_ctx* c, int32_t which, const double* quat_wxyz, float* out_dev) {
+    if (!c) {
+        g_thread_error = "corr_spectrum: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] {
+        if (which != 0 && which != 1) fail(CORR_EINVAL, "which must be 0 (A) or 1 (B)");
+        if (!out_dev) fail(CORR_EINVAL, "out_dev is NULL");
+        static const double ident[4] = {1, 0, 0, 0};
+        const double* q = which == 0 ? ident : quat_wxyz;
+        validate_quats(q, 1);
+        const Shape& s = which == 0 ? c->A : c->B;
+        stage_quats(c, q, 1);
+        run_spectrum_stages(c, s, c->quats, 1);
+        stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z spectrum", [&] {
+            return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->buf0), 1, s.ex.q, s.vtab, c->deconv,
+                                               reinterpret_cast<float2*>(out_dev), c->twm, c->stream);
+        });
+    });
+}
+
+int corr_info(const corr_ctx* c, corr_info_t* out) {
+    if (!c || !out) {
+        g_thread_error = "corr_info: NULL argument";
+        return CORR_EINVAL;
+    }
+    out->n = c->g.n;
+    out->m = c->g.m;
+    out->kb_width = c->g.w;
+    out->q_a = c->A.ex.q;
+    out->q_b = c->B.ex.q;
+    out->n_a = c->A.n;
+    out->n_b = c->B.n;
+    out->batch = c->batch;
+    out->workspace_bytes = (int64_t)c->mem.bytes;
+    out->beta = c->g.beta;
+    out->radius_err_a = c->A.ex.err;
+    out->radius_err_b = c->B.ex.err;
+    return CORR_OK;
+}
+
+int corr_profile(corr_ctx* c, int32_t enable) {
+    if (!c) {
+        g_thread_error = "corr_profile: NULL context";
+        return CORR_EINVAL;
+    }
+    c->profiling = enable != 0;
+    return CORR_OK;
+}
+
+int corr_profile_read(corr_ctx* c, double* ms, int64_t* launches, int32_t n_stages) {
+    if (!c) {
+        g_thread_error = "corr_profile_read: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] {
+        if (n_stages < 0 || (n_stages > 0 && (!ms || !launches))) fail(CORR_EINVAL, "bad output arrays");
+        for (int i = 0; i < n_stages; ++i) {
+            ms[i] = 0;
+            launches[i] = 0;
+        }
+        hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+        for (auto& mk : c->marks) {
+            float t = 0;
+            hip_check(hipEventElapsedTime(&t, mk.a, mk.b), "hipEventElapsedTime");
+            if (mk.stage < n_stages) {
+                ms[mk.stage] += t;
+                launches[mk.stage] += 1;
+            }
+            c->spare.push_back(mk.a);
+            c->spare.push_back(mk.b);
+        }
+        c->marks.clear();
+    });
+}
+
+int corr_destroy(corr_ctx* c) {
+    destroy_ctx(c);
+    return CORR_OK;
+}
+
+const char* corr_last_error(const corr_ctx* c) {
+    return c ? c->err.c_str() : g_thread_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal interface between the host side (corr_host.cpp) and the gfx950
+// kernels (corr_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace corr {
+
+// Sizes of one correlation grid.
+//   n     translations per axis (the kept modes are |m_d| < n/2)
+//   m     spreading grid per axis (sigma * n), a power of two
+//   w     Kaiser-Bessel window width in spreading cells
+//   m2n   entries of a ball-transform table: |m|^2 = 0 .. 3 (n/2 - 1)^2
+struct Geom {
+    int n = 0, m = 0, w = 0, half = 0, m2n = 0;
+    float beta = 0.f;         // window shape
+    float inv_i0beta = 0.f;   // 1 / I0(beta): window normalised to 1 at its centre
+    double inv_hf = 0.0;      // 1 / spreading-cell size
+};
+
+// Columns handled by one workgroup of a column-FFT kernel: n_len * cols = 4096.
+inline int fft_cols_for(int len, int max_cols) {
+    int c = 4096 / len;
+    if (c > max_cols) c = max_cols;
+    if (c < 1) c = 1;
+    return c;
+}
+
+// ---- table builders (FP64 on the device) ---------------------------------
+hipError_t launch_deconv_tables(const Geom& g, double box, const double origin[3],
+                                double* d_deconv /*[n]*/, double2* d_phase /*[3][n]*/,
+                                hipStream_t st);
+hipError_t launch_ball_table(const Geom& g, double dk, const double* d_nodes, const double* d_basis,
+                             int p, int q, double rhi, float* d_vtab /*[q][m2n]*/, hipStream_t st);
+
+// ---- pipeline stages -----------------------------------------------------
+// a0: turn the knots of S rotations and place them on the spreading grid.
+hipError_t launch_rotate(const Geom& g, const double* d_quats, int S, const double* d_pos,
+                         int64_t nk, float4* d_knots, hipStream_t st);
+hipError_t launch_zero(float* p, size_t count, hipStream_t st);
+// a1: Kaiser-Bessel spreading of q weighted components per knot.
+hipError_t launch_spread(const Geom& g, const float4* d_knots, int S, int64_t nk,
+                         const float* d_wts, int q, float* d_fine, hipStream_t st);
+// a2: pruned forward FFT, x (real to half-complex), then y.
+hipError_t launch_fft_x(const Geom& g, const float* d_fine, int slabs, float2* d_out,
+                        const float2* d_twm, hipStream_t st);
+hipError_t launch_fft_y(const Geom& g, const float2* d_in, int slabs, float2* d_out,
+                        const float2* d_twm, hipStream_t st);
+// a2 (z) + a3: z transform of every component, the radius-expansion sum with the
+// ball-transform table, and the deconvolution; writes the shape spectrum.
+hipError_t launch_fft_z_spectrum(const Geom& g, const float2* d_in, int S, int q,
+                                 const float* d_vtab, const double* d_deconv, float2* d_spec,
+                                 const float2* d_twm, hipStream_t st);
+// a2 (z) + a3 + a4 + first inverse pass of a5: as above for the rotated shape,
+// times the fixed shape's spectrum, the origin phase and 1/L^3, then the
+// inverse z transform.
+hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q,
+                                const float* d_vtab, const double2* d_phase, const float2* d_fa,
+                                float2* d_out, const float2* d_twm, const float2* d_twn,
+                                hipStream_t st);
+// a5: inverse y, then inverse x (half-complex to real) with per-block peaks.
+hipError_t launch_ifft_y(const Geom& g, const float2* d_in, int S, float2* d_out,
+                         const float2* d_twn, hipStream_t st);
+int ifft_x_blocks(const Geom& g);
+hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scores,
+                         float* d_pval, int* d_pidx, const float2* d_twn, hipStream_t st);
+hipError_t launch_peak_final(const float* d_pval, const int* d_pidx, int S, int nblocks,
+                             float* d_peak_val, int64_t* d_peak_idx, hipStream_t st);
+
+}  // namespace corr

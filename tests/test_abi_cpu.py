@@ -1,0 +1,110 @@
+"""C-ABI checks that need no GPU: every declared symbol is exported, and invalid
+arguments are rejected with CORR_EINVAL / CORR_EUNSUPPORTED before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1711_05075_amd as pkg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*|void)\s+\**\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pkg.LIB_PATH):
+        pkg.build.build_library()
+    return pkg.load_library()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared("corr.h")
+    for n in pkg.EXPORTS:
+        assert n in names
+    assert set(names) <= set(pkg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", pkg.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s+(\w+)$", out, flags=re.M))
+    for name in _declared("corr.h"):
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def _grid(**kw):
+    d = dict(n=32, box=4.0, origin=(-2, -2, -2))
+    d.update(kw)
+    return pkg.make_grid(**d)
+
+
+def _create(A, B, g):
+    lib = pkg.load_library()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    out = ctypes.c_void_p()
+    rc = lib.corr_create(A.ctypes.data if A.size else None, len(A), B.ctypes.data if B.size else None, len(B),
+                         ctypes.byref(g), None, ctypes.byref(out))
+    return rc, out
+
+
+GOOD = np.array([[0.0, 0.0, 0.0, 0.05, 1.0], [0.1, 0.0, 0.0, 0.04, 1.0]])
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(n=48), pkg.CORR_EUNSUPPORTED),
+    (dict(n=8), pkg.CORR_EUNSUPPORTED),
+    (dict(box=0.0), pkg.CORR_EINVAL),
+    (dict(box=float("nan")), pkg.CORR_EINVAL),
+    (dict(origin=(0, float("inf"), 0)), pkg.CORR_EINVAL),
+    (dict(sigma=1.5), pkg.CORR_EUNSUPPORTED),
+    (dict(kb_width=7), pkg.CORR_EUNSUPPORTED),
+    (dict(kb_width=14), pkg.CORR_EUNSUPPORTED),
+    (dict(tol=-1.0), pkg.CORR_EINVAL),
+    (dict(tol=2.0), pkg.CORR_EINVAL),
+    (dict(flags=8), pkg.CORR_EINVAL),
+    (dict(batch=-1), pkg.CORR_EINVAL),
+    (dict(batch=1000), pkg.CORR_EINVAL),
+])
+def test_create_rejects_bad_grids(lib, bad, code):
+    rc, out = _create(GOOD, GOOD, _grid(**bad))
+    assert rc == code
+    assert not out.value
+    assert len(pkg.corr_last_error(None)) > 0
+
+
+@pytest.mark.parametrize("col,val", [(3, 0.0), (3, -0.1), (3, float("nan")), (0, float("inf")), (4, float("nan"))])
+def test_create_rejects_bad_balls(lib, col, val):
+    B = GOOD.copy()
+    B[1, col] = val
+    rc, out = _create(GOOD, B, _grid())
+    assert rc == pkg.CORR_EINVAL
+    assert "B[1]" in pkg.corr_last_error(None)
+
+
+def test_create_rejects_null_arguments(lib):
+    out = ctypes.c_void_p()
+    g = _grid()
+    assert lib.corr_create(None, 3, None, 0, ctypes.byref(g), None, ctypes.byref(out)) == pkg.CORR_EINVAL
+    A = np.ascontiguousarray(GOOD)
+    assert lib.corr_create(A.ctypes.data, 2, A.ctypes.data, 2, None, None, ctypes.byref(out)) == pkg.CORR_EINVAL
+    assert lib.corr_create(A.ctypes.data, 2, A.ctypes.data, 2, ctypes.byref(g), None, None) == pkg.CORR_EINVAL
+    assert lib.corr_create(A.ctypes.data, -1, A.ctypes.data, 2, ctypes.byref(g), None, ctypes.byref(out)) == pkg.CORR_EINVAL
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    assert lib.corr_eval(None, None, 0, None, None, None) == pkg.CORR_EINVAL
+    assert lib.corr_prepare_a(None) == pkg.CORR_EINVAL
+    assert lib.corr_spectrum(None, 0, None, None) == pkg.CORR_EINVAL
+    assert lib.corr_info(None, None) == pkg.CORR_EINVAL
+    assert lib.corr_destroy(None) == pkg.CORR_OK
+    assert "NULL" in pkg.corr_last_error(None)
