@@ -33,15 +33,14 @@ def stage_bytes(info, n_rot_per_launch, n_b):
     h = n // 2
     S = n_rot_per_launch
     qb = info["q_b"]
-    fine = 4 * qb * m ** 3
+    w = info["kb_width"]
     xout = 8 * qb * m * m * h
     yout = 8 * qb * m * n * h
     spec = 8 * n * n * h
     return {
-        "zero": S * fine,
-        "rotate": S * n_b * (24 + 16),
-        "spread": S * (fine + n_b * (16 + 4 * qb)),
-        "fft_x": S * (fine + xout),
+        "rotate": S * n_b * (24 + 8 + 12 * w),
+        "bin": S * n_b * 12,
+        "spread_fft_x": S * (n_b * (8 + 12 * w + 4 * qb) + xout),
         "fft_y": S * (xout + yout),
         "fft_z_product": S * (yout + 2 * spec) + spec,
         "ifft_y": S * 2 * spec,

@@ -47,7 +47,8 @@ extern "C" {
 #define CORR_EUNSUPPORTED -4  /* valid but unsupported parameter (grid size, ...)  */
 
 /* flags of corr_grid */
-#define CORR_DETERMINISTIC 1u /* spreading without floating-point atomics          */
+#define CORR_DETERMINISTIC 1u /* bit-reproducible results; every path already is:
+                                 spreading uses no floating-point atomics           */
 
 typedef struct {
     double x, y, z; /* centre                */
@@ -124,17 +125,16 @@ int corr_spectrum(corr_ctx* ctx, int32_t which, const double* quat_wxyz, float* 
 int corr_info(const corr_ctx* ctx, corr_info_t* out);
 
 /* Stage ids reported by corr_profile_read. */
-#define CORR_STAGE_ZERO           0  /* clear the spreading grids                     */
-#define CORR_STAGE_ROTATE         1  /* a0: turn and place the knots                  */
-#define CORR_STAGE_SPREAD         2  /* a1: Kaiser-Bessel spreading                   */
-#define CORR_STAGE_FFT_X          3  /* a2: forward x pass (real to half-complex)     */
-#define CORR_STAGE_FFT_Y          4  /* a2: forward y pass                            */
-#define CORR_STAGE_FFT_Z_SPECTRUM 5  /* a2 z pass + a3, for A or corr_spectrum        */
-#define CORR_STAGE_FFT_Z_PRODUCT  6  /* a2 z pass + a3 + a4 + inverse z, for B        */
-#define CORR_STAGE_IFFT_Y         7  /* a5: inverse y pass                            */
-#define CORR_STAGE_IFFT_X         8  /* a5: inverse x pass (to real) + block peaks    */
-#define CORR_STAGE_PEAK           9  /* a5: per-rotation peak                         */
-#define CORR_N_STAGES            10
+#define CORR_STAGE_ROTATE         0  /* a0: turn and place the knots, window weights  */
+#define CORR_STAGE_BIN            1  /* a0: stable counting sort of knots by z-cell    */
+#define CORR_STAGE_SPREAD_FFT_X   2  /* a1 + a2: spreading fused with the x pass      */
+#define CORR_STAGE_FFT_Y          3  /* a2: forward y pass                            */
+#define CORR_STAGE_FFT_Z_SPECTRUM 4  /* a2 z pass + a3, for A or corr_spectrum        */
+#define CORR_STAGE_FFT_Z_PRODUCT  5  /* a2 z pass + a3 + a4 + inverse z, for B        */
+#define CORR_STAGE_IFFT_Y         6  /* a5: inverse y pass                            */
+#define CORR_STAGE_IFFT_X         7  /* a5: inverse x pass (to real) + block peaks    */
+#define CORR_STAGE_PEAK           8  /* a5: per-rotation peak                         */
+#define CORR_N_STAGES             9
 
 /* Turn per-stage timing on (enable != 0) or off.  While on, every stage launch
  * on the context's stream is bracketed by a pair of HIP events. */

@@ -30,7 +30,7 @@ CORR_DETERMINISTIC = 1
 
 EXPORTS = ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
            "corr_profile_read", "corr_destroy", "corr_last_error")
-STAGES = ("zero", "rotate", "spread", "fft_x", "fft_y", "fft_z_spectrum", "fft_z_product", "ifft_y", "ifft_x", "peak")
+STAGES = ("rotate", "bin", "spread_fft_x", "fft_y", "fft_z_spectrum", "fft_z_product", "ifft_y", "ifft_x", "peak")
 
 
 class corr_grid(ctypes.Structure):

@@ -260,6 +260,7 @@ struct DevMem {
 struct Shape {
     int64_t n = 0;
     Expansion ex;
+    float fix_scale = 1.0f;  // fixed-point scale of the spreading sums
     double* pos = nullptr;  // [n][3]
     float* wts = nullptr;   // [q][n]
     float* vtab = nullptr;  // [q][m2n]
@@ -281,9 +282,17 @@ struct corr_ctx {
     double* deconv = nullptr;
     double2* phase = nullptr;
     float2* fa = nullptr;          // fixed shape's spectrum [n][n][half]
-    float* buf0 = nullptr;         // [batch][qmax][m^3] floats (fine grid, reused)
-    float2* buf1 = nullptr;        // [batch][qmax][m^2][half]
-    float4* knots = nullptr;       // [batch][max(nA, nB)]
+    float* buf0 = nullptr;         // [batch][qmax][m][n][half] complex (after y; reused after inverse z)
+    float2* buf1 = nullptr;        // [batch][qmax][m^2][half] (after spread + x; reused after product)
+    int64_t nkmax = 1;             // max(nA, nB, 1)
+    int* cell = nullptr;           // [batch][nkmax] packed cell of each knot
+    float* kbw = nullptr;          // [batch][nkmax][3][w] window weights
+    int* rank = nullptr;           // [batch][nkmax] rank within its sort block and z-cell
+    int* counts = nullptr;         // [batch][m][blocks] counts, then offsets
+    int* bin_start = nullptr;      // [batch][m + 1]
+    int* scell = nullptr;          // [batch][nkmax] sorted by z-cell: packed cell
+    float* skbw = nullptr;         // [batch][nkmax][3][w]              window weights
+    float* swts = nullptr;         // [batch][nkmax][q]                 component weights
     double* quats = nullptr;       // [batch][4]
     float* pval = nullptr;         // [batch][blocks]
     int* pidx = nullptr;
@@ -301,7 +310,7 @@ struct corr_ctx {
 
 namespace {
 
-size_t buf0_floats(const corr_ctx* c) { return (size_t)c->qmax * c->g.m * c->g.m * c->g.m; }
+size_t buf0_floats(const corr_ctx* c) { return (size_t)2 * c->qmax * c->g.m * c->g.n * c->g.half; }
 size_t buf1_float2(const corr_ctx* c) { return (size_t)c->qmax * c->g.m * c->g.m * c->g.half; }
 
 void upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
@@ -359,6 +368,19 @@ void upload_shape(corr_ctx* c, Shape& s, const corr_ball* balls, double dk) {
         }
         upload(s.pos, pos.data(), sizeof(double) * pos.size(), c->stream);
         upload(s.wts, w.data(), sizeof(float) * w.size(), c->stream);
+        // fixed-point scale: any spreading sum is bounded by sum_i max_c |w_ic|
+        // (window values are <= 1), so 2^61 / that bound cannot overflow int64
+        double bound = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            double mx = 0;
+            for (int q = 0; q < e.q; ++q) mx = std::max(mx, (double)std::fabs(w[(size_t)q * n + i]));
+            bound += mx;
+        }
+        int ex2 = 61;
+        if (bound > 0) ex2 = (int)std::floor(std::log2(std::ldexp(1.0, 61) / bound));
+        ex2 = std::min(ex2, 100);
+        if (ex2 < -100) fail(CORR_EUNSUPPORTED, "ball weights too large for the spreading sums");
+        s.fix_scale = (float)std::ldexp(1.0, ex2);
     }
     double* d_nodes = c->mem.alloc<double>(e.p);
     double* d_basis = c->mem.alloc<double>((size_t)e.p * e.q);
@@ -398,10 +420,17 @@ void stage(corr_ctx* c, int id, const char* what, L&& launch) {
 void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int S) {
     const Geom& g = c->g;
     const int q = s.ex.q;
-    stage(c, CORR_STAGE_ZERO, "zero", [&] { return corr::launch_zero(c->buf0, (size_t)S * q * g.m * g.m * g.m, c->stream); });
-    stage(c, CORR_STAGE_ROTATE, "rotate", [&] { return corr::launch_rotate(g, d_quats, S, s.pos, s.n, c->knots, c->stream); });
-    stage(c, CORR_STAGE_SPREAD, "spread", [&] { return corr::launch_spread(g, c->knots, S, s.n, s.wts, q, c->buf0, c->stream); });
-    stage(c, CORR_STAGE_FFT_X, "fft x", [&] { return corr::launch_fft_x(g, c->buf0, S * q, c->buf1, c->twm, c->stream); });
+    stage(c, CORR_STAGE_ROTATE, "rotate", [&] {
+        return corr::launch_rotate_bin(g, d_quats, S, s.pos, s.n, c->cell, c->kbw, c->rank, c->counts, c->stream);
+    });
+    stage(c, CORR_STAGE_BIN, "bin", [&] {
+        return corr::launch_bin_sort(g, S, s.n, q, c->cell, c->kbw, s.wts, c->rank, c->counts, c->bin_start, c->scell,
+                                     c->skbw, c->swts, c->stream);
+    });
+    stage(c, CORR_STAGE_SPREAD_FFT_X, "spread + fft x", [&] {
+        return corr::launch_spread_fftx(g, S, s.n, c->bin_start, c->scell, c->skbw, c->swts, q, s.fix_scale, c->buf1,
+                                        c->twm, c->stream);
+    });
     stage(c, CORR_STAGE_FFT_Y, "fft y", [&] {
         return corr::launch_fft_y(g, c->buf1, S * q, reinterpret_cast<float2*>(c->buf0), c->twm, c->stream);
     });
@@ -499,7 +528,6 @@ int corr_create(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t nB, 
         double tol = gr.tol == 0 ? 1e-6 : gr.tol;
         if (!std::isfinite(tol) || !(tol > 0) || tol >= 1) fail(CORR_EINVAL, "tol must be in (0, 1)");
         if (gr.flags & ~CORR_DETERMINISTIC) fail(CORR_EINVAL, "unknown flag bits 0x%x", gr.flags);
-        if (gr.flags & CORR_DETERMINISTIC) fail(CORR_EUNSUPPORTED, "CORR_DETERMINISTIC spreading is not available yet");
         if (gr.batch < 0 || gr.batch > 256) fail(CORR_EINVAL, "batch = %d; allowed 0..256", gr.batch);
 
         c = new corr_ctx();
@@ -528,8 +556,10 @@ int corr_create(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t nB, 
         c->qmax = std::max(c->A.ex.q, c->B.ex.q);
 
         // batch: rotations per pass, bounded by a 4 GiB workspace
+        c->nkmax = std::max<int64_t>(std::max(nA, nB), 1);
+        const size_t nblk = (size_t)corr::bin_blocks(c->nkmax);
         size_t per_slot = sizeof(float) * buf0_floats(c) + sizeof(float2) * buf1_float2(c) +
-                          sizeof(float4) * (size_t)std::max<int64_t>(std::max(nA, nB), 1);
+                          (size_t)c->nkmax * (12 + 24 * w + 4 * c->qmax) + sizeof(int) * ((size_t)g.m * nblk + g.m + 1);
         int batch = gr.batch;
         if (batch == 0) batch = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 30) / per_slot));
         c->batch = batch;
@@ -538,10 +568,7 @@ int corr_create(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t nB, 
         hip_check(hipGetDeviceProperties(&prop, c->device), "hipGetDeviceProperties");
         // largest dynamic LDS any stage asks for
         {
-            int cx = corr::fft_cols_for(g.m, g.m * g.m / 2);
-            int cy = corr::fft_cols_for(g.m, g.half);
-            size_t need = std::max(sizeof(float2) * 2 * (size_t)cx * (g.m + 1),
-                                   sizeof(float2) * ((size_t)2 * cy * g.m + (size_t)cy * g.n));
+            size_t need = corr::max_lds_bytes(g, c->qmax);
             if (need > prop.sharedMemPerBlock)
                 fail(CORR_EUNSUPPORTED, "grid n = %d needs %zu bytes of LDS per workgroup; device has %zu", g.n, need,
                      (size_t)prop.sharedMemPerBlock);
@@ -566,7 +593,14 @@ int corr_create(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t nB, 
         c->fa = c->mem.alloc<float2>((size_t)g.n * g.n * g.half);
         c->buf0 = c->mem.alloc<float>((size_t)batch * buf0_floats(c));
         c->buf1 = c->mem.alloc<float2>((size_t)batch * buf1_float2(c));
-        c->knots = c->mem.alloc<float4>((size_t)batch * std::max<int64_t>(std::max(nA, nB), 1));
+        c->cell = c->mem.alloc<int>((size_t)batch * c->nkmax);
+        c->kbw = c->mem.alloc<float>((size_t)batch * c->nkmax * 3 * w);
+        c->rank = c->mem.alloc<int>((size_t)batch * c->nkmax);
+        c->scell = c->mem.alloc<int>((size_t)batch * c->nkmax);
+        c->skbw = c->mem.alloc<float>((size_t)batch * c->nkmax * 3 * w);
+        c->swts = c->mem.alloc<float>((size_t)batch * c->nkmax * c->qmax);
+        c->counts = c->mem.alloc<int>((size_t)batch * g.m * nblk);
+        c->bin_start = c->mem.alloc<int>((size_t)batch * (g.m + 1));
         c->quats = c->mem.alloc<double>((size_t)4 * batch);
         c->pval = c->mem.alloc<float>((size_t)batch * corr::ifft_x_blocks(g));
         c->pidx = c->mem.alloc<int>((size_t)batch * corr::ifft_x_blocks(g));

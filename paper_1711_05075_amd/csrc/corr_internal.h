@@ -21,14 +21,6 @@ struct Geom {
     double inv_hf = 0.0;      // 1 / spreading-cell size
 };
 
-// Columns handled by one workgroup of a column-FFT kernel: n_len * cols = 4096.
-inline int fft_cols_for(int len, int max_cols) {
-    int c = 4096 / len;
-    if (c > max_cols) c = max_cols;
-    if (c < 1) c = 1;
-    return c;
-}
-
 // ---- table builders (FP64 on the device) ---------------------------------
 hipError_t launch_deconv_tables(const Geom& g, double box, const double origin[3],
                                 double* d_deconv /*[n]*/, double2* d_phase /*[3][n]*/,
@@ -37,16 +29,25 @@ hipError_t launch_ball_table(const Geom& g, double dk, const double* d_nodes, co
                              int p, int q, double rhi, float* d_vtab /*[q][m2n]*/, hipStream_t st);
 
 // ---- pipeline stages -----------------------------------------------------
-// a0: turn the knots of S rotations and place them on the spreading grid.
-hipError_t launch_rotate(const Geom& g, const double* d_quats, int S, const double* d_pos,
-                         int64_t nk, float4* d_knots, hipStream_t st);
-hipError_t launch_zero(float* p, size_t count, hipStream_t st);
-// a1: Kaiser-Bessel spreading of q weighted components per knot.
-hipError_t launch_spread(const Geom& g, const float4* d_knots, int S, int64_t nk,
-                         const float* d_wts, int q, float* d_fine, hipStream_t st);
-// a2: pruned forward FFT, x (real to half-complex), then y.
-hipError_t launch_fft_x(const Geom& g, const float* d_fine, int slabs, float2* d_out,
-                        const float2* d_twm, hipStream_t st);
+// a0, binned: rotate, place, window weights, and the per-block ranks and
+// counts of a stable counting sort of the knots by z-cell ...
+inline int bin_blocks(int64_t nk) { return (int)((nk + 255) / 256); }
+hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const double* d_pos, int64_t nk,
+                             int* d_cell, float* d_kbw, int* d_rank, int* d_counts, hipStream_t st);
+// ... then the scan of the counts and the scatter of every knot's record (cell,
+// window weights, q component weights) into sorted order.
+hipError_t launch_bin_sort(const Geom& g, int S, int64_t nk, int q, const int* d_cell, const float* d_kbw,
+                           const float* d_wts, const int* d_rank, int* d_counts, int* d_bin_start, int* d_scell,
+                           float* d_skbw, float* d_swts, hipStream_t st);
+// a1 + a2 (x): gather-spreading of the sorted knots fused with the x transform;
+// writes [S][q][z][y][mx] without a spreading grid in HBM.
+// fix_scale: power of two with fix_scale * sum_i max_c |wts[c][i]| <= 2^61.
+hipError_t launch_spread_fftx(const Geom& g, int S, int64_t nk, const int* d_bin_start, const int* d_scell,
+                              const float* d_skbw, const float* d_swts, int q, float fix_scale, float2* d_out,
+                              const float2* d_twm, hipStream_t st);
+// Largest dynamic LDS any stage asks for.
+size_t max_lds_bytes(const Geom& g, int qmax);
+// a2: pruned forward y pass.
 hipError_t launch_fft_y(const Geom& g, const float2* d_in, int slabs, float2* d_out,
                         const float2* d_twm, hipStream_t st);
 // a2 (z) + a3: z transform of every component, the radius-expansion sum with the

@@ -14,13 +14,17 @@
 //   a5  inverse FFT to the n^3 translation grid, with per-rotation peaks.
 //
 // Column FFTs run in LDS as Stockham autosort passes of radix 8, 4 and 2 (each
-// thread does one radix-R butterfly per pass in registers), over a batch of
-// columns so that every HBM access is a contiguous row segment.
+// thread does whole radix-R butterflies per pass in registers), over a batch of
+// columns so that every HBM access is a contiguous row segment.  Kernels are
+// templates on the spreading-grid size M (translation grid N = M/2), so every
+// index computation is a shift or mask.
 #include "corr_internal.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace corr {
 namespace {
@@ -77,63 +81,70 @@ __device__ __forceinline__ void dft8(float2* v) {
     v[7] = csub(e3, w3o);
 }
 
-// One Stockham pass of radix R over `cols` columns of length `len`; element
-// (i, c) of a column batch lives at buf[i * si + c * sc].  tw[j] = exp(-2 pi i j / len).
-template <int R, int SIGN>
-__device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, float2* __restrict__ dst,
-                                              int si, int sc, int len, int cols, int ns,
-                                              const float2* __restrict__ tw) {
-    const int nb = len / R;
-    const int tws = len / (ns * R);
-    for (int t = threadIdx.x; t < nb * cols; t += blockDim.x) {
-        const int c = t % cols, j = t / cols;
-        const int k = j % ns;
-        float2 v[R];
+// ---------------------------------------------------------------------------
+// Column FFT engine.  A workgroup transforms COLS columns of LEN points held in
+// LDS; element (i, c) lives at buf[i * SI + c * SC] ("LINES" layout: each
+// column contiguous with a padded stride, otherwise columns interleaved).  The
+// transform is a sequence of Stockham autosort passes of radix 8 (then 4 or 2):
+// every thread does whole butterflies in registers, reading its inputs from one
+// buffer and writing its outputs to the other.  All sizes are compile-time
+// powers of two.  tw[j] = exp(-2 pi i j / LEN) is an LDS table.
+// ---------------------------------------------------------------------------
+template <int LEN, int NS, int SIGN, int COLS, int SI, int SC>
+__device__ __forceinline__ float2* fft_passes(float2* a, float2* b, const float2* tw) {
+    if constexpr (NS >= LEN) {
+        return a;
+    } else {
+        constexpr int REM = LEN / NS;
+        constexpr int R = REM >= 8 ? 8 : REM;
+        constexpr int NB = LEN / R;
+        constexpr int TWS = LEN / (NS * R);
+        constexpr int WORK = NB * COLS;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = src[(j + r * nb) * si + c * sc];
-        if (k) {
+        for (int t0 = 0; t0 < WORK; t0 += kThreads) {
+            const int t = t0 + (int)threadIdx.x;
+            if (WORK % kThreads == 0 || t < WORK) {
+                const int c = t % COLS, j = t / COLS;
+                const int k = j % NS;
+                float2 v[R];
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                float2 w = tw[r * k * tws];
-                if (SIGN > 0) w.y = -w.y;
-                v[r] = cmul(v[r], w);
+                for (int r = 0; r < R; ++r) v[r] = a[(j + r * NB) * SI + c * SC];
+                if constexpr (NS > 1) {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) {
+                        float2 w = tw[r * k * TWS];
+                        if constexpr (SIGN > 0) w.y = -w.y;
+                        v[r] = cmul(v[r], w);
+                    }
+                }
+                if constexpr (R == 8) dft8<SIGN>(v);
+                else if constexpr (R == 4) dft4<SIGN>(v[0], v[1], v[2], v[3]);
+                else dft2<SIGN>(v);
+                const int o = (j / NS) * NS * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) b[(o + r * NS) * SI + c * SC] = v[r];
             }
         }
-        if (R == 8) dft8<SIGN>(v);
-        else if (R == 4) dft4<SIGN>(v[0], v[1], v[2], v[3]);
-        else dft2<SIGN>(v);
-        const int o = (j / ns) * ns * R + k;
-#pragma unroll
-        for (int r = 0; r < R; ++r) dst[(o + r * ns) * si + c * sc] = v[r];
+        __syncthreads();
+        return fft_passes<LEN, NS * R, SIGN, COLS, SI, SC>(b, a, tw);
     }
 }
 
-// Unnormalised DFT of every column (sum_i x_i exp(SIGN 2 pi i i s / len)) with
-// a and b as ping-pong buffers; returns the buffer that holds the result.
-// Must be entered by the whole workgroup after the input is visible in `a`.
-template <int SIGN>
-__device__ float2* fft_cols(float2* a, float2* b, int si, int sc, int len, int cols,
-                            const float2* __restrict__ tw) {
-    int ns = 1;
-    while (ns < len) {
-        const int rem = len / ns;
-        if (rem >= 8) {
-            stockham_pass<8, SIGN>(a, b, si, sc, len, cols, ns, tw);
-            ns *= 8;
-        } else if (rem == 4) {
-            stockham_pass<4, SIGN>(a, b, si, sc, len, cols, ns, tw);
-            ns *= 4;
-        } else {
-            stockham_pass<2, SIGN>(a, b, si, sc, len, cols, ns, tw);
-            ns *= 2;
-        }
-        __syncthreads();
-        float2* t = a;
-        a = b;
-        b = t;
-    }
-    return a;
+// Unnormalised DFT sum_i x_i exp(SIGN 2 pi i i s / LEN) of every column; a and
+// b are ping-pong buffers and the returned pointer holds the result.  Entered by
+// the whole workgroup once the input in `a` and the table are visible.
+template <int LEN, int SIGN, int COLS, bool LINES>
+__device__ __forceinline__ float2* fft_cols(float2* a, float2* b, const float2* tw) {
+    return fft_passes<LEN, 1, SIGN, COLS, (LINES ? 1 : COLS), (LINES ? LEN + 1 : 1)>(a, b, tw);
 }
+
+template <int LEN>
+__device__ __forceinline__ void load_table(float2* dst, const float2* __restrict__ src) {
+    for (int t = threadIdx.x; t < LEN; t += kThreads) dst[t] = src[t];
+}
+
+template <int A, int B>
+constexpr int cmin() { return A < B ? A : B; }
 
 __device__ __forceinline__ int signed_mode(int i, int n) { return i < n / 2 ? i : i - n; }
 
@@ -218,269 +229,473 @@ __global__ void k_ball_table(int m2n, double dk, const double* __restrict__ node
 }
 
 // ---------------------------------------------------------------------------
-// a0: rotate + place
+// a0 (binned form): rotate + place + window weights, and a stable counting sort
+// of the knots by z-cell, so that a spreading tile finds the knots that reach
+// it as one or two contiguous ranges.
 // ---------------------------------------------------------------------------
+constexpr int kBinBlock = 256;
 
-// Knot record: fractional offsets within the cell (x, y, z) and the cell index
-// packed as cx | cy << 10 | cz << 20 (m <= 512).  The position is formed in
-// FP64 so that the fraction keeps full float precision.
-__global__ void k_rotate(const double* __restrict__ quats, const double* __restrict__ pos, int64_t nk,
-                         double inv_hf, int m, float4* __restrict__ knots) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int s = blockIdx.y;
-    if (j >= nk) return;
-    const double* q = quats + 4 * s;
-    double nn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    double w = q[0] / nn, x = q[1] / nn, y = q[2] / nn, z = q[3] / nn;
-    double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z),     2 * (x * z + w * y),
-                   2 * (x * y + w * z),     1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
-                   2 * (x * z - w * y),     2 * (y * z + w * x),     1 - 2 * (x * x + y * y)};
-    double px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
-    double u[3] = {(R[0] * px + R[1] * py + R[2] * pz) * inv_hf, (R[3] * px + R[4] * py + R[5] * pz) * inv_hf,
-                   (R[6] * px + R[7] * py + R[8] * pz) * inv_hf};
-    float f[3];
-    int c[3];
-    for (int d = 0; d < 3; ++d) {
-        double fl = floor(u[d]);
-        f[d] = (float)(u[d] - fl);
-        long long ci = (long long)fl % m;
-        if (ci < 0) ci += m;
-        c[d] = (int)ci;
-        if (f[d] >= 1.0f) {  // rounding up to 1 moves to the next cell
-            f[d] = 0.0f;
-            c[d] = (c[d] + 1) % m;
-        }
-    }
-    knots[(int64_t)s * nk + j] = make_float4(f[0], f[1], f[2], __int_as_float(c[0] | (c[1] << 10) | (c[2] << 20)));
-}
-
-__global__ void k_zero(float4* __restrict__ p, size_t n4) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n4; i += stride) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-}
-
-// ---------------------------------------------------------------------------
-// a1: spreading (one workgroup of 64 lanes per knot; lanes own (dy, dz) rows)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_spread(const float4* __restrict__ knots, int64_t nk,
-                                               const float* __restrict__ wts, int q, int m, int w,
-                                               float beta, float inv_i0beta, float* __restrict__ fine) {
-    int64_t j = blockIdx.x;
-    int s = blockIdx.y;
-    float4 kn = knots[(int64_t)s * nk + j];
-    int packed = __float_as_int(kn.w);
-    int cx = packed & 1023, cy = (packed >> 10) & 1023, cz = (packed >> 20) & 1023;
-    const float tw = 2.0f / (float)w;
-    const int lo = w / 2 - 1;
-    float wx[16];
-    for (int d = 0; d < w; ++d) wx[d] = kb_window(kn.x - (float)(d - lo), tw, beta, inv_i0beta);
-    const size_t m3 = (size_t)m * m * m;
-    for (int t = threadIdx.x; t < w * w; t += blockDim.x) {
-        int dy = t % w, dz = t / w;
-        float wyz = kb_window(kn.y - (float)(dy - lo), tw, beta, inv_i0beta) *
-                    kb_window(kn.z - (float)(dz - lo), tw, beta, inv_i0beta);
-        int yy = (cy + dy - lo + m) & (m - 1);
-        int zz = (cz + dz - lo + m) & (m - 1);
-        for (int c = 0; c < q; ++c) {
-            float wq = wts[(size_t)c * nk + j] * wyz;
-            float* row = fine + ((size_t)s * q + c) * m3 + ((size_t)zz * m + yy) * m;
-            for (int dx = 0; dx < w; ++dx) {
-                int xx = (cx + dx - lo + m) & (m - 1);
-                atomicAdd(row + xx, wq * wx[dx]);
+__global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restrict__ quats,
+                                                          const double* __restrict__ pos, int64_t nk, double inv_hf,
+                                                          int m, int w, float beta, float inv_i0beta,
+                                                          int* __restrict__ cell, float* __restrict__ kbw,
+                                                          int* __restrict__ rank, int* __restrict__ counts, int nblk) {
+    __shared__ int zc[kBinBlock];
+    __shared__ int hist[512];
+    const int64_t j = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
+    const int s = blockIdx.y;
+    for (int b = threadIdx.x; b < m; b += kBinBlock) hist[b] = 0;
+    int cz = -1;
+    if (j < nk) {
+        const double* q = quats + 4 * s;
+        double nn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        double qw = q[0] / nn, x = q[1] / nn, y = q[2] / nn, z = q[3] / nn;
+        double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - qw * z),    2 * (x * z + qw * y),
+                       2 * (x * y + qw * z),    1 - 2 * (x * x + z * z), 2 * (y * z - qw * x),
+                       2 * (x * z - qw * y),    2 * (y * z + qw * x),    1 - 2 * (x * x + y * y)};
+        double px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
+        double u[3] = {(R[0] * px + R[1] * py + R[2] * pz) * inv_hf, (R[3] * px + R[4] * py + R[5] * pz) * inv_hf,
+                       (R[6] * px + R[7] * py + R[8] * pz) * inv_hf};
+        const float tw = 2.0f / (float)w;
+        const int lo = w / 2 - 1;
+        int c[3];
+        float* kw = kbw + ((int64_t)s * nk + j) * 3 * w;
+        for (int d = 0; d < 3; ++d) {
+            double fl = floor(u[d]);
+            float f = (float)(u[d] - fl);
+            long long ci = (long long)fl % m;
+            if (ci < 0) ci += m;
+            c[d] = (int)ci;
+            if (f >= 1.0f) {
+                f = 0.0f;
+                c[d] = (c[d] + 1) % m;
             }
+            for (int i = 0; i < w; ++i) kw[d * w + i] = kb_window(f - (float)(i - lo), tw, beta, inv_i0beta);
         }
+        cell[(int64_t)s * nk + j] = c[0] | (c[1] << 10) | (c[2] << 20);
+        cz = c[2];
     }
-}
-
-// ---------------------------------------------------------------------------
-// a2: x pass.  Two real lines are packed into one complex column, transformed
-// together and separated: X1 = (Z_m + conj Z_{M-m}) / 2, X2 = (Z_m - conj Z_{M-m}) / 2i.
-// LDS layout [column][i] with a padded column stride.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_fft_x(const float* __restrict__ fine, float2* __restrict__ out,
-                                                    int m, int half, int cols, const float2* __restrict__ tw) {
-    extern __shared__ float2 lds[];
-    const int sc = m + 1;
-    float2* a = lds;
-    float2* b = lds + cols * sc;
-    const size_t slab = blockIdx.y;
-    const size_t line0 = (size_t)blockIdx.x * 2 * cols;
-    const float* src = fine + slab * (size_t)m * m * m + line0 * m;
-    const int nx4 = m / 4;
-    for (int t = threadIdx.x; t < cols * nx4; t += blockDim.x) {
-        int c = t / nx4, x4 = t % nx4;
-        float4 r0 = *reinterpret_cast<const float4*>(src + (size_t)(2 * c) * m + 4 * x4);
-        float4 r1 = *reinterpret_cast<const float4*>(src + (size_t)(2 * c + 1) * m + 4 * x4);
-        float2* d = a + c * sc + 4 * x4;
-        d[0] = make_float2(r0.x, r1.x);
-        d[1] = make_float2(r0.y, r1.y);
-        d[2] = make_float2(r0.z, r1.z);
-        d[3] = make_float2(r0.w, r1.w);
+    zc[threadIdx.x] = cz;
+    __syncthreads();
+    if (j < nk) {
+        int r = 0;
+        for (int k = 0; k < (int)threadIdx.x; ++k) r += (zc[k] == cz);
+        rank[(int64_t)s * nk + j] = r;
+        atomicAdd(&hist[cz], 1);
     }
     __syncthreads();
-    float2* res = fft_cols<-1>(a, b, 1, sc, m, cols, tw);
-    float2* dst = out + slab * (size_t)m * m * half + line0 * half;
-    for (int t = threadIdx.x; t < 2 * cols * half; t += blockDim.x) {
-        int l = t / half, mm = t % half;
-        int c = l >> 1;
-        float2 z1 = res[c * sc + mm];
-        float2 z2 = res[c * sc + ((m - mm) & (m - 1))];
-        float2 o = (l & 1) ? make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x))
-                           : make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
-        dst[(size_t)l * half + mm] = o;
+    for (int b = threadIdx.x; b < m; b += kBinBlock) counts[((size_t)s * m + b) * nblk + blockIdx.x] = hist[b];
+}
+
+// Exclusive scan of counts[s][bin][block] (bin-major) into offsets, one
+// workgroup per rotation; bin_start[s][bin] = first sorted position of a bin.
+__global__ __launch_bounds__(1024) void k_bin_scan(int* __restrict__ counts, int m, int nblk, int64_t nk,
+                                                   int* __restrict__ bin_start) {
+    __shared__ int part[1024];
+    const int s = blockIdx.x;
+    int* c = counts + (size_t)s * m * nblk;
+    const int total = m * nblk;
+    const int per = (total + 1023) / 1024;
+    const int b0 = threadIdx.x * per, b1 = min(total, b0 + per);
+    int sum = 0;
+    for (int i = b0; i < b1; ++i) sum += c[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            int v = part[t];
+            part[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int run = part[threadIdx.x];
+    for (int i = b0; i < b1; ++i) {
+        int v = c[i];
+        c[i] = run;
+        run += v;
+    }
+    __syncthreads();
+    int* bs = bin_start + (size_t)s * (m + 1);
+    for (int b = threadIdx.x; b < m; b += 1024) bs[b] = c[b * nblk];
+    if (threadIdx.x == 0) bs[m] = (int)nk;
+}
+
+// Scatter each knot's record into sorted position: its packed cell, its window
+// weights and its q component weights, so that a spreading tile reads the knots
+// of its z-cells as contiguous memory.
+__global__ __launch_bounds__(kBinBlock) void k_bin_scatter(const int* __restrict__ cell, const float* __restrict__ kbw,
+                                                           const float* __restrict__ wts, const int* __restrict__ rank,
+                                                           const int* __restrict__ offsets, int64_t nk, int m, int w,
+                                                           int q, int nblk, int* __restrict__ scell,
+                                                           float* __restrict__ skbw, float* __restrict__ swts) {
+    const int64_t j = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
+    const int s = blockIdx.y;
+    if (j >= nk) return;
+    const int packed = cell[(int64_t)s * nk + j];
+    const int cz = (packed >> 20) & 1023;
+    const int64_t p = (int64_t)s * nk + offsets[((size_t)s * m + cz) * nblk + blockIdx.x] + rank[(int64_t)s * nk + j];
+    scell[p] = packed;
+    const float* src = kbw + ((int64_t)s * nk + j) * 3 * w;
+    float* dst = skbw + p * 3 * w;
+    for (int i = 0; i < 3 * w; ++i) dst[i] = src[i];
+    for (int c = 0; c < q; ++c) swts[p * q + c] = wts[(size_t)c * nk + j];
+}
+
+// ---------------------------------------------------------------------------
+// a1 + a2 (x): spreading fused with the x transform.  A workgroup owns TY full
+// x-lines (z row z0, y rows y0 .. y0+TY-1).  For each pair of radius components
+// (c, c+1) it accumulates both into one complex line (c in the real part, c+1
+// in the imaginary part), transforms the lines along x in LDS and separates the
+// two half spectra:
+//   X_c = (Z_m + conj Z_{M-m}) / 2,  X_{c+1} = (Z_m - conj Z_{M-m}) / 2i.
+// The knots that reach z row z0 are those of z-cells z0-w/2 .. z0+w/2-1: one or
+// two contiguous ranges of the sorted order.  Those whose window also reaches
+// the tile's y rows are compacted in order (wave ballots + a block scan) and
+// staged in LDS with their window and component weights.  Each wave applies one
+// staged knot at a time, a lane per window point, adding into 64-bit fixed-point
+// sums with LDS integer atomics: integer addition is exact and associative, so
+// the result does not depend on scheduling.  The fixed-point scale is a power of
+// two chosen per shape so that no sum can overflow.
+// ---------------------------------------------------------------------------
+struct SpreadStage {
+    int* cell;    // [cap] packed cell
+    float* wx;    // [cap][w]
+    float* wy;    // [cap][w]
+    float* wz;    // [cap] weight of this z row
+    float* wq;    // [cap][q] component weights
+};
+
+// Stage the filtered knots with filtered rank in [first, first + cap); returns
+// the total number of filtered knots.  sc_, kb_, wq_ point at this rotation's
+// sorted records.
+__device__ int stage_knots(const int* __restrict__ sc_, const float* __restrict__ kb_, const float* __restrict__ wq_,
+                           int q, int m, int w, int ty, int y0, int z0, int r0a, int n0, int r1a, int ncand, int first,
+                           int cap, SpreadStage st, int* wave_tot) {
+    const int lo = w / 2 - 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int running = 0;
+    for (int base = 0; base < ncand; base += kThreads) {
+        const int ci = base + threadIdx.x;
+        int p = 0, packed = 0;
+        bool keep = false;
+        if (ci < ncand) {
+            p = ci < n0 ? r0a + ci : r1a + (ci - n0);
+            packed = sc_[p];
+            const int cy = (packed >> 10) & 1023;
+            const int ry = (cy - lo - y0 + 2 * m) & (m - 1);
+            keep = ry < ty || ry > m - w;
+        }
+        const unsigned long long mask = __ballot(keep);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_tot[wave] = __popcll(mask);
+        __syncthreads();
+        int off = running, total = 0;
+#pragma unroll
+        for (int v = 0; v < kThreads / 64; ++v) {
+            off += v < wave ? wave_tot[v] : 0;
+            total += wave_tot[v];
+        }
+        const int rk = off + before - first;
+        if (keep && rk >= 0 && rk < cap) {
+            st.cell[rk] = packed;
+            const float* kw = kb_ + (int64_t)p * 3 * w;
+            for (int d = 0; d < w; ++d) {
+                st.wx[rk * w + d] = kw[d];
+                st.wy[rk * w + d] = kw[w + d];
+            }
+            const int cz = (packed >> 20) & 1023;
+            st.wz[rk] = kw[2 * w + ((z0 - cz + lo + m) & (m - 1))];
+            for (int c = 0; c < q; ++c) st.wq[rk * q + c] = wq_[(int64_t)p * q + c];
+        }
+        running += total;
+        __syncthreads();
+    }
+    return running;
+}
+
+template <int M>
+struct SpreadShape {
+    static constexpr int TY = cmin<2048 / M, M>();
+    static constexpr int SC = M + 1;
+    static constexpr int NPTS = TY * M;
+    // fixed-point sums (16 B per point, reused as the FFT's second buffer), the
+    // padded FFT input, the twiddle table; the staged knots follow
+    static constexpr size_t FIXED = 16 * (size_t)NPTS + 8 * (size_t)TY * SC + 8 * (size_t)M;
+};
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void k_spread_fftx(const int* __restrict__ bin_start,
+                                                          const int* __restrict__ scell, const float* __restrict__ skbw,
+                                                          const float* __restrict__ swts, int64_t nk, int q, int w,
+                                                          int cap, float fix_scale, float fix_inv,
+                                                          float2* __restrict__ out, const float2* __restrict__ twm) {
+    constexpr int H = M / 4;  // half of the n = M/2 kept modes along x
+    constexpr int TY = SpreadShape<M>::TY, SC = SpreadShape<M>::SC, NPTS = SpreadShape<M>::NPTS;
+    extern __shared__ float2 lds[];
+    __shared__ int wave_tot[kThreads / 64];
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds);
+    float2* b = lds;
+    float2* a = lds + 2 * NPTS;
+    float2* twl = a + TY * SC;
+    SpreadStage st;
+    st.cell = reinterpret_cast<int*>(twl + M);
+    st.wx = reinterpret_cast<float*>(st.cell + cap);
+    st.wy = st.wx + cap * w;
+    st.wz = st.wy + cap * w;
+    st.wq = st.wz + cap;
+    const int y0 = blockIdx.x * TY, z0 = blockIdx.y, s = blockIdx.z;
+    const int lo = w / 2 - 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int dmul = (65536 + w - 1) / w;  // t / w for t < w*w by a multiply
+    load_table<M>(twl, twm);
+    const int* bs = bin_start + (size_t)s * (M + 1);
+    const int zlo = z0 - w / 2, zhi = z0 + lo;  // inclusive range of z-cells
+    int r0a = 0, r0b = 0, r1a = 0, r1b = 0;    // an empty shape has no bins to read
+    if (nk == 0) {
+    } else if (zlo < 0) {
+        r0a = bs[zlo + M]; r0b = bs[M]; r1a = bs[0]; r1b = bs[zhi + 1];
+    } else if (zhi >= M) {
+        r0a = bs[zlo]; r0b = bs[M]; r1a = bs[0]; r1b = bs[zhi - M + 1];
+    } else {
+        r0a = bs[zlo]; r0b = bs[zhi + 1];
+    }
+    const int n0 = r0b - r0a, ncand = n0 + (r1b - r1a);
+    const int* sc_ = scell + (int64_t)s * nk;
+    const float* kb_ = skbw + (int64_t)s * nk * 3 * w;
+    const float* wq_ = swts + (int64_t)s * nk * q;
+    const int nfilt = ncand ? stage_knots(sc_, kb_, wq_, q, M, w, TY, y0, z0, r0a, n0, r1a, ncand, 0, cap, st, wave_tot)
+                            : 0;
+    const int rounds = (nfilt + cap - 1) / cap;
+    for (int cp = 0; cp < q; cp += 2) {
+        for (int t = threadIdx.x; t < 2 * NPTS; t += kThreads) acc[t] = 0ull;
+        __syncthreads();
+        for (int r = 0; r < rounds; ++r) {
+            if (rounds > 1 && (r > 0 || cp > 0))
+                stage_knots(sc_, kb_, wq_, q, M, w, TY, y0, z0, r0a, n0, r1a, ncand, r * cap, cap, st, wave_tot);
+            const int nst = min(cap, nfilt - r * cap);
+            for (int i = wave; i < nst; i += kThreads / 64) {
+                const int packed = st.cell[i];
+                const int cx = packed & 1023, cy = (packed >> 10) & 1023;
+                const int ry = (cy - lo - y0 + 2 * M) & (M - 1);
+                const float wz = st.wz[i] * fix_scale;
+                const float c0 = st.wq[i * q + cp] * wz;
+                const float c1 = (cp + 1 < q) ? st.wq[i * q + cp + 1] * wz : 0.0f;
+                for (int t = lane; t < w * w; t += 64) {
+                    const int ddy = (t * dmul) >> 16, ddx = t - ddy * w;
+                    const int l = (ry + ddy) & (M - 1);
+                    if (l < TY) {
+                        const int x = (cx - lo + ddx + M) & (M - 1);
+                        const float v = st.wy[i * w + ddy] * st.wx[i * w + ddx];
+                        unsigned long long* e = acc + 2 * (l * M + x);
+                        atomicAdd(e, (unsigned long long)__float2ll_rn(c0 * v));
+                        atomicAdd(e + 1, (unsigned long long)__float2ll_rn(c1 * v));
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        for (int t = threadIdx.x; t < NPTS; t += kThreads) {
+            const int l = t / M, x = t % M;
+            a[l * SC + x] = make_float2((float)(long long)acc[2 * t] * fix_inv, (float)(long long)acc[2 * t + 1] * fix_inv);
+        }
+        __syncthreads();
+        float2* res = fft_cols<M, -1, TY, true>(a, b, twl);
+        constexpr int PER = TY * H;
+        for (int t = threadIdx.x; t < 2 * PER; t += kThreads) {
+            const int comp = t >= PER;
+            const int r = t - comp * PER;
+            const int l = r / H, mm = r % H;
+            if (cp + comp >= q) continue;
+            const float2 z1 = res[l * SC + mm];
+            const float2 z2 = res[l * SC + ((M - mm) & (M - 1))];
+            const float2 o = comp ? make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x))
+                                  : make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
+            out[((((size_t)s * q + cp + comp) * M + z0) * M + y0 + l) * H + mm] = o;
+        }
+        __syncthreads();
     }
 }
 
 // Index of kept output mode o (FFT order of an n-point axis) in an m-point FFT;
 // -1 for the Nyquist slot.
-__device__ __forceinline__ int kept_source(int o, int n, int m) {
-    if (o == n / 2) return -1;
-    int mo = o < n / 2 ? o : o - n;
-    return (mo + m) & (m - 1);
+template <int N, int M>
+__device__ __forceinline__ int kept_source(int o) {
+    if (o == N / 2) return -1;
+    const int mo = o < N / 2 ? o : o - N;
+    return (mo + M) & (M - 1);
 }
 
-// a2: y pass over [slab][z][y][mx] -> [slab][z][my][mx], m points pruned to n.
+template <int M>
+struct ColShape {
+    static constexpr int N = M / 2, H = N / 2;
+    static constexpr int COLS = cmin<H, 4096 / M>();          // forward y / z passes
+    static constexpr int ICOLS = cmin<H, 4096 / N>();         // inverse y pass
+    static constexpr int XCOLS = cmin<N * N / 2, 4096 / N>(); // inverse x pass (line pairs)
+};
+
+// a2: y pass over [slab][z][y][mx] -> [slab][z][my][mx], M points pruned to N.
+template <int M>
 __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ in, float2* __restrict__ out,
-                                                    int m, int n, int half, int cols,
-                                                    const float2* __restrict__ tw) {
+                                                    const float2* __restrict__ twm) {
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS;
     extern __shared__ float2 lds[];
     float2* a = lds;
-    float2* b = lds + m * cols;
-    const int c0 = blockIdx.x * cols;
-    const size_t plane = (size_t)blockIdx.z * m + blockIdx.y;  // slab * m + z
-    const float2* src = in + plane * m * half + c0;
-    for (int t = threadIdx.x; t < m * cols; t += blockDim.x) {
-        int i = t / cols, c = t % cols;
-        a[i * cols + c] = src[(size_t)i * half + c];
-    }
+    float2* b = lds + M * COLS;
+    float2* twl = b + M * COLS;
+    load_table<M>(twl, twm);
+    const int c0 = blockIdx.x * COLS;
+    const size_t plane = (size_t)blockIdx.z * M + blockIdx.y;  // slab * M + z
+    const float2* src = in + plane * M * H + c0;
+    for (int t = threadIdx.x; t < M * COLS; t += kThreads) a[t] = src[(size_t)(t / COLS) * H + t % COLS];
     __syncthreads();
-    float2* res = fft_cols<-1>(a, b, cols, 1, m, cols, tw);
-    float2* dst = out + plane * n * half + c0;
-    for (int t = threadIdx.x; t < n * cols; t += blockDim.x) {
-        int o = t / cols, c = t % cols;
-        int src_i = kept_source(o, n, m);
-        dst[(size_t)o * half + c] = src_i < 0 ? make_float2(0.f, 0.f) : res[src_i * cols + c];
+    float2* res = fft_cols<M, -1, COLS, false>(a, b, twl);
+    float2* dst = out + plane * N * H + c0;
+    for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
+        const int o = t / COLS, c = t % COLS;
+        const int si = kept_source<N, M>(o);
+        dst[(size_t)o * H + c] = si < 0 ? make_float2(0.f, 0.f) : res[si * COLS + c];
     }
 }
 
 // Shared part of the z pass: transform each component's z-columns for one my
-// row and accumulate sum_c vtab[c][|m|^2] * G_c into acc[mz][col].
-__device__ void z_accumulate(const float2* __restrict__ in, int s, int q, int m, int n, int half, int cols,
-                             int iy, int c0, const float* __restrict__ vtab, int m2n, float2* a, float2* b,
-                             float2* acc, const float2* __restrict__ twm) {
-    const int my = signed_mode(iy, n);
-    for (int t = threadIdx.x; t < n * cols; t += blockDim.x) acc[t] = make_float2(0.f, 0.f);
+// row and accumulate sum_c vtab[c][|m|^2] * G_c into per-thread registers
+// (thread t holds entries t + k*kThreads of the [mz][col] block).
+template <int M>
+struct ZAcc {
+    static constexpr int N = M / 2, COLS = ColShape<M>::COLS;
+    static constexpr int PER = (N * COLS + kThreads - 1) / kThreads;
+};
+
+template <int M>
+__device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int s, int q, int iy, int c0,
+                                             const float* __restrict__ vtab, int m2n, float2* a, float2* b,
+                                             const float2* twl, float2 (&acc)[ZAcc<M>::PER]) {
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
+    const int my = iy < N / 2 ? iy : iy - N;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) acc[k] = make_float2(0.f, 0.f);
     for (int c = 0; c < q; ++c) {
-        const float2* src = in + (((size_t)s * q + c) * m) * n * half + (size_t)iy * half + c0;
-        for (int t = threadIdx.x; t < m * cols; t += blockDim.x) {
-            int i = t / cols, cc = t % cols;
-            a[i * cols + cc] = src[(size_t)i * n * half + cc];
-        }
+        const float2* src = in + (((size_t)s * q + c) * M) * N * H + (size_t)iy * H + c0;
+        for (int t = threadIdx.x; t < M * COLS; t += kThreads) a[t] = src[(size_t)(t / COLS) * N * H + t % COLS];
         __syncthreads();
-        float2* res = fft_cols<-1>(a, b, cols, 1, m, cols, twm);
+        const float2* res = fft_cols<M, -1, COLS, false>(a, b, twl);
         const float* vt = vtab + (size_t)c * m2n;
-        for (int t = threadIdx.x; t < n * cols; t += blockDim.x) {
-            int o = t / cols, cc = t % cols;
-            int src_i = kept_source(o, n, m);
-            if (src_i < 0) continue;
-            int mz = signed_mode(o, n), mx = c0 + cc;
-            float v = vt[mx * mx + my * my + mz * mz];
-            float2 g = res[src_i * cols + cc];
-            acc[t].x += v * g.x;
-            acc[t].y += v * g.y;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int t = threadIdx.x + k * kThreads;
+            if (t < N * COLS) {
+                const int o = t / COLS, cc = t % COLS;
+                const int si = kept_source<N, M>(o);
+                if (si >= 0) {
+                    const int mz = o < N / 2 ? o : o - N, mx = c0 + cc;
+                    const float v = vt[mx * mx + my * my + mz * mz];
+                    const float2 g = res[si * COLS + cc];
+                    acc[k].x += v * g.x;
+                    acc[k].y += v * g.y;
+                }
+            }
         }
         __syncthreads();
     }
 }
 
 // a2 (z) + a3 for the fixed shape or a single spectrum: F = D(m) * acc.
+template <int M>
 __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __restrict__ in, int q,
                                                              const float* __restrict__ vtab, int m2n,
                                                              const double* __restrict__ deconv,
-                                                             float2* __restrict__ spec, int m, int n, int half,
-                                                             int cols, const float2* __restrict__ twm) {
+                                                             float2* __restrict__ spec, const float2* __restrict__ twm) {
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
     extern __shared__ float2 lds[];
     float2* a = lds;
-    float2* b = a + m * cols;
-    float2* acc = b + m * cols;
-    const int c0 = blockIdx.x * cols, iy = blockIdx.y, s = blockIdx.z;
-    float2* dst = spec + (size_t)s * n * n * half + (size_t)iy * half + c0;
-    if (iy == n / 2) {
-        for (int t = threadIdx.x; t < n * cols; t += blockDim.x)
-            dst[(size_t)(t / cols) * n * half + t % cols] = make_float2(0.f, 0.f);
+    float2* b = a + M * COLS;
+    float2* twl = b + M * COLS;
+    const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
+    float2* dst = spec + (size_t)s * N * N * H + (size_t)iy * H + c0;
+    if (iy == N / 2) {
+        for (int t = threadIdx.x; t < N * COLS; t += kThreads)
+            dst[(size_t)(t / COLS) * N * H + t % COLS] = make_float2(0.f, 0.f);
         return;
     }
-    z_accumulate(in, s, q, m, n, half, cols, iy, c0, vtab, m2n, a, b, acc, twm);
-    for (int t = threadIdx.x; t < n * cols; t += blockDim.x) {
-        int o = t / cols, cc = t % cols;
-        float d = (float)(deconv[c0 + cc] * deconv[iy] * deconv[o]);
-        dst[(size_t)o * n * half + cc] = make_float2(acc[t].x * d, acc[t].y * d);
+    load_table<M>(twl, twm);
+    float2 acc[PER];
+    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, b, twl, acc);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * kThreads;
+        if (t < N * COLS) {
+            const int o = t / COLS, cc = t % COLS;
+            const float d = (float)(deconv[c0 + cc] * deconv[iy] * deconv[o]);
+            dst[(size_t)o * N * H + cc] = make_float2(acc[k].x * d, acc[k].y * d);
+        }
     }
 }
 
 // a2 (z) + a3 + a4 + inverse z for the rotated shape:
-//   S = F_A * conj(acc) * prod_d D(m_d) exp(i k_d o_d) / L   (FP64 factor),
+//   S = F_A * conj(acc) * prod_d D(m_d) exp(i k_d o_d) / L   (factor in FP64),
 // then the unnormalised inverse transform along z.
+template <int M>
 __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __restrict__ in, int q,
                                                             const float* __restrict__ vtab, int m2n,
                                                             const double2* __restrict__ phase,
                                                             const float2* __restrict__ fa, float2* __restrict__ out,
-                                                            int m, int n, int half, int cols,
                                                             const float2* __restrict__ twm,
                                                             const float2* __restrict__ twn) {
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
     extern __shared__ float2 lds[];
     float2* a = lds;
-    float2* b = a + m * cols;
-    float2* acc = b + m * cols;
-    const int c0 = blockIdx.x * cols, iy = blockIdx.y, s = blockIdx.z;
-    float2* dst = out + (size_t)s * n * n * half + (size_t)iy * half + c0;
-    if (iy == n / 2) {
-        for (int t = threadIdx.x; t < n * cols; t += blockDim.x)
-            dst[(size_t)(t / cols) * n * half + t % cols] = make_float2(0.f, 0.f);
+    float2* b = a + M * COLS;
+    float2* twl = b + M * COLS;
+    float2* twnl = twl + M;
+    const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
+    float2* dst = out + (size_t)s * N * N * H + (size_t)iy * H + c0;
+    if (iy == N / 2) {
+        for (int t = threadIdx.x; t < N * COLS; t += kThreads)
+            dst[(size_t)(t / COLS) * N * H + t % COLS] = make_float2(0.f, 0.f);
         return;
     }
-    z_accumulate(in, s, q, m, n, half, cols, iy, c0, vtab, m2n, a, b, acc, twm);
-    const double2 py = phase[n + iy];
-    for (int t = threadIdx.x; t < n * cols; t += blockDim.x) {
-        int o = t / cols, cc = t % cols;
-        double2 px = phase[c0 + cc], pz = phase[2 * n + o];
-        // f = px * py * pz in FP64
-        double fr = px.x * py.x - px.y * py.y, fi = px.x * py.y + px.y * py.x;
-        double gr = fr * pz.x - fi * pz.y, gi = fr * pz.y + fi * pz.x;
-        float2 fac = make_float2((float)gr, (float)gi);
-        float2 A = fa[((size_t)o * n + iy) * half + c0 + cc];
-        float2 cb = make_float2(acc[t].x, -acc[t].y);
-        a[o * cols + cc] = cmul(cmul(A, cb), fac);
+    load_table<M>(twl, twm);
+    load_table<N>(twnl, twn);
+    float2 acc[PER];
+    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, b, twl, acc);
+    const double2 py = phase[N + iy];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * kThreads;
+        if (t < N * COLS) {
+            const int o = t / COLS, cc = t % COLS;
+            const double2 px = phase[c0 + cc], pz = phase[2 * N + o];
+            const double fr = px.x * py.x - px.y * py.y, fi = px.x * py.y + px.y * py.x;
+            const double gr = fr * pz.x - fi * pz.y, gi = fr * pz.y + fi * pz.x;
+            const float2 A = fa[((size_t)o * N + iy) * H + c0 + cc];
+            a[o * COLS + cc] = cmul(cmul(A, make_float2(acc[k].x, -acc[k].y)), make_float2((float)gr, (float)gi));
+        }
     }
     __syncthreads();
-    float2* res = fft_cols<1>(a, b, cols, 1, n, cols, twn);
-    for (int t = threadIdx.x; t < n * cols; t += blockDim.x) {
-        int z = t / cols, cc = t % cols;
-        dst[(size_t)z * n * half + cc] = res[z * cols + cc];
-    }
+    const float2* res = fft_cols<N, 1, COLS, false>(a, b, twnl);
+    for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * N * H + t % COLS] = res[t];
 }
 
 // a5: inverse y over [s][z][my][mx] -> [s][z][y][mx].
+template <int M>
 __global__ __launch_bounds__(kThreads) void k_ifft_y(const float2* __restrict__ in, float2* __restrict__ out,
-                                                     int n, int half, int cols, const float2* __restrict__ twn) {
+                                                     const float2* __restrict__ twn) {
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ICOLS;
     extern __shared__ float2 lds[];
     float2* a = lds;
-    float2* b = lds + n * cols;
-    const int c0 = blockIdx.x * cols;
-    const size_t plane = (size_t)blockIdx.z * n + blockIdx.y;
-    const float2* src = in + plane * n * half + c0;
-    for (int t = threadIdx.x; t < n * cols; t += blockDim.x) {
-        int i = t / cols, c = t % cols;
-        a[i * cols + c] = src[(size_t)i * half + c];
-    }
+    float2* b = lds + N * COLS;
+    float2* twl = b + N * COLS;
+    load_table<N>(twl, twn);
+    const int c0 = blockIdx.x * COLS;
+    const size_t plane = (size_t)blockIdx.z * N + blockIdx.y;
+    const float2* src = in + plane * N * H + c0;
+    for (int t = threadIdx.x; t < N * COLS; t += kThreads) a[t] = src[(size_t)(t / COLS) * H + t % COLS];
     __syncthreads();
-    float2* res = fft_cols<1>(a, b, cols, 1, n, cols, twn);
-    float2* dst = out + plane * n * half + c0;
-    for (int t = threadIdx.x; t < n * cols; t += blockDim.x) {
-        int i = t / cols, c = t % cols;
-        dst[(size_t)i * half + c] = res[i * cols + c];
-    }
+    const float2* res = fft_cols<N, 1, COLS, false>(a, b, twl);
+    float2* dst = out + plane * N * H + c0;
+    for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * H + t % COLS] = res[t];
 }
 
 // a5: inverse x, half-complex to real.  Two lines X1, X2 share one complex
@@ -488,28 +703,31 @@ __global__ __launch_bounds__(kThreads) void k_ifft_y(const float2* __restrict__ 
 // (X[n-m] = conj X[m], Nyquist 0, imaginary part of X[0] dropped); the real and
 // imaginary parts of the result are the two score lines.  Each block also
 // reduces its scores to (max, lowest index of the max).
+template <int M>
 __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ in, float* __restrict__ scores,
-                                                     float* __restrict__ pval, int* __restrict__ pidx, int n,
-                                                     int half, int cols, const float2* __restrict__ twn) {
+                                                     float* __restrict__ pval, int* __restrict__ pidx,
+                                                     const float2* __restrict__ twn) {
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::XCOLS, SC = N + 1;
     extern __shared__ float2 lds[];
     __shared__ float red_v[kThreads];
     __shared__ int red_i[kThreads];
-    const int sc = n + 1;
     float2* a = lds;
-    float2* b = lds + cols * sc;
+    float2* b = lds + COLS * SC;
+    float2* twl = b + COLS * SC;
+    load_table<N>(twl, twn);
     const int s = blockIdx.y;
-    const size_t line0 = (size_t)blockIdx.x * 2 * cols;
-    const float2* src = in + (size_t)s * n * n * half + line0 * half;
-    for (int t = threadIdx.x; t < cols * n; t += blockDim.x) {
-        int c = t / n, mm = t % n;
+    const size_t line0 = (size_t)blockIdx.x * 2 * COLS;
+    const float2* src = in + (size_t)s * N * N * H + line0 * H;
+    for (int t = threadIdx.x; t < COLS * N; t += kThreads) {
+        const int c = t / N, mm = t % N;
         float2 z;
-        if (mm == half) {
+        if (mm == H) {
             z = make_float2(0.f, 0.f);
         } else {
-            bool lo = mm < half;
-            int mi = lo ? mm : n - mm;
-            float2 x1 = src[(size_t)(2 * c) * half + mi];
-            float2 x2 = src[(size_t)(2 * c + 1) * half + mi];
+            const bool lo = mm < H;
+            const int mi = lo ? mm : N - mm;
+            float2 x1 = src[(size_t)(2 * c) * H + mi];
+            float2 x2 = src[(size_t)(2 * c + 1) * H + mi];
             if (mi == 0) {
                 x1.y = 0.f;
                 x2.y = 0.f;
@@ -520,19 +738,19 @@ __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ 
             }
             z = make_float2(x1.x - x2.y, x1.y + x2.x);
         }
-        a[c * sc + mm] = z;
+        a[c * SC + mm] = z;
     }
     __syncthreads();
-    float2* res = fft_cols<1>(a, b, 1, sc, n, cols, twn);
+    const float2* res = fft_cols<N, 1, COLS, true>(a, b, twl);
     float best = -INFINITY;
     int besti = 0x7fffffff;
-    float* dst = scores ? scores + (size_t)s * n * n * n + line0 * n : nullptr;
-    for (int t = threadIdx.x; t < 2 * cols * n; t += blockDim.x) {
-        int l = t / n, x = t % n;
-        float2 zz = res[(l >> 1) * sc + x];
-        float v = (l & 1) ? zz.y : zz.x;
-        if (dst) dst[(size_t)l * n + x] = v;
-        int gi = (int)((line0 + l) * n + x);
+    float* dst = scores ? scores + (size_t)s * N * N * N + line0 * N : nullptr;
+    for (int t = threadIdx.x; t < 2 * COLS * N; t += kThreads) {
+        const int l = t / N, x = t % N;
+        const float2 zz = res[(l >> 1) * SC + x];
+        const float v = (l & 1) ? zz.y : zz.x;
+        if (dst) dst[(size_t)l * N + x] = v;
+        const int gi = (int)((line0 + l) * N + x);
         if (v > best || (v == best && gi < besti)) {
             best = v;
             besti = gi;
@@ -541,10 +759,10 @@ __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ 
     red_v[threadIdx.x] = best;
     red_i[threadIdx.x] = besti;
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            float v2 = red_v[threadIdx.x + off];
-            int i2 = red_i[threadIdx.x + off];
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            const float v2 = red_v[threadIdx.x + off];
+            const int i2 = red_i[threadIdx.x + off];
             if (v2 > red_v[threadIdx.x] || (v2 == red_v[threadIdx.x] && i2 < red_i[threadIdx.x])) {
                 red_v[threadIdx.x] = v2;
                 red_i[threadIdx.x] = i2;
@@ -566,9 +784,9 @@ __global__ __launch_bounds__(kThreads) void k_peak_final(const float* __restrict
     const int s = blockIdx.x;
     float best = -INFINITY;
     int besti = 0x7fffffff;
-    for (int t = threadIdx.x; t < nblocks; t += blockDim.x) {
-        float v = pval[(size_t)s * nblocks + t];
-        int i = pidx[(size_t)s * nblocks + t];
+    for (int t = threadIdx.x; t < nblocks; t += kThreads) {
+        const float v = pval[(size_t)s * nblocks + t];
+        const int i = pidx[(size_t)s * nblocks + t];
         if (v > best || (v == best && i < besti)) {
             best = v;
             besti = i;
@@ -577,10 +795,10 @@ __global__ __launch_bounds__(kThreads) void k_peak_final(const float* __restrict
     red_v[threadIdx.x] = best;
     red_i[threadIdx.x] = besti;
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            float v2 = red_v[threadIdx.x + off];
-            int i2 = red_i[threadIdx.x + off];
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            const float v2 = red_v[threadIdx.x + off];
+            const int i2 = red_i[threadIdx.x + off];
             if (v2 > red_v[threadIdx.x] || (v2 == red_v[threadIdx.x] && i2 < red_i[threadIdx.x])) {
                 red_v[threadIdx.x] = v2;
                 red_i[threadIdx.x] = i2;
@@ -599,6 +817,40 @@ __global__ __launch_bounds__(kThreads) void k_peak_final(const float* __restrict
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+namespace {
+
+// Call f(std::integral_constant<int, M>) for the spreading-grid size m.
+template <class F>
+hipError_t with_m(int m, F&& f) {
+    switch (m) {
+        case 32: f(std::integral_constant<int, 32>{}); break;
+        case 64: f(std::integral_constant<int, 64>{}); break;
+        case 128: f(std::integral_constant<int, 128>{}); break;
+        case 256: f(std::integral_constant<int, 256>{}); break;
+        case 512: f(std::integral_constant<int, 512>{}); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+constexpr size_t kSpreadLds = 80 * 1024;  // two spreading workgroups per CU
+
+template <int M>
+int spread_cap_t(int w, int q) {
+    const size_t per = sizeof(float) * (2 + 2 * (size_t)w + q);
+    const size_t fixed = SpreadShape<M>::FIXED;
+    const size_t room = fixed < kSpreadLds ? kSpreadLds - fixed : 0;
+    int cap = (int)std::min<size_t>(512, room / per);
+    cap &= ~63;
+    return cap < 64 ? 64 : cap;
+}
+
+template <int M>
+size_t spread_lds_t(int w, int q) {
+    return SpreadShape<M>::FIXED + (size_t)spread_cap_t<M>(w, q) * sizeof(float) * (2 + 2 * (size_t)w + q);
+}
+
+}  // namespace
 
 hipError_t launch_deconv_tables(const Geom& g, double box, const double origin[3], double* d_deconv,
                                 double2* d_phase, hipStream_t st) {
@@ -614,89 +866,117 @@ hipError_t launch_ball_table(const Geom& g, double dk, const double* d_nodes, co
     return hipGetLastError();
 }
 
-hipError_t launch_rotate(const Geom& g, const double* d_quats, int S, const double* d_pos, int64_t nk,
-                         float4* d_knots, hipStream_t st) {
+hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const double* d_pos, int64_t nk,
+                             int* d_cell, float* d_kbw, int* d_rank, int* d_counts, hipStream_t st) {
     if (nk == 0 || S == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rotate, dim3((unsigned)((nk + 255) / 256), S), dim3(256), 0, st, d_quats, d_pos, nk,
-                       g.inv_hf, g.m, d_knots);
+    const int nblk = bin_blocks(nk);
+    hipLaunchKernelGGL(k_rotate_bin, dim3(nblk, S), dim3(kBinBlock), 0, st, d_quats, d_pos, nk, g.inv_hf, g.m, g.w,
+                       g.beta, g.inv_i0beta, d_cell, d_kbw, d_rank, d_counts, nblk);
     return hipGetLastError();
 }
 
-hipError_t launch_zero(float* p, size_t count, hipStream_t st) {
-    size_t n4 = count / 4;  // all buffers are multiples of 4 floats
-    if (n4 == 0) return hipSuccess;
-    size_t blocks = (n4 + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<float4*>(p), n4);
-    return hipGetLastError();
-}
-
-hipError_t launch_spread(const Geom& g, const float4* d_knots, int S, int64_t nk, const float* d_wts, int q,
-                         float* d_fine, hipStream_t st) {
+hipError_t launch_bin_sort(const Geom& g, int S, int64_t nk, int q, const int* d_cell, const float* d_kbw,
+                           const float* d_wts, const int* d_rank, int* d_counts, int* d_bin_start, int* d_scell,
+                           float* d_skbw, float* d_swts, hipStream_t st) {
     if (nk == 0 || S == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spread, dim3((unsigned)nk, S), dim3(64), 0, st, d_knots, nk, d_wts, q, g.m, g.w, g.beta,
-                       g.inv_i0beta, d_fine);
+    const int nblk = bin_blocks(nk);
+    hipLaunchKernelGGL(k_bin_scan, dim3(S), dim3(1024), 0, st, d_counts, g.m, nblk, nk, d_bin_start);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_scatter, dim3(nblk, S), dim3(kBinBlock), 0, st, d_cell, d_kbw, d_wts, d_rank, d_counts,
+                       nk, g.m, g.w, q, nblk, d_scell, d_skbw, d_swts);
     return hipGetLastError();
 }
 
-hipError_t launch_fft_x(const Geom& g, const float* d_fine, int slabs, float2* d_out, const float2* d_twm,
-                        hipStream_t st) {
-    const int cols = fft_cols_for(g.m, g.m * g.m / 2);
-    const size_t lds = sizeof(float2) * 2 * (size_t)cols * (g.m + 1);
-    hipLaunchKernelGGL(k_fft_x, dim3((unsigned)(g.m * g.m / (2 * cols)), slabs), dim3(kThreads), lds, st, d_fine,
-                       d_out, g.m, g.half, cols, d_twm);
-    return hipGetLastError();
+size_t max_lds_bytes(const Geom& g, int qmax) {
+    size_t need = 0;
+    with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        constexpr int N = M / 2;
+        using C = ColShape<M>;
+        need = std::max(need, spread_lds_t<M>(g.w, qmax));
+        need = std::max(need, sizeof(float2) * ((size_t)2 * M * C::COLS + M + N));
+        need = std::max(need, sizeof(float2) * ((size_t)2 * N * C::ICOLS + N));
+        need = std::max(need, sizeof(float2) * ((size_t)2 * C::XCOLS * (N + 1) + N) + 8 * kThreads);
+    });
+    return need;
+}
+
+hipError_t launch_spread_fftx(const Geom& g, int S, int64_t nk, const int* d_bin_start, const int* d_scell,
+                              const float* d_skbw, const float* d_swts, int q, float fix_scale, float2* d_out,
+                              const float2* d_twm, hipStream_t st) {
+    if (S == 0) return hipSuccess;
+    return with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        constexpr int TY = SpreadShape<M>::TY;
+        hipLaunchKernelGGL(k_spread_fftx<M>, dim3(M / TY, M, S), dim3(kThreads), spread_lds_t<M>(g.w, q), st,
+                           d_bin_start, d_scell, d_skbw, d_swts, nk, q, g.w, spread_cap_t<M>(g.w, q), fix_scale,
+                           1.0f / fix_scale, d_out, d_twm);
+    });
 }
 
 hipError_t launch_fft_y(const Geom& g, const float2* d_in, int slabs, float2* d_out, const float2* d_twm,
                         hipStream_t st) {
-    const int cols = fft_cols_for(g.m, g.half);
-    const size_t lds = sizeof(float2) * 2 * (size_t)cols * g.m;
-    hipLaunchKernelGGL(k_fft_y, dim3(g.half / cols, g.m, slabs), dim3(kThreads), lds, st, d_in, d_out, g.m, g.n,
-                       g.half, cols, d_twm);
-    return hipGetLastError();
+    return with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        using C = ColShape<M>;
+        hipLaunchKernelGGL(k_fft_y<M>, dim3(C::H / C::COLS, M, slabs), dim3(kThreads),
+                           sizeof(float2) * ((size_t)2 * M * C::COLS + M), st, d_in, d_out, d_twm);
+    });
 }
 
 hipError_t launch_fft_z_spectrum(const Geom& g, const float2* d_in, int S, int q, const float* d_vtab,
                                  const double* d_deconv, float2* d_spec, const float2* d_twm, hipStream_t st) {
-    const int cols = fft_cols_for(g.m, g.half);
-    const size_t lds = sizeof(float2) * ((size_t)2 * cols * g.m + (size_t)cols * g.n);
-    hipLaunchKernelGGL(k_fft_z_spectrum, dim3(g.half / cols, g.n, S), dim3(kThreads), lds, st, d_in, q, d_vtab,
-                       g.m2n, d_deconv, d_spec, g.m, g.n, g.half, cols, d_twm);
-    return hipGetLastError();
+    return with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        using C = ColShape<M>;
+        hipLaunchKernelGGL(k_fft_z_spectrum<M>, dim3(C::H / C::COLS, C::N, S), dim3(kThreads),
+                           sizeof(float2) * ((size_t)2 * M * C::COLS + M), st, d_in, q, d_vtab, g.m2n, d_deconv,
+                           d_spec, d_twm);
+    });
 }
 
 hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q, const float* d_vtab,
                                 const double2* d_phase, const float2* d_fa, float2* d_out, const float2* d_twm,
                                 const float2* d_twn, hipStream_t st) {
-    const int cols = fft_cols_for(g.m, g.half);
-    const size_t lds = sizeof(float2) * ((size_t)2 * cols * g.m + (size_t)cols * g.n);
-    hipLaunchKernelGGL(k_fft_z_product, dim3(g.half / cols, g.n, S), dim3(kThreads), lds, st, d_in, q, d_vtab,
-                       g.m2n, d_phase, d_fa, d_out, g.m, g.n, g.half, cols, d_twm, d_twn);
-    return hipGetLastError();
+    return with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        using C = ColShape<M>;
+        hipLaunchKernelGGL(k_fft_z_product<M>, dim3(C::H / C::COLS, C::N, S), dim3(kThreads),
+                           sizeof(float2) * ((size_t)2 * M * C::COLS + M + C::N), st, d_in, q, d_vtab, g.m2n,
+                           d_phase, d_fa, d_out, d_twm, d_twn);
+    });
 }
 
 hipError_t launch_ifft_y(const Geom& g, const float2* d_in, int S, float2* d_out, const float2* d_twn,
                          hipStream_t st) {
-    const int cols = fft_cols_for(g.n, g.half);
-    const size_t lds = sizeof(float2) * 2 * (size_t)cols * g.n;
-    hipLaunchKernelGGL(k_ifft_y, dim3(g.half / cols, g.n, S), dim3(kThreads), lds, st, d_in, d_out, g.n, g.half,
-                       cols, d_twn);
-    return hipGetLastError();
+    return with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        using C = ColShape<M>;
+        hipLaunchKernelGGL(k_ifft_y<M>, dim3(C::H / C::ICOLS, C::N, S), dim3(kThreads),
+                           sizeof(float2) * ((size_t)2 * C::N * C::ICOLS + C::N), st, d_in, d_out, d_twn);
+    });
 }
 
 int ifft_x_blocks(const Geom& g) {
-    const int cols = fft_cols_for(g.n, g.n * g.n / 2);
-    return g.n * g.n / (2 * cols);
+    int nb = 0;
+    with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        using C = ColShape<M>;
+        nb = C::N * C::N / (2 * C::XCOLS);
+    });
+    return nb;
 }
 
 hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scores, float* d_pval, int* d_pidx,
                          const float2* d_twn, hipStream_t st) {
-    const int cols = fft_cols_for(g.n, g.n * g.n / 2);
-    const size_t lds = sizeof(float2) * 2 * (size_t)cols * (g.n + 1);
-    hipLaunchKernelGGL(k_ifft_x, dim3((unsigned)ifft_x_blocks(g), S), dim3(kThreads), lds, st, d_in, d_scores,
-                       d_pval, d_pidx, g.n, g.half, cols, d_twn);
-    return hipGetLastError();
+    return with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        using C = ColShape<M>;
+        hipLaunchKernelGGL(k_ifft_x<M>, dim3(C::N * C::N / (2 * C::XCOLS), S), dim3(kThreads),
+                           sizeof(float2) * ((size_t)2 * C::XCOLS * (C::N + 1) + C::N), st, d_in, d_scores, d_pval,
+                           d_pidx, d_twn);
+    });
 }
 
 hipError_t launch_peak_final(const float* d_pval, const int* d_pidx, int S, int nblocks, float* d_peak_val,

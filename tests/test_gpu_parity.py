@@ -218,3 +218,19 @@ def test_batched_rotations_full_size_sampled():
     ref = _o2(A, B, q[pick], g)
     _check_scores("c3", s[pick].double().cpu().numpy(), ref)
     c.close()
+
+
+def test_repeated_evaluation_is_bitwise_identical():
+    # spreading sums are exact fixed-point integers: no dependence on scheduling
+    A = synth.mixture_balls(3000, 1300)
+    B = synth.mixture_balls(2500, 2300)
+    g = synth.grid_for(A, B, 64)
+    q = synth.random_quaternions(3, 3300)
+    _say("case: bitwise repeatability, 3000+2500 balls, n=64")
+    c = _corr(A, B, g, batch=2)
+    s1, p1, i1 = c.eval(q)
+    c.prepare_a()
+    s2, p2, i2 = c.eval(q)
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2) and torch.equal(p1, p2) and torch.equal(i1, i2)
+    c.close()
