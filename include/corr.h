@@ -145,6 +145,44 @@ int corr_profile(corr_ctx* ctx, int32_t enable);
  * since the last read; clears the record. */
 int corr_profile_read(corr_ctx* ctx, double* ms, int64_t* launches, int32_t n_stages);
 
+/* ---- uneven batches of pairs --------------------------------------------- */
+
+/* One shape pair with its own translation grid (grid.batch is ignored). */
+typedef struct {
+    const corr_ball* A;
+    int64_t nA;
+    const corr_ball* B;
+    int64_t nB;
+    corr_grid grid;
+} corr_pair;
+
+typedef struct corr_batch corr_batch;
+
+/*
+ * Plan every pair (ball counts and grid sizes may all differ) and share one
+ * device workspace among them, sized for the largest pair and `slots`
+ * rotations per pass (0 = largest that fits 4 GiB, at most 64).  Computes every
+ * A spectrum.  Pair p is validated like corr_create; its errors name the pair.
+ */
+int corr_batch_create(const corr_pair* pairs, int32_t n_pairs, int32_t slots, void* hip_stream,
+                      corr_batch** out);
+
+/*
+ * Score rotation r = rot_offsets[p] .. rot_offsets[p+1]-1 (host quaternions
+ * quat_wxyz[r]) of pair p, for every p.  rot_offsets: host int64 [n_pairs + 1],
+ * starting at 0, non-decreasing.  scores_dev (or NULL): pair p's
+ * [rotations][n_p][n_p][n_p] block starts at float offset score_offsets[p]
+ * (host int64 [n_pairs]), or, with score_offsets NULL, the blocks are packed in
+ * pair order.  peak_val_dev / peak_idx_dev (device, [rot_offsets[n_pairs]],
+ * both or neither): per-rotation peaks as in corr_eval.  Asynchronous.
+ */
+int corr_batch_eval(corr_batch* b, const double* quat_wxyz, const int64_t* rot_offsets, float* scores_dev,
+                    const int64_t* score_offsets, float* peak_val_dev, int64_t* peak_idx_dev);
+
+int corr_batch_info(const corr_batch* b, int32_t pair, corr_info_t* out);
+int corr_batch_destroy(corr_batch* b);
+const char* corr_batch_last_error(const corr_batch* b);
+
 /* Free the context and its device memory (waits for its stream).  NULL is a no-op. */
 int corr_destroy(corr_ctx* ctx);
 

@@ -29,7 +29,8 @@ CORR_EUNSUPPORTED = -4
 CORR_DETERMINISTIC = 1
 
 EXPORTS = ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
-           "corr_profile_read", "corr_destroy", "corr_last_error")
+           "corr_profile_read", "corr_destroy", "corr_last_error", "corr_batch_create", "corr_batch_eval",
+           "corr_batch_info", "corr_batch_destroy", "corr_batch_last_error")
 STAGES = ("rotate", "bin", "spread_fft_x", "fft_y", "fft_z_spectrum", "fft_z_product", "ifft_y", "ifft_x", "peak")
 
 
@@ -198,6 +199,288 @@ class Correlator:
         if getattr(self, "ctx", None):
             corr_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- proposal network (include/prop.h) ----------------------------------------
+
+PROP_EXPORTS = ("prop_create", "prop_descriptor", "prop_features", "prop_train", "prop_predict", "prop_rank",
+                "prop_gradient", "prop_get_params", "prop_set_params", "prop_destroy", "prop_last_error")
+PROP_IN, PROP_HIDDEN, PROP_BINS = 160, 256, 64
+PROP_NPARAMS = 160 * 256 + 256 + 2 * (256 * 256 + 256) + 256 + 1
+
+
+def _prop_lib():
+    lib = load_library()
+    if not getattr(lib, "_prop_declared", False):
+        vp, i64, i32, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float
+        lib.prop_create.argtypes = [i32, ctypes.c_uint64, vp, ctypes.POINTER(vp)]
+        lib.prop_descriptor.argtypes = [vp, vp, i64, vp]
+        lib.prop_features.argtypes = [vp, vp, i64, vp, vp, vp]
+        lib.prop_train.argtypes = [vp, vp, vp, i64, i32, f32, vp]
+        lib.prop_predict.argtypes = [vp, vp, i64, vp]
+        lib.prop_rank.argtypes = [vp, vp, i64, i32, vp]
+        lib.prop_gradient.argtypes = [vp, vp, vp, i64, vp]
+        lib.prop_get_params.argtypes = [vp, vp]
+        lib.prop_set_params.argtypes = [vp, vp]
+        lib.prop_destroy.argtypes = [vp]
+        lib.prop_last_error.argtypes = [vp]
+        lib.prop_last_error.restype = ctypes.c_char_p
+        for name in PROP_EXPORTS[:-1]:
+            getattr(lib, name).restype = ctypes.c_int
+        lib._prop_declared = True
+    return lib
+
+
+def _pcheck(rc, ctx=None):
+    if rc != CORR_OK:
+        raise CorrError(rc, _prop_lib().prop_last_error(ctx).decode())
+
+
+def prop_create(batch, seed, stream=0):
+    out = ctypes.c_void_p()
+    _pcheck(_prop_lib().prop_create(int(batch), int(seed), ctypes.c_void_p(stream or None), ctypes.byref(out)))
+    return out
+
+
+def prop_descriptor(ctx, balls, desc_ptr):
+    b = _balls(balls)
+    _pcheck(_prop_lib().prop_descriptor(ctx, b.ctypes.data, len(b), desc_ptr), ctx)
+
+
+def prop_features(ctx, quats, desc_a_ptr, desc_b_ptr, x_ptr):
+    q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
+    _pcheck(_prop_lib().prop_features(ctx, q.ctypes.data, len(q), desc_a_ptr, desc_b_ptr, x_ptr), ctx)
+
+
+def prop_train(ctx, x_ptr, y_ptr, n, epochs, lr):
+    losses = np.zeros(max(int(epochs), 1), dtype=np.float32)
+    _pcheck(_prop_lib().prop_train(ctx, x_ptr, y_ptr, int(n), int(epochs), float(lr), losses.ctypes.data), ctx)
+    return losses[:epochs]
+
+
+def prop_predict(ctx, x_ptr, n, y_ptr):
+    _pcheck(_prop_lib().prop_predict(ctx, x_ptr, int(n), y_ptr), ctx)
+
+
+def prop_rank(ctx, x_ptr, n, k, idx_ptr):
+    _pcheck(_prop_lib().prop_rank(ctx, x_ptr, int(n), int(k), idx_ptr), ctx)
+
+
+def prop_gradient(ctx, x_ptr, y_ptr, n) -> np.ndarray:
+    g = np.zeros(PROP_NPARAMS, dtype=np.float32)
+    _pcheck(_prop_lib().prop_gradient(ctx, x_ptr, y_ptr, int(n), g.ctypes.data), ctx)
+    return g
+
+
+def prop_get_params(ctx) -> np.ndarray:
+    p = np.zeros(PROP_NPARAMS, dtype=np.float32)
+    _pcheck(_prop_lib().prop_get_params(ctx, p.ctypes.data), ctx)
+    return p
+
+
+def prop_set_params(ctx, params):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+    if p.size != PROP_NPARAMS:
+        raise ValueError("need %d parameters" % PROP_NPARAMS)
+    _pcheck(_prop_lib().prop_set_params(ctx, p.ctypes.data), ctx)
+
+
+def prop_destroy(ctx):
+    _prop_lib().prop_destroy(ctx)
+
+
+def prop_last_error(ctx=None) -> str:
+    return _prop_lib().prop_last_error(ctx).decode()
+
+
+def unpack_params(flat):
+    """Split a flat parameter vector into [(W (in, out), b)] for the four layers."""
+    flat = np.asarray(flat)
+    out, o = [], 0
+    for fi, fo in ((160, 256), (256, 256), (256, 256), (256, 1)):
+        W = flat[o:o + fi * fo].reshape(fi, fo)
+        o += fi * fo
+        b = flat[o:o + fo]
+        o += fo
+        out.append((W, b))
+    return out
+
+
+class Proposer:
+    """Proposal network on torch device memory."""
+
+    def __init__(self, batch=1024, seed=0, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device or "cuda")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.ctx = prop_create(batch, seed, self.stream.cuda_stream)
+
+    def descriptor(self, balls):
+        d = self.torch.empty(PROP_BINS, dtype=self.torch.float32, device=self.device)
+        prop_descriptor(self.ctx, balls, d.data_ptr())
+        return d
+
+    def features(self, quats, desc_a, desc_b):
+        q = np.asarray(quats, dtype=np.float64).reshape(-1, 4)
+        X = self.torch.empty((len(q), PROP_IN), dtype=self.torch.float32, device=self.device)
+        prop_features(self.ctx, q, desc_a.data_ptr(), desc_b.data_ptr(), X.data_ptr())
+        return X
+
+    def train(self, X, y, epochs, lr):
+        return prop_train(self.ctx, X.data_ptr(), y.data_ptr(), X.shape[0], epochs, lr)
+
+    def predict(self, X):
+        y = self.torch.empty(X.shape[0], dtype=self.torch.float32, device=self.device)
+        prop_predict(self.ctx, X.data_ptr(), X.shape[0], y.data_ptr())
+        return y
+
+    def rank(self, X, k):
+        idx = self.torch.empty(k, dtype=self.torch.int64, device=self.device)
+        prop_rank(self.ctx, X.data_ptr(), X.shape[0], k, idx.data_ptr())
+        return idx
+
+    def gradient(self, X, y):
+        return prop_gradient(self.ctx, X.data_ptr(), y.data_ptr(), X.shape[0])
+
+    def get_params(self):
+        return prop_get_params(self.ctx)
+
+    def set_params(self, p):
+        prop_set_params(self.ctx, p)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            prop_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- uneven batches (corr_batch_*) ---------------------------------------------
+
+BATCH_EXPORTS = ("corr_batch_create", "corr_batch_eval", "corr_batch_info", "corr_batch_destroy",
+                 "corr_batch_last_error")
+
+
+class corr_pair(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("nA", ctypes.c_int64), ("B", ctypes.c_void_p), ("nB", ctypes.c_int64),
+                ("grid", corr_grid)]
+
+
+def _batch_lib():
+    lib = load_library()
+    if not getattr(lib, "_batch_declared", False):
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        lib.corr_batch_create.argtypes = [vp, i32, i32, vp, ctypes.POINTER(vp)]
+        lib.corr_batch_eval.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        lib.corr_batch_info.argtypes = [vp, i32, ctypes.POINTER(corr_info_t)]
+        lib.corr_batch_destroy.argtypes = [vp]
+        lib.corr_batch_last_error.argtypes = [vp]
+        lib.corr_batch_last_error.restype = ctypes.c_char_p
+        for name in BATCH_EXPORTS[:-1]:
+            getattr(lib, name).restype = ctypes.c_int
+        lib._batch_declared = True
+    return lib
+
+
+def _bcheck(rc, b=None):
+    if rc != CORR_OK:
+        raise CorrError(rc, _batch_lib().corr_batch_last_error(b).decode())
+
+
+def corr_batch_create(pairs, slots=0, stream=0):
+    """pairs: list of (A, B, grid) with grid a corr_grid."""
+    keep = []
+    arr = (corr_pair * len(pairs))()
+    for i, (A, B, g) in enumerate(pairs):
+        A, B = _balls(A), _balls(B)
+        keep += [A, B]
+        arr[i].A = A.ctypes.data if len(A) else None
+        arr[i].nA = len(A)
+        arr[i].B = B.ctypes.data if len(B) else None
+        arr[i].nB = len(B)
+        arr[i].grid = g
+    out = ctypes.c_void_p()
+    _bcheck(_batch_lib().corr_batch_create(arr, len(pairs), int(slots), ctypes.c_void_p(stream or None),
+                                           ctypes.byref(out)))
+    return out
+
+
+def corr_batch_eval(b, quats, rot_offsets, scores_ptr, score_offsets, peak_val_ptr, peak_idx_ptr):
+    q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
+    ro = np.ascontiguousarray(np.asarray(rot_offsets, dtype=np.int64))
+    so = None if score_offsets is None else np.ascontiguousarray(np.asarray(score_offsets, dtype=np.int64))
+    _bcheck(_batch_lib().corr_batch_eval(b, q.ctypes.data if len(q) else None, ro.ctypes.data, scores_ptr or None,
+                                         so.ctypes.data if so is not None else None, peak_val_ptr or None,
+                                         peak_idx_ptr or None), b)
+
+
+def corr_batch_info(b, pair) -> dict:
+    info = corr_info_t()
+    _bcheck(_batch_lib().corr_batch_info(b, int(pair), ctypes.byref(info)), b)
+    return {k: getattr(info, k) for k, _ in corr_info_t._fields_}
+
+
+def corr_batch_destroy(b):
+    _batch_lib().corr_batch_destroy(b)
+
+
+class Batch:
+    """Uneven batch of pairs on torch device memory; peaks for every rotation and,
+    optionally, the packed scores of every pair."""
+
+    def __init__(self, pairs, slots=0, device=None):
+        """pairs: list of (A, B, n, box, origin)."""
+        import torch
+        self.torch = torch
+        self.device = torch.device(device or "cuda")
+        self.ns = [int(p[2]) for p in pairs]
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.b = corr_batch_create([(A, B, make_grid(n, box, origin)) for A, B, n, box, origin in pairs], slots,
+                                       self.stream.cuda_stream)
+
+    def eval(self, quats_per_pair, scores=False):
+        torch = self.torch
+        counts = [len(q) for q in quats_per_pair]
+        offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        q = np.concatenate([np.asarray(x, dtype=np.float64).reshape(-1, 4) for x in quats_per_pair])
+        pv = torch.empty(int(offs[-1]), dtype=torch.float32, device=self.device)
+        pi = torch.empty(int(offs[-1]), dtype=torch.int64, device=self.device)
+        s = None
+        if scores:
+            total = sum(c * n ** 3 for c, n in zip(counts, self.ns))
+            s = torch.empty(total, dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            corr_batch_eval(self.b, q, offs, s.data_ptr() if s is not None else None, None, pv.data_ptr(),
+                            pi.data_ptr())
+        out = None
+        if scores:
+            out, o = [], 0
+            for c, n in zip(counts, self.ns):
+                out.append(s[o:o + c * n ** 3].view(c, n, n, n))
+                o += c * n ** 3
+        return out, pv, pi, offs
+
+    def info(self, pair):
+        return corr_batch_info(self.b, pair)
+
+    def close(self):
+        if getattr(self, "b", None):
+            corr_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

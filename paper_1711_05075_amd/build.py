@@ -42,7 +42,8 @@ def build_library(verbose: bool = False) -> str:
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = []
-    for src, lang in (("corr_kernels.hip", "hip"), ("corr_host.cpp", "hip")):
+    for src, lang in (("corr_kernels.hip", "hip"), ("corr_host.cpp", "hip"), ("prop_kernels.hip", "hip"),
+                      ("prop_host.cpp", "hip")):
         obj = os.path.join(bdir, src + ".o")
         cmd = [hipcc, "-x", lang, "--offload-arch=" + ARCH, *COMMON, *DEVICE_FLAGS, "-c",
                os.path.join(CSRC, src), "-o", obj]

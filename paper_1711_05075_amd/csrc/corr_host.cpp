@@ -268,38 +268,93 @@ struct Shape {
 
 }  // namespace
 
+namespace corr {
+
+// Buffers of one pipeline pass, `slots` rotations at a time; every per-slot
+// region is sized for the largest plan that uses the workspace.
+struct WsReq {
+    size_t buf0 = 0, buf1 = 0;      // floats, float2 per slot
+    size_t nk = 1, nkw = 1, nkq = 1;  // knots, knots*3w, knots*q per slot
+    size_t counts = 1, bins = 1;    // m * sort blocks, m + 1 per slot
+    size_t blocks = 1;              // inverse-x blocks per slot
+    void merge(const WsReq& o) {
+        buf0 = std::max(buf0, o.buf0); buf1 = std::max(buf1, o.buf1);
+        nk = std::max(nk, o.nk); nkw = std::max(nkw, o.nkw); nkq = std::max(nkq, o.nkq);
+        counts = std::max(counts, o.counts); bins = std::max(bins, o.bins); blocks = std::max(blocks, o.blocks);
+    }
+    size_t slot_bytes() const {
+        return 4 * buf0 + 8 * buf1 + 4 * (3 * nk + nkw + nkq) + 12 * nkw + 4 * (counts + bins) + 8 * blocks + 32;
+    }
+};
+
+struct Workspace {
+    int slots = 1;
+    WsReq req;
+    DevMem mem;
+    float* buf0 = nullptr;         // [slots][q][m][n][half] complex (after y; reused after inverse z)
+    float2* buf1 = nullptr;        // [slots][q][m^2][half] (after spread + x; reused after product)
+    int* cell = nullptr;           // [slots][nk] packed cell of each knot
+    float* kbw = nullptr;          // [slots][nk][3][w] window weights
+    int* rank = nullptr;           // [slots][nk] rank within its sort block and z-cell
+    int* counts = nullptr;         // [slots][m][blocks] counts, then offsets
+    int* bin_start = nullptr;      // [slots][m + 1]
+    int* scell = nullptr;          // [slots][nk] sorted by z-cell: packed cell
+    float* skbw = nullptr;         // [slots][nk][3][w]              window weights
+    float* swts = nullptr;         // [slots][nk][q]                 component weights
+    double* quats = nullptr;       // [slots][4]
+    float* pval = nullptr;         // [slots][blocks]
+    int* pidx = nullptr;
+    double* host_quats = nullptr;  // pinned [slots][4]
+    hipEvent_t quat_done = nullptr;
+
+    void allocate(int nslots, const WsReq& r, hipStream_t st) {
+        slots = nslots;
+        req = r;
+        const size_t S = (size_t)nslots;
+        buf0 = mem.alloc<float>(S * r.buf0);
+        buf1 = mem.alloc<float2>(S * r.buf1);
+        cell = mem.alloc<int>(S * r.nk);
+        kbw = mem.alloc<float>(S * r.nkw);
+        rank = mem.alloc<int>(S * r.nk);
+        counts = mem.alloc<int>(S * r.counts);
+        bin_start = mem.alloc<int>(S * r.bins);
+        scell = mem.alloc<int>(S * r.nk);
+        skbw = mem.alloc<float>(S * r.nkw);
+        swts = mem.alloc<float>(S * r.nkq);
+        quats = mem.alloc<double>(S * 4);
+        pval = mem.alloc<float>(S * r.blocks);
+        pidx = mem.alloc<int>(S * r.blocks);
+        hip_check(hipHostMalloc((void**)&host_quats, sizeof(double) * 4 * S, hipHostMallocDefault), "hipHostMalloc");
+        hip_check(hipEventCreateWithFlags(&quat_done, hipEventDisableTiming), "hipEventCreate");
+        hip_check(hipEventRecord(quat_done, st), "event");
+    }
+    void release() {
+        mem.release();
+        if (host_quats) (void)hipHostFree(host_quats);
+        host_quats = nullptr;
+        if (quat_done) (void)hipEventDestroy(quat_done);
+        quat_done = nullptr;
+    }
+};
+
+}  // namespace corr
+
 struct corr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     Geom g;
     double box = 0, origin[3] = {0, 0, 0}, sigma = 2, tol = 1e-6;
     uint32_t flags = 0;
-    int batch = 1;
     int qmax = 1;
+    int64_t nkmax = 1;  // max(nA, nB, 1)
     Shape A, B;
     DevMem mem;
     float2 *twm = nullptr, *twn = nullptr;
     double* deconv = nullptr;
     double2* phase = nullptr;
     float2* fa = nullptr;          // fixed shape's spectrum [n][n][half]
-    float* buf0 = nullptr;         // [batch][qmax][m][n][half] complex (after y; reused after inverse z)
-    float2* buf1 = nullptr;        // [batch][qmax][m^2][half] (after spread + x; reused after product)
-    int64_t nkmax = 1;             // max(nA, nB, 1)
-    int* cell = nullptr;           // [batch][nkmax] packed cell of each knot
-    float* kbw = nullptr;          // [batch][nkmax][3][w] window weights
-    int* rank = nullptr;           // [batch][nkmax] rank within its sort block and z-cell
-    int* counts = nullptr;         // [batch][m][blocks] counts, then offsets
-    int* bin_start = nullptr;      // [batch][m + 1]
-    int* scell = nullptr;          // [batch][nkmax] sorted by z-cell: packed cell
-    float* skbw = nullptr;         // [batch][nkmax][3][w]              window weights
-    float* swts = nullptr;         // [batch][nkmax][q]                 component weights
-    double* quats = nullptr;       // [batch][4]
-    float* pval = nullptr;         // [batch][blocks]
-    int* pidx = nullptr;
-    float* peak_tmp_v = nullptr;   // [batch] when the caller wants no peaks
-    int64_t* peak_tmp_i = nullptr;
-    double* host_quats = nullptr;  // pinned [batch][4]
-    hipEvent_t quat_done = nullptr;
+    corr::Workspace* ws = nullptr;  // per-rotation buffers (shared by the pairs of a batch)
+    bool own_ws = false;
     // stage timing (corr_profile): event pairs recorded around each launch
     bool profiling = false;
     struct Mark { int stage; hipEvent_t a, b; };
@@ -310,8 +365,6 @@ struct corr_ctx {
 
 namespace {
 
-size_t buf0_floats(const corr_ctx* c) { return (size_t)2 * c->qmax * c->g.m * c->g.n * c->g.half; }
-size_t buf1_float2(const corr_ctx* c) { return (size_t)c->qmax * c->g.m * c->g.m * c->g.half; }
 
 void upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
     hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync H2D");
@@ -421,18 +474,18 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
     const Geom& g = c->g;
     const int q = s.ex.q;
     stage(c, CORR_STAGE_ROTATE, "rotate", [&] {
-        return corr::launch_rotate_bin(g, d_quats, S, s.pos, s.n, c->cell, c->kbw, c->rank, c->counts, c->stream);
+        return corr::launch_rotate_bin(g, d_quats, S, s.pos, s.n, c->ws->cell, c->ws->kbw, c->ws->rank, c->ws->counts, c->stream);
     });
     stage(c, CORR_STAGE_BIN, "bin", [&] {
-        return corr::launch_bin_sort(g, S, s.n, q, c->cell, c->kbw, s.wts, c->rank, c->counts, c->bin_start, c->scell,
-                                     c->skbw, c->swts, c->stream);
+        return corr::launch_bin_sort(g, S, s.n, q, c->ws->cell, c->ws->kbw, s.wts, c->ws->rank, c->ws->counts, c->ws->bin_start, c->ws->scell,
+                                     c->ws->skbw, c->ws->swts, c->stream);
     });
     stage(c, CORR_STAGE_SPREAD_FFT_X, "spread + fft x", [&] {
-        return corr::launch_spread_fftx(g, S, s.n, c->bin_start, c->scell, c->skbw, c->swts, q, s.fix_scale, c->buf1,
+        return corr::launch_spread_fftx(g, S, s.n, c->ws->bin_start, c->ws->scell, c->ws->skbw, c->ws->swts, q, s.fix_scale, c->ws->buf1,
                                         c->twm, c->stream);
     });
     stage(c, CORR_STAGE_FFT_Y, "fft y", [&] {
-        return corr::launch_fft_y(g, c->buf1, S * q, reinterpret_cast<float2*>(c->buf0), c->twm, c->stream);
+        return corr::launch_fft_y(g, c->ws->buf1, S * q, reinterpret_cast<float2*>(c->ws->buf0), c->twm, c->stream);
     });
 }
 
@@ -441,19 +494,19 @@ void stage_quats(corr_ctx* c, const double* q, int S);
 void prepare_a(corr_ctx* c) {
     static const double ident[4] = {1, 0, 0, 0};
     stage_quats(c, ident, 1);
-    run_spectrum_stages(c, c->A, c->quats, 1);
+    run_spectrum_stages(c, c->A, c->ws->quats, 1);
     stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z (A)", [&] {
-        return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->buf0), 1, c->A.ex.q, c->A.vtab, c->deconv,
+        return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->ws->buf0), 1, c->A.ex.q, c->A.vtab, c->deconv,
                                            c->fa, c->twm, c->stream);
     });
 }
 
 // host quaternions -> pinned staging -> device, S at a time
 void stage_quats(corr_ctx* c, const double* q, int S) {
-    hip_check(hipEventSynchronize(c->quat_done), "event sync");
-    std::memcpy(c->host_quats, q, sizeof(double) * 4 * S);
-    hip_check(hipMemcpyAsync(c->quats, c->host_quats, sizeof(double) * 4 * S, hipMemcpyHostToDevice, c->stream), "quat H2D");
-    hip_check(hipEventRecord(c->quat_done, c->stream), "event");
+    hip_check(hipEventSynchronize(c->ws->quat_done), "event sync");
+    std::memcpy(c->ws->host_quats, q, sizeof(double) * 4 * S);
+    hip_check(hipMemcpyAsync(c->ws->quats, c->ws->host_quats, sizeof(double) * 4 * S, hipMemcpyHostToDevice, c->stream), "quat H2D");
+    hip_check(hipEventRecord(c->ws->quat_done, c->stream), "event");
 }
 
 void validate_quats(const double* q, int64_t n) {
@@ -465,6 +518,135 @@ void validate_quats(const double* q, int64_t n) {
             s += q[4 * i + k] * q[4 * i + k];
         }
         if (std::sqrt(s) < 1e-12) fail(CORR_EINVAL, "quaternion %lld has norm < 1e-12", (long long)i);
+    }
+}
+
+void destroy_ctx(corr_ctx* c);
+
+// Validate one pair and its grid, plan the window, grids and radius
+// expansions, build the tables and upload both shapes (no workspace yet).
+corr_ctx* plan_pair(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t nB, const corr_grid* grid,
+                    void* hip_stream, const char* who) {
+    if (!grid) fail(CORR_EINVAL, "%sgrid is NULL", who);
+    validate_balls(A, nA, "A");
+    validate_balls(B, nB, "B");
+    const corr_grid& gr = *grid;
+    if (gr.n != 16 && gr.n != 32 && gr.n != 64 && gr.n != 128 && gr.n != 256)
+        fail(CORR_EUNSUPPORTED, "%sgrid n = %d; supported: 16, 32, 64, 128, 256", who, gr.n);
+    if (!std::isfinite(gr.box) || !(gr.box > 0)) fail(CORR_EINVAL, "%sgrid box must be finite and > 0", who);
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(gr.origin[d])) fail(CORR_EINVAL, "%sgrid origin must be finite", who);
+    const double sigma = gr.sigma == 0 ? 2.0 : gr.sigma;
+    if (sigma != 2.0) fail(CORR_EUNSUPPORTED, "%ssigma = %g; supported: 2", who, sigma);
+    const int w = gr.kb_width == 0 ? 8 : gr.kb_width;
+    if (w < 4 || w > 12 || (w & 1)) fail(CORR_EUNSUPPORTED, "%skb_width = %d; supported: even 4..12", who, w);
+    const double tol = gr.tol == 0 ? 1e-6 : gr.tol;
+    if (!std::isfinite(tol) || !(tol > 0) || tol >= 1) fail(CORR_EINVAL, "%stol must be in (0, 1)", who);
+    if (gr.flags & ~CORR_DETERMINISTIC) fail(CORR_EINVAL, "%sunknown flag bits 0x%x", who, gr.flags);
+    if (gr.batch < 0 || gr.batch > 256) fail(CORR_EINVAL, "%sbatch = %d; allowed 0..256", who, gr.batch);
+
+    corr_ctx* c = new corr_ctx();
+    try {
+        hip_check(hipGetDevice(&c->device), "hipGetDevice");
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        c->box = gr.box;
+        std::memcpy(c->origin, gr.origin, sizeof c->origin);
+        c->sigma = sigma;
+        c->tol = tol;
+        c->flags = gr.flags;
+        Geom& g = c->g;
+        g.n = gr.n;
+        g.m = (int)std::lround(sigma * gr.n);
+        g.w = w;
+        g.half = gr.n / 2;
+        g.m2n = 3 * (g.half - 1) * (g.half - 1) + 1;
+        // window shape for oversampling sigma (Beatty, Nishimura & Pauly, 2005)
+        const double beta = M_PI * std::sqrt((w / sigma) * (w / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8);
+        g.beta = (float)beta;
+        g.inv_i0beta = (float)(1.0 / std::cyl_bessel_i(0.0, (double)g.beta));
+        g.inv_hf = g.m / gr.box;
+        const double dk = 2.0 * M_PI / gr.box;
+
+        setup_shape(c, c->A, A, nA, dk);
+        setup_shape(c, c->B, B, nB, dk);
+        c->qmax = std::max(c->A.ex.q, c->B.ex.q);
+        c->nkmax = std::max<int64_t>(std::max(nA, nB), 1);
+
+        hipDeviceProp_t prop;
+        hip_check(hipGetDeviceProperties(&prop, c->device), "hipGetDeviceProperties");
+        const size_t need = corr::max_lds_bytes(g, c->qmax);  // largest dynamic LDS of any stage
+        if (need > prop.sharedMemPerBlock)
+            fail(CORR_EUNSUPPORTED, "%sgrid n = %d needs %zu bytes of LDS per workgroup; device has %zu", who, g.n,
+                 need, (size_t)prop.sharedMemPerBlock);
+
+        std::vector<float2> tw(g.m);
+        for (int j = 0; j < g.m; ++j)
+            tw[j] = make_float2((float)std::cos(2 * M_PI * j / g.m), (float)-std::sin(2 * M_PI * j / g.m));
+        c->twm = c->mem.alloc<float2>(g.m);
+        upload(c->twm, tw.data(), sizeof(float2) * g.m, c->stream);
+        tw.resize(g.n);
+        for (int j = 0; j < g.n; ++j)
+            tw[j] = make_float2((float)std::cos(2 * M_PI * j / g.n), (float)-std::sin(2 * M_PI * j / g.n));
+        c->twn = c->mem.alloc<float2>(g.n);
+        upload(c->twn, tw.data(), sizeof(float2) * g.n, c->stream);
+        c->deconv = c->mem.alloc<double>(g.n);
+        c->phase = c->mem.alloc<double2>((size_t)3 * g.n);
+        hip_check(corr::launch_deconv_tables(g, c->box, c->origin, c->deconv, c->phase, c->stream), "deconv tables");
+        upload_shape(c, c->A, A, dk);
+        upload_shape(c, c->B, B, dk);
+        c->fa = c->mem.alloc<float2>((size_t)g.n * g.n * g.half);
+    } catch (...) {
+        destroy_ctx(c);
+        throw;
+    }
+    return c;
+}
+
+corr::WsReq ws_req(const corr_ctx* c) {
+    corr::WsReq r;
+    const Geom& g = c->g;
+    r.buf0 = (size_t)2 * c->qmax * g.m * g.n * g.half;
+    r.buf1 = (size_t)c->qmax * g.m * g.m * g.half;
+    r.nk = (size_t)c->nkmax;
+    r.nkw = (size_t)c->nkmax * 3 * g.w;
+    r.nkq = (size_t)c->nkmax * c->qmax;
+    r.counts = (size_t)g.m * corr::bin_blocks(c->nkmax);
+    r.bins = (size_t)g.m + 1;
+    r.blocks = (size_t)corr::ifft_x_blocks(g);
+    return r;
+}
+
+// Score n_rot rotations of B against A (validated here), batch by batch.
+void eval_impl(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* scores_dev, float* peak_val_dev,
+               int64_t* peak_idx_dev) {
+    if (n_rot < 0) fail(CORR_EINVAL, "n_rot < 0");
+    if ((peak_val_dev == nullptr) != (peak_idx_dev == nullptr))
+        fail(CORR_EINVAL, "peak_val_dev and peak_idx_dev must both be set or both be NULL");
+    validate_quats(quat_wxyz, n_rot);
+    const Geom& g = c->g;
+    const size_t n3 = (size_t)g.n * g.n * g.n;
+    const int nb = corr::ifft_x_blocks(g);
+    for (int64_t r0 = 0; r0 < n_rot; r0 += c->ws->slots) {
+        const int S = (int)std::min<int64_t>(c->ws->slots, n_rot - r0);
+        stage_quats(c, quat_wxyz + 4 * r0, S);
+        run_spectrum_stages(c, c->B, c->ws->quats, S);
+        stage(c, CORR_STAGE_FFT_Z_PRODUCT, "fft z product", [&] {
+            return corr::launch_fft_z_product(g, reinterpret_cast<float2*>(c->ws->buf0), S, c->B.ex.q, c->B.vtab,
+                                              c->phase, c->fa, c->ws->buf1, c->twm, c->twn, c->stream);
+        });
+        stage(c, CORR_STAGE_IFFT_Y, "ifft y", [&] {
+            return corr::launch_ifft_y(g, c->ws->buf1, S, reinterpret_cast<float2*>(c->ws->buf0), c->twn, c->stream);
+        });
+        stage(c, CORR_STAGE_IFFT_X, "ifft x", [&] {
+            return corr::launch_ifft_x(g, reinterpret_cast<float2*>(c->ws->buf0), S,
+                                       scores_dev ? scores_dev + (size_t)r0 * n3 : nullptr, c->ws->pval, c->ws->pidx,
+                                       c->twn, c->stream);
+        });
+        if (peak_val_dev)
+            stage(c, CORR_STAGE_PEAK, "peak", [&] {
+                return corr::launch_peak_final(c->ws->pval, c->ws->pidx, S, nb, peak_val_dev + r0, peak_idx_dev + r0,
+                                               c->stream);
+            });
     }
 }
 
@@ -492,8 +674,11 @@ void destroy_ctx(corr_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     c->mem.release();
-    if (c->host_quats) (void)hipHostFree(c->host_quats);
-    if (c->quat_done) (void)hipEventDestroy(c->quat_done);
+    if (c->own_ws && c->ws) {
+        c->ws->release();
+        delete c->ws;
+    }
+    c->ws = nullptr;
     for (auto& mk : c->marks) {
         (void)hipEventDestroy(mk.a);
         (void)hipEventDestroy(mk.b);
@@ -512,104 +697,13 @@ int corr_create(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t nB, 
     int rc = guarded(nullptr, [&] {
         if (!out) fail(CORR_EINVAL, "out is NULL");
         *out = nullptr;
-        if (!grid) fail(CORR_EINVAL, "grid is NULL");
-        validate_balls(A, nA, "A");
-        validate_balls(B, nB, "B");
-        const corr_grid& gr = *grid;
-        if (gr.n != 16 && gr.n != 32 && gr.n != 64 && gr.n != 128 && gr.n != 256)
-            fail(CORR_EUNSUPPORTED, "grid n = %d; supported: 16, 32, 64, 128, 256", gr.n);
-        if (!std::isfinite(gr.box) || !(gr.box > 0)) fail(CORR_EINVAL, "grid box must be finite and > 0");
-        for (int d = 0; d < 3; ++d)
-            if (!std::isfinite(gr.origin[d])) fail(CORR_EINVAL, "grid origin must be finite");
-        double sigma = gr.sigma == 0 ? 2.0 : gr.sigma;
-        if (sigma != 2.0) fail(CORR_EUNSUPPORTED, "sigma = %g; supported: 2", sigma);
-        int w = gr.kb_width == 0 ? 8 : gr.kb_width;
-        if (w < 4 || w > 12 || (w & 1)) fail(CORR_EUNSUPPORTED, "kb_width = %d; supported: even 4..12", w);
-        double tol = gr.tol == 0 ? 1e-6 : gr.tol;
-        if (!std::isfinite(tol) || !(tol > 0) || tol >= 1) fail(CORR_EINVAL, "tol must be in (0, 1)");
-        if (gr.flags & ~CORR_DETERMINISTIC) fail(CORR_EINVAL, "unknown flag bits 0x%x", gr.flags);
-        if (gr.batch < 0 || gr.batch > 256) fail(CORR_EINVAL, "batch = %d; allowed 0..256", gr.batch);
-
-        c = new corr_ctx();
-        hip_check(hipGetDevice(&c->device), "hipGetDevice");
-        c->stream = static_cast<hipStream_t>(hip_stream);
-        c->box = gr.box;
-        std::memcpy(c->origin, gr.origin, sizeof c->origin);
-        c->sigma = sigma;
-        c->tol = tol;
-        c->flags = gr.flags;
-        Geom& g = c->g;
-        g.n = gr.n;
-        g.m = (int)std::lround(sigma * gr.n);
-        g.w = w;
-        g.half = gr.n / 2;
-        g.m2n = 3 * (g.half - 1) * (g.half - 1) + 1;
-        // window shape for oversampling sigma (Beatty, Nishimura & Pauly, 2005)
-        double beta = M_PI * std::sqrt((w / sigma) * (w / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8);
-        g.beta = (float)beta;
-        g.inv_i0beta = (float)(1.0 / std::cyl_bessel_i(0.0, (double)g.beta));
-        g.inv_hf = g.m / gr.box;
-        const double dk = 2.0 * M_PI / gr.box;
-
-        setup_shape(c, c->A, A, nA, dk);
-        setup_shape(c, c->B, B, nB, dk);
-        c->qmax = std::max(c->A.ex.q, c->B.ex.q);
-
-        // batch: rotations per pass, bounded by a 4 GiB workspace
-        c->nkmax = std::max<int64_t>(std::max(nA, nB), 1);
-        const size_t nblk = (size_t)corr::bin_blocks(c->nkmax);
-        size_t per_slot = sizeof(float) * buf0_floats(c) + sizeof(float2) * buf1_float2(c) +
-                          (size_t)c->nkmax * (12 + 24 * w + 4 * c->qmax) + sizeof(int) * ((size_t)g.m * nblk + g.m + 1);
-        int batch = gr.batch;
-        if (batch == 0) batch = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 30) / per_slot));
-        c->batch = batch;
-
-        hipDeviceProp_t prop;
-        hip_check(hipGetDeviceProperties(&prop, c->device), "hipGetDeviceProperties");
-        // largest dynamic LDS any stage asks for
-        {
-            size_t need = corr::max_lds_bytes(g, c->qmax);
-            if (need > prop.sharedMemPerBlock)
-                fail(CORR_EUNSUPPORTED, "grid n = %d needs %zu bytes of LDS per workgroup; device has %zu", g.n, need,
-                     (size_t)prop.sharedMemPerBlock);
-        }
-
-        // tables
-        std::vector<float2> tw(g.m);
-        for (int j = 0; j < g.m; ++j) tw[j] = make_float2((float)std::cos(2 * M_PI * j / g.m), (float)-std::sin(2 * M_PI * j / g.m));
-        c->twm = c->mem.alloc<float2>(g.m);
-        upload(c->twm, tw.data(), sizeof(float2) * g.m, c->stream);
-        tw.resize(g.n);
-        for (int j = 0; j < g.n; ++j) tw[j] = make_float2((float)std::cos(2 * M_PI * j / g.n), (float)-std::sin(2 * M_PI * j / g.n));
-        c->twn = c->mem.alloc<float2>(g.n);
-        upload(c->twn, tw.data(), sizeof(float2) * g.n, c->stream);
-        c->deconv = c->mem.alloc<double>(g.n);
-        c->phase = c->mem.alloc<double2>((size_t)3 * g.n);
-        hip_check(corr::launch_deconv_tables(g, c->box, c->origin, c->deconv, c->phase, c->stream), "deconv tables");
-
-        upload_shape(c, c->A, A, dk);
-        upload_shape(c, c->B, B, dk);
-
-        c->fa = c->mem.alloc<float2>((size_t)g.n * g.n * g.half);
-        c->buf0 = c->mem.alloc<float>((size_t)batch * buf0_floats(c));
-        c->buf1 = c->mem.alloc<float2>((size_t)batch * buf1_float2(c));
-        c->cell = c->mem.alloc<int>((size_t)batch * c->nkmax);
-        c->kbw = c->mem.alloc<float>((size_t)batch * c->nkmax * 3 * w);
-        c->rank = c->mem.alloc<int>((size_t)batch * c->nkmax);
-        c->scell = c->mem.alloc<int>((size_t)batch * c->nkmax);
-        c->skbw = c->mem.alloc<float>((size_t)batch * c->nkmax * 3 * w);
-        c->swts = c->mem.alloc<float>((size_t)batch * c->nkmax * c->qmax);
-        c->counts = c->mem.alloc<int>((size_t)batch * g.m * nblk);
-        c->bin_start = c->mem.alloc<int>((size_t)batch * (g.m + 1));
-        c->quats = c->mem.alloc<double>((size_t)4 * batch);
-        c->pval = c->mem.alloc<float>((size_t)batch * corr::ifft_x_blocks(g));
-        c->pidx = c->mem.alloc<int>((size_t)batch * corr::ifft_x_blocks(g));
-        c->peak_tmp_v = c->mem.alloc<float>(batch);
-        c->peak_tmp_i = c->mem.alloc<int64_t>(batch);
-        hip_check(hipHostMalloc((void**)&c->host_quats, sizeof(double) * 4 * batch, hipHostMallocDefault), "hipHostMalloc");
-        hip_check(hipEventCreateWithFlags(&c->quat_done, hipEventDisableTiming), "hipEventCreate");
-        hip_check(hipEventRecord(c->quat_done, c->stream), "event");
-
+        c = plan_pair(A, nA, B, nB, grid, hip_stream, "");
+        const corr::WsReq r = ws_req(c);
+        int slots = grid->batch;
+        if (slots == 0) slots = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 30) / r.slot_bytes()));
+        c->ws = new corr::Workspace();
+        c->own_ws = true;
+        c->ws->allocate(slots, r, c->stream);
         prepare_a(c);
         *out = c;
     });
@@ -631,37 +725,7 @@ int corr_eval(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* scores
         g_thread_error = "corr_eval: NULL context";
         return CORR_EINVAL;
     }
-    return guarded(c, [&] {
-        if (n_rot < 0) fail(CORR_EINVAL, "n_rot < 0");
-        if ((peak_val_dev == nullptr) != (peak_idx_dev == nullptr))
-            fail(CORR_EINVAL, "peak_val_dev and peak_idx_dev must both be set or both be NULL");
-        validate_quats(quat_wxyz, n_rot);
-        const Geom& g = c->g;
-        const size_t n3 = (size_t)g.n * g.n * g.n;
-        const int nb = corr::ifft_x_blocks(g);
-        for (int64_t r0 = 0; r0 < n_rot; r0 += c->batch) {
-            int S = (int)std::min<int64_t>(c->batch, n_rot - r0);
-            stage_quats(c, quat_wxyz + 4 * r0, S);
-            run_spectrum_stages(c, c->B, c->quats, S);
-            stage(c, CORR_STAGE_FFT_Z_PRODUCT, "fft z product", [&] {
-                return corr::launch_fft_z_product(g, reinterpret_cast<float2*>(c->buf0), S, c->B.ex.q, c->B.vtab,
-                                                  c->phase, c->fa, c->buf1, c->twm, c->twn, c->stream);
-            });
-            stage(c, CORR_STAGE_IFFT_Y, "ifft y", [&] {
-                return corr::launch_ifft_y(g, c->buf1, S, reinterpret_cast<float2*>(c->buf0), c->twn, c->stream);
-            });
-            stage(c, CORR_STAGE_IFFT_X, "ifft x", [&] {
-                return corr::launch_ifft_x(g, reinterpret_cast<float2*>(c->buf0), S,
-                                           scores_dev ? scores_dev + (size_t)r0 * n3 : nullptr, c->pval, c->pidx,
-                                           c->twn, c->stream);
-            });
-            if (peak_val_dev)
-                stage(c, CORR_STAGE_PEAK, "peak", [&] {
-                    return corr::launch_peak_final(c->pval, c->pidx, S, nb, peak_val_dev + r0, peak_idx_dev + r0,
-                                                   c->stream);
-                });
-        }
-    });
+    return guarded(c, [&] { eval_impl(c, quat_wxyz, n_rot, scores_dev, peak_val_dev, peak_idx_dev); });
 }
 
 int corr_spectrum(corr_ctx* c, int32_t which, const double* quat_wxyz, float* out_dev) {
@@ -677,9 +741,9 @@ int corr_spectrum(corr_ctx* c, int32_t which, const double* quat_wxyz, float* ou
         validate_quats(q, 1);
         const Shape& s = which == 0 ? c->A : c->B;
         stage_quats(c, q, 1);
-        run_spectrum_stages(c, s, c->quats, 1);
+        run_spectrum_stages(c, s, c->ws->quats, 1);
         stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z spectrum", [&] {
-            return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->buf0), 1, s.ex.q, s.vtab, c->deconv,
+            return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->ws->buf0), 1, s.ex.q, s.vtab, c->deconv,
                                                reinterpret_cast<float2*>(out_dev), c->twm, c->stream);
         });
     });
@@ -697,8 +761,8 @@ int corr_info(const corr_ctx* c, corr_info_t* out) {
     out->q_b = c->B.ex.q;
     out->n_a = c->A.n;
     out->n_b = c->B.n;
-    out->batch = c->batch;
-    out->workspace_bytes = (int64_t)c->mem.bytes;
+    out->batch = c->ws->slots;
+    out->workspace_bytes = (int64_t)(c->mem.bytes + (c->own_ws ? c->ws->mem.bytes : 0));
     out->beta = c->g.beta;
     out->radius_err_a = c->A.ex.err;
     out->radius_err_b = c->B.ex.err;
@@ -739,6 +803,95 @@ int corr_profile_read(corr_ctx* c, double* ms, int64_t* launches, int32_t n_stag
         c->marks.clear();
     });
 }
+
+struct corr_batch {
+    hipStream_t stream = nullptr;
+    std::vector<corr_ctx*> pairs;
+    corr::Workspace ws;
+    std::string err = "no error";
+};
+
+int corr_batch_create(const corr_pair* pairs, int32_t n_pairs, int32_t slots, void* hip_stream, corr_batch** out) {
+    corr_batch* b = nullptr;
+    int rc = guarded(nullptr, [&] {
+        if (!out) fail(CORR_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (n_pairs < 1 || !pairs) fail(CORR_EINVAL, "need n_pairs >= 1 pairs");
+        if (slots < 0 || slots > 256) fail(CORR_EINVAL, "slots = %d; allowed 0..256", slots);
+        b = new corr_batch();
+        b->stream = static_cast<hipStream_t>(hip_stream);
+        corr::WsReq r;
+        for (int p = 0; p < n_pairs; ++p) {
+            char who[64];
+            snprintf(who, sizeof who, "pair %d: ", p);
+            const corr_pair& pr = pairs[p];
+            b->pairs.push_back(plan_pair(pr.A, pr.nA, pr.B, pr.nB, &pr.grid, hip_stream, who));
+            r.merge(ws_req(b->pairs.back()));
+        }
+        if (slots == 0) slots = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 30) / r.slot_bytes()));
+        b->ws.allocate(slots, r, b->stream);
+        for (corr_ctx* c : b->pairs) {
+            c->ws = &b->ws;
+            c->own_ws = false;
+            prepare_a(c);
+        }
+        *out = b;
+    });
+    if (rc != CORR_OK && b) corr_batch_destroy(b);
+    return rc;
+}
+
+int corr_batch_eval(corr_batch* b, const double* quat_wxyz, const int64_t* rot_offsets, float* scores_dev,
+                    const int64_t* score_offsets, float* peak_val_dev, int64_t* peak_idx_dev) {
+    if (!b) {
+        g_thread_error = "corr_batch_eval: NULL batch";
+        return CORR_EINVAL;
+    }
+    corr_ctx* cur = nullptr;
+    int rc = guarded(nullptr, [&] {
+        const int np = (int)b->pairs.size();
+        if (!rot_offsets) fail(CORR_EINVAL, "rot_offsets is NULL");
+        if (rot_offsets[0] != 0) fail(CORR_EINVAL, "rot_offsets[0] must be 0");
+        for (int p = 0; p < np; ++p)
+            if (rot_offsets[p + 1] < rot_offsets[p]) fail(CORR_EINVAL, "rot_offsets must not decrease (pair %d)", p);
+        if ((peak_val_dev == nullptr) != (peak_idx_dev == nullptr))
+            fail(CORR_EINVAL, "peak_val_dev and peak_idx_dev must both be set or both be NULL");
+        validate_quats(quat_wxyz, rot_offsets[np]);
+        int64_t packed = 0;
+        for (int p = 0; p < np; ++p) {
+            corr_ctx* c = b->pairs[p];
+            cur = c;
+            const int64_t r0 = rot_offsets[p], nr = rot_offsets[p + 1] - rot_offsets[p];
+            const int64_t n3 = (int64_t)c->g.n * c->g.n * c->g.n;
+            float* sc = nullptr;
+            if (scores_dev) sc = scores_dev + (score_offsets ? score_offsets[p] : packed);
+            packed += nr * n3;
+            eval_impl(c, quat_wxyz + 4 * r0, nr, sc, peak_val_dev ? peak_val_dev + r0 : nullptr,
+                      peak_idx_dev ? peak_idx_dev + r0 : nullptr);
+        }
+    });
+    if (rc != CORR_OK) b->err = cur && cur->err != "no error" ? cur->err : g_thread_error;
+    return rc;
+}
+
+int corr_batch_info(const corr_batch* b, int32_t pair, corr_info_t* out) {
+    if (!b || pair < 0 || pair >= (int32_t)b->pairs.size()) {
+        g_thread_error = "corr_batch_info: bad batch or pair index";
+        return CORR_EINVAL;
+    }
+    return corr_info(b->pairs[pair], out);
+}
+
+int corr_batch_destroy(corr_batch* b) {
+    if (!b) return CORR_OK;
+    (void)hipStreamSynchronize(b->stream);
+    for (corr_ctx* c : b->pairs) destroy_ctx(c);
+    b->ws.release();
+    delete b;
+    return CORR_OK;
+}
+
+const char* corr_batch_last_error(const corr_batch* b) { return b ? b->err.c_str() : g_thread_error.c_str(); }
 
 int corr_destroy(corr_ctx* c) {
     destroy_ctx(c);

@@ -31,14 +31,17 @@ def test_header_declares_the_entry_points():
     for n in pkg.EXPORTS:
         assert n in names
     assert set(names) <= set(pkg.EXPORTS)
+    pnames = _declared("prop.h")
+    assert set(pnames) == set(pkg.PROP_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol(lib):
     out = subprocess.run(["nm", "-D", "--defined-only", pkg.LIB_PATH], capture_output=True, text=True, check=True).stdout
     exported = set(re.findall(r"\sT\s+(\w+)$", out, flags=re.M))
-    for name in _declared("corr.h"):
-        assert name in exported, name
-        assert hasattr(lib, name)
+    for header in ("corr.h", "prop.h"):
+        for name in _declared(header):
+            assert name in exported, name
+            assert hasattr(lib, name)
 
 
 def _grid(**kw):
@@ -108,3 +111,44 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.corr_info(None, None) == pkg.CORR_EINVAL
     assert lib.corr_destroy(None) == pkg.CORR_OK
     assert "NULL" in pkg.corr_last_error(None)
+
+
+def test_prop_rejects_bad_arguments(lib):
+    plib = pkg._prop_lib()
+    out = ctypes.c_void_p()
+    for batch in (0, 32, 100, 16384):
+        assert plib.prop_create(batch, 1, None, ctypes.byref(out)) == pkg.CORR_EINVAL
+        assert not out.value
+    assert plib.prop_create(64, 1, None, None) == pkg.CORR_EINVAL
+    assert plib.prop_train(None, None, None, 0, 1, 0.01, None) == pkg.CORR_EINVAL
+    assert plib.prop_rank(None, None, 0, 1, None) == pkg.CORR_EINVAL
+    assert plib.prop_destroy(None) == pkg.CORR_OK
+    assert len(pkg.prop_last_error(None)) > 0
+
+
+def test_unpack_params_layout():
+    flat = np.arange(pkg.PROP_NPARAMS, dtype=np.float64)
+    layers = pkg.unpack_params(flat)
+    assert [W.shape for W, _ in layers] == [(160, 256), (256, 256), (256, 256), (256, 1)]
+    assert layers[0][1][0] == 160 * 256 and layers[3][1][0] == pkg.PROP_NPARAMS - 1
+
+
+def test_batch_rejects_bad_arguments(lib):
+    blib = pkg._batch_lib()
+    out = ctypes.c_void_p()
+    assert blib.corr_batch_create(None, 0, 0, None, ctypes.byref(out)) == pkg.CORR_EINVAL
+    A = np.ascontiguousarray(GOOD)
+    bad = pkg.make_grid(48, 2.0, (-1, -1, -1))
+    arr = (pkg.corr_pair * 2)()
+    for i, g in enumerate((pkg.make_grid(32, 2.0, (-1, -1, -1)), bad)):
+        arr[i].A = A.ctypes.data
+        arr[i].nA = 2
+        arr[i].B = A.ctypes.data
+        arr[i].nB = 2
+        arr[i].grid = g
+    # pair 1 has an unsupported grid: rejected before any device work, and named
+    arr[0].grid = bad
+    assert blib.corr_batch_create(arr, 2, 0, None, ctypes.byref(out)) == pkg.CORR_EUNSUPPORTED
+    assert "pair 0" in pkg._batch_lib().corr_batch_last_error(None).decode()
+    assert blib.corr_batch_eval(None, None, None, None, None, None, None) == pkg.CORR_EINVAL
+    assert blib.corr_batch_destroy(None) == pkg.CORR_OK
