@@ -47,8 +47,9 @@ extern "C" {
 #define CORR_EUNSUPPORTED -4  /* valid but unsupported parameter (grid size, ...)  */
 
 /* flags of corr_grid */
-#define CORR_DETERMINISTIC 1u /* bit-reproducible results; every path already is:
-                                 spreading uses no floating-point atomics           */
+#define CORR_DETERMINISTIC 1u /* bit-reproducible results; accepted for clarity: every
+                                 run already is (spreading sums are exact 64-bit
+                                 fixed point, independent of scheduling)           */
 
 typedef struct {
     double x, y, z; /* centre                */

@@ -481,8 +481,8 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
                                      c->ws->skbw, c->ws->swts, c->stream);
     });
     stage(c, CORR_STAGE_SPREAD_FFT_X, "spread + fft x", [&] {
-        return corr::launch_spread_fftx(g, S, s.n, c->ws->bin_start, c->ws->scell, c->ws->skbw, c->ws->swts, q, s.fix_scale, c->ws->buf1,
-                                        c->twm, c->stream);
+        return corr::launch_spread_fftx(g, S, s.n, c->ws->bin_start, c->ws->scell, c->ws->skbw, c->ws->swts, q,
+                                        s.fix_scale, c->ws->buf1, c->twm, c->stream);
     });
     stage(c, CORR_STAGE_FFT_Y, "fft y", [&] {
         return corr::launch_fft_y(g, c->ws->buf1, S * q, reinterpret_cast<float2*>(c->ws->buf0), c->twm, c->stream);

@@ -41,7 +41,8 @@ hipError_t launch_bin_sort(const Geom& g, int S, int64_t nk, int q, const int* d
                            float* d_skbw, float* d_swts, hipStream_t st);
 // a1 + a2 (x): gather-spreading of the sorted knots fused with the x transform;
 // writes [S][q][z][y][mx] without a spreading grid in HBM.
-// fix_scale: power of two with fix_scale * sum_i max_c |wts[c][i]| <= 2^61.
+// Sums are exact 64-bit fixed point; fix_scale is a power of two with
+// fix_scale * sum_i max_c |wts[c][i]| <= 2^61.
 hipError_t launch_spread_fftx(const Geom& g, int S, int64_t nk, const int* d_bin_start, const int* d_scell,
                               const float* d_skbw, const float* d_swts, int q, float fix_scale, float2* d_out,
                               const float2* d_twm, hipStream_t st);

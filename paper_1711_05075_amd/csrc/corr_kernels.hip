@@ -85,57 +85,66 @@ __device__ __forceinline__ void dft8(float2* v) {
 // Column FFT engine.  A workgroup transforms COLS columns of LEN points held in
 // LDS; element (i, c) lives at buf[i * SI + c * SC] ("LINES" layout: each
 // column contiguous with a padded stride, otherwise columns interleaved).  The
-// transform is a sequence of Stockham autosort passes of radix 8 (then 4 or 2):
-// every thread does whole butterflies in registers, reading its inputs from one
-// buffer and writing its outputs to the other.  All sizes are compile-time
-// powers of two.  tw[j] = exp(-2 pi i j / LEN) is an LDS table.
+// transform is a sequence of Stockham autosort passes of radix 8 (then 4 or 2)
+// done in place: in every pass each thread first reads the inputs of all its
+// butterflies into registers, the workgroup synchronises, and the outputs are
+// written back over the same buffer.  All sizes are compile-time powers of
+// two.  tw[j] = exp(-2 pi i j / LEN) is an LDS table.
 // ---------------------------------------------------------------------------
 template <int LEN, int NS, int SIGN, int COLS, int SI, int SC>
-__device__ __forceinline__ float2* fft_passes(float2* a, float2* b, const float2* tw) {
-    if constexpr (NS >= LEN) {
-        return a;
-    } else {
+__device__ __forceinline__ void fft_passes(float2* a, const float2* tw) {
+    if constexpr (NS < LEN) {
         constexpr int REM = LEN / NS;
         constexpr int R = REM >= 8 ? 8 : REM;
         constexpr int NB = LEN / R;
         constexpr int TWS = LEN / (NS * R);
         constexpr int WORK = NB * COLS;
+        constexpr int NBF = (WORK + kThreads - 1) / kThreads;
+        float2 v[NBF][R];
 #pragma unroll
-        for (int t0 = 0; t0 < WORK; t0 += kThreads) {
-            const int t = t0 + (int)threadIdx.x;
+        for (int u = 0; u < NBF; ++u) {
+            const int t = u * kThreads + (int)threadIdx.x;
             if (WORK % kThreads == 0 || t < WORK) {
                 const int c = t % COLS, j = t / COLS;
                 const int k = j % NS;
-                float2 v[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[r] = a[(j + r * NB) * SI + c * SC];
+                for (int r = 0; r < R; ++r) v[u][r] = a[(j + r * NB) * SI + c * SC];
                 if constexpr (NS > 1) {
 #pragma unroll
                     for (int r = 1; r < R; ++r) {
                         float2 w = tw[r * k * TWS];
                         if constexpr (SIGN > 0) w.y = -w.y;
-                        v[r] = cmul(v[r], w);
+                        v[u][r] = cmul(v[u][r], w);
                     }
                 }
-                if constexpr (R == 8) dft8<SIGN>(v);
-                else if constexpr (R == 4) dft4<SIGN>(v[0], v[1], v[2], v[3]);
-                else dft2<SIGN>(v);
-                const int o = (j / NS) * NS * R + k;
-#pragma unroll
-                for (int r = 0; r < R; ++r) b[(o + r * NS) * SI + c * SC] = v[r];
+                if constexpr (R == 8) dft8<SIGN>(v[u]);
+                else if constexpr (R == 4) dft4<SIGN>(v[u][0], v[u][1], v[u][2], v[u][3]);
+                else dft2<SIGN>(v[u]);
             }
         }
         __syncthreads();
-        return fft_passes<LEN, NS * R, SIGN, COLS, SI, SC>(b, a, tw);
+#pragma unroll
+        for (int u = 0; u < NBF; ++u) {
+            const int t = u * kThreads + (int)threadIdx.x;
+            if (WORK % kThreads == 0 || t < WORK) {
+                const int c = t % COLS, j = t / COLS;
+                const int k = j % NS;
+                const int o = (j / NS) * NS * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) a[(o + r * NS) * SI + c * SC] = v[u][r];
+            }
+        }
+        __syncthreads();
+        fft_passes<LEN, NS * R, SIGN, COLS, SI, SC>(a, tw);
     }
 }
 
-// Unnormalised DFT sum_i x_i exp(SIGN 2 pi i i s / LEN) of every column; a and
-// b are ping-pong buffers and the returned pointer holds the result.  Entered by
-// the whole workgroup once the input in `a` and the table are visible.
+// Unnormalised DFT sum_i x_i exp(SIGN 2 pi i i s / LEN) of every column, in
+// place.  Entered by the whole workgroup once the input in `a` and the table
+// are visible; the result is visible to the whole workgroup on return.
 template <int LEN, int SIGN, int COLS, bool LINES>
-__device__ __forceinline__ float2* fft_cols(float2* a, float2* b, const float2* tw) {
-    return fft_passes<LEN, 1, SIGN, COLS, (LINES ? 1 : COLS), (LINES ? LEN + 1 : 1)>(a, b, tw);
+__device__ __forceinline__ void fft_cols(float2* a, const float2* tw) {
+    fft_passes<LEN, 1, SIGN, COLS, (LINES ? 1 : COLS), (LINES ? LEN + 1 : 1)>(a, tw);
 }
 
 template <int LEN>
@@ -353,10 +362,10 @@ __global__ __launch_bounds__(kBinBlock) void k_bin_scatter(const int* __restrict
 // The knots that reach z row z0 are those of z-cells z0-w/2 .. z0+w/2-1: one or
 // two contiguous ranges of the sorted order.  Those whose window also reaches
 // the tile's y rows are compacted in order (wave ballots + a block scan) and
-// staged in LDS with their window and component weights.  Each wave applies one
-// staged knot at a time, a lane per window point, adding into 64-bit fixed-point
-// sums with LDS integer atomics: integer addition is exact and associative, so
-// the result does not depend on scheduling.  The fixed-point scale is a power of
+// staged in LDS with their window and component weights.  Each wave applies
+// staged knots, a lane per window point, adding into 64-bit fixed-point sums
+// with LDS integer atomics: integer addition is exact and associative, so the
+// result does not depend on scheduling.  The fixed-point scale is a power of
 // two chosen per shape so that no sum can overflow.
 // ---------------------------------------------------------------------------
 struct SpreadStage {
@@ -420,10 +429,21 @@ struct SpreadShape {
     static constexpr int TY = cmin<2048 / M, M>();
     static constexpr int SC = M + 1;
     static constexpr int NPTS = TY * M;
-    // fixed-point sums (16 B per point, reused as the FFT's second buffer), the
-    // padded FFT input, the twiddle table; the staged knots follow
-    static constexpr size_t FIXED = 16 * (size_t)NPTS + 8 * (size_t)TY * SC + 8 * (size_t)M;
+    // fixed-point sums: a plane of int64 real parts and one of imaginary
+    // parts, lines padded by 8 words so that consecutive lines of a window use
+    // the two different halves of the LDS banks
+    static constexpr int LS = M + 8;  // int64 words per line
+    // fixed-point sums, the padded FFT input, the twiddle table; the staged
+    // knots follow
+    static constexpr size_t FIXED = 16 * (size_t)TY * LS + 8 * (size_t)TY * SC + 8 * (size_t)M;
 };
+
+// Exact int64 -> double split (hi * 2^32 + lo), then one rounding to float.
+__device__ __forceinline__ float fixed_to_float(unsigned long long u, float inv) {
+    const long long x = (long long)u;
+    const double d = fma((double)(int)(x >> 32), 4294967296.0, (double)(unsigned)(x & 0xffffffffull));
+    return (float)(d * (double)inv);
+}
 
 template <int M>
 __global__ __launch_bounds__(kThreads) void k_spread_fftx(const int* __restrict__ bin_start,
@@ -432,12 +452,14 @@ __global__ __launch_bounds__(kThreads) void k_spread_fftx(const int* __restrict_
                                                           int cap, float fix_scale, float fix_inv,
                                                           float2* __restrict__ out, const float2* __restrict__ twm) {
     constexpr int H = M / 4;  // half of the n = M/2 kept modes along x
-    constexpr int TY = SpreadShape<M>::TY, SC = SpreadShape<M>::SC, NPTS = SpreadShape<M>::NPTS;
+    using SS = SpreadShape<M>;
+    constexpr int TY = SS::TY, SC = SS::SC, NPTS = SS::NPTS, LS = SS::LS;
+    constexpr int NW = kThreads / 64;
+    constexpr int U = 2;  // staged knots in flight per wave
     extern __shared__ float2 lds[];
-    __shared__ int wave_tot[kThreads / 64];
-    unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds);
-    float2* b = lds;
-    float2* a = lds + 2 * NPTS;
+    __shared__ int wave_tot[NW];
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds);  // [2][TY][LS]
+    float2* a = lds + 2 * TY * LS;
     float2* twl = a + TY * SC;
     SpreadStage st;
     st.cell = reinterpret_cast<int*>(twl + M);
@@ -450,6 +472,7 @@ __global__ __launch_bounds__(kThreads) void k_spread_fftx(const int* __restrict_
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int dmul = (65536 + w - 1) / w;  // t / w for t < w*w by a multiply
     load_table<M>(twl, twm);
+    for (int t = threadIdx.x; t < 2 * TY * LS; t += kThreads) acc[t] = 0ull;
     const int* bs = bin_start + (size_t)s * (M + 1);
     const int zlo = z0 - w / 2, zhi = z0 + lo;  // inclusive range of z-cells
     int r0a = 0, r0b = 0, r1a = 0, r1b = 0;    // an empty shape has no bins to read
@@ -468,48 +491,67 @@ __global__ __launch_bounds__(kThreads) void k_spread_fftx(const int* __restrict_
     const int nfilt = ncand ? stage_knots(sc_, kb_, wq_, q, M, w, TY, y0, z0, r0a, n0, r1a, ncand, 0, cap, st, wave_tot)
                             : 0;
     const int rounds = (nfilt + cap - 1) / cap;
+    __syncthreads();
     for (int cp = 0; cp < q; cp += 2) {
-        for (int t = threadIdx.x; t < 2 * NPTS; t += kThreads) acc[t] = 0ull;
-        __syncthreads();
         for (int r = 0; r < rounds; ++r) {
             if (rounds > 1 && (r > 0 || cp > 0))
                 stage_knots(sc_, kb_, wq_, q, M, w, TY, y0, z0, r0a, n0, r1a, ncand, r * cap, cap, st, wave_tot);
             const int nst = min(cap, nfilt - r * cap);
-            for (int i = wave; i < nst; i += kThreads / 64) {
-                const int packed = st.cell[i];
-                const int cx = packed & 1023, cy = (packed >> 10) & 1023;
-                const int ry = (cy - lo - y0 + 2 * M) & (M - 1);
-                const float wz = st.wz[i] * fix_scale;
-                const float c0 = st.wq[i * q + cp] * wz;
-                const float c1 = (cp + 1 < q) ? st.wq[i * q + cp + 1] * wz : 0.0f;
-                for (int t = lane; t < w * w; t += 64) {
+            // each wave takes U staged knots at a time, a lane per window point;
+            // the reads of all U are issued before their atomic adds
+            for (int i0 = wave; i0 < nst; i0 += U * NW) {
+                for (int t0 = 0; t0 < w * w; t0 += 64) {
+                    const int t = t0 + lane;
                     const int ddy = (t * dmul) >> 16, ddx = t - ddy * w;
-                    const int l = (ry + ddy) & (M - 1);
-                    if (l < TY) {
-                        const int x = (cx - lo + ddx + M) & (M - 1);
-                        const float v = st.wy[i * w + ddy] * st.wx[i * w + ddx];
-                        unsigned long long* e = acc + 2 * (l * M + x);
-                        atomicAdd(e, (unsigned long long)__float2ll_rn(c0 * v));
-                        atomicAdd(e + 1, (unsigned long long)__float2ll_rn(c1 * v));
+                    int off[U];
+                    float v0[U], v1[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int i = i0 + u * NW;
+                        off[u] = -1;
+                        v0[u] = v1[u] = 0.f;
+                        if (i < nst && t < w * w) {
+                            const int packed = st.cell[i];
+                            const int cx = packed & 1023, cy = (packed >> 10) & 1023;
+                            const int l = (cy - lo - y0 + ddy + 2 * M) & (M - 1);
+                            if (l < TY) {
+                                const int x = (cx - lo + ddx + M) & (M - 1);
+                                const float v = st.wy[i * w + ddy] * st.wx[i * w + ddx] * st.wz[i] * fix_scale;
+                                v0[u] = st.wq[i * q + cp] * v;
+                                v1[u] = (cp + 1 < q) ? st.wq[i * q + cp + 1] * v : 0.0f;
+                                off[u] = l * LS + x;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (off[u] < 0) continue;
+                        atomicAdd(acc + off[u], (unsigned long long)__float2ll_rn(v0[u]));
+                        atomicAdd(acc + TY * LS + off[u], (unsigned long long)__float2ll_rn(v1[u]));
                     }
                 }
             }
             __syncthreads();
         }
+        // sums -> FFT input, clearing the sums for the next component pair
         for (int t = threadIdx.x; t < NPTS; t += kThreads) {
             const int l = t / M, x = t % M;
-            a[l * SC + x] = make_float2((float)(long long)acc[2 * t] * fix_inv, (float)(long long)acc[2 * t + 1] * fix_inv);
+            unsigned long long* e = acc + l * LS + x;
+            const unsigned long long re = e[0], im = e[TY * LS];
+            e[0] = 0ull;
+            e[TY * LS] = 0ull;
+            a[l * SC + x] = make_float2(fixed_to_float(re, fix_inv), fixed_to_float(im, fix_inv));
         }
         __syncthreads();
-        float2* res = fft_cols<M, -1, TY, true>(a, b, twl);
+        fft_cols<M, -1, TY, true>(a, twl);
         constexpr int PER = TY * H;
         for (int t = threadIdx.x; t < 2 * PER; t += kThreads) {
             const int comp = t >= PER;
             const int r = t - comp * PER;
             const int l = r / H, mm = r % H;
             if (cp + comp >= q) continue;
-            const float2 z1 = res[l * SC + mm];
-            const float2 z2 = res[l * SC + ((M - mm) & (M - 1))];
+            const float2 z1 = a[l * SC + mm];
+            const float2 z2 = a[l * SC + ((M - mm) & (M - 1))];
             const float2 o = comp ? make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x))
                                   : make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
             out[((((size_t)s * q + cp + comp) * M + z0) * M + y0 + l) * H + mm] = o;
@@ -542,15 +584,15 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ i
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS;
     extern __shared__ float2 lds[];
     float2* a = lds;
-    float2* b = lds + M * COLS;
-    float2* twl = b + M * COLS;
+    float2* twl = a + M * COLS;
     load_table<M>(twl, twm);
     const int c0 = blockIdx.x * COLS;
     const size_t plane = (size_t)blockIdx.z * M + blockIdx.y;  // slab * M + z
     const float2* src = in + plane * M * H + c0;
     for (int t = threadIdx.x; t < M * COLS; t += kThreads) a[t] = src[(size_t)(t / COLS) * H + t % COLS];
     __syncthreads();
-    float2* res = fft_cols<M, -1, COLS, false>(a, b, twl);
+    fft_cols<M, -1, COLS, false>(a, twl);
+    const float2* res = a;
     float2* dst = out + plane * N * H + c0;
     for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
         const int o = t / COLS, c = t % COLS;
@@ -570,17 +612,34 @@ struct ZAcc {
 
 template <int M>
 __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int s, int q, int iy, int c0,
-                                             const float* __restrict__ vtab, int m2n, float2* a, float2* b,
+                                             const float* __restrict__ vtab, int m2n, float2* a,
                                              const float2* twl, float2 (&acc)[ZAcc<M>::PER]) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
+    constexpr int LD = (M * COLS + kThreads - 1) / kThreads;  // column values per thread
     const int my = iy < N / 2 ? iy : iy - N;
 #pragma unroll
     for (int k = 0; k < PER; ++k) acc[k] = make_float2(0.f, 0.f);
-    for (int c = 0; c < q; ++c) {
+    // component c's columns are read into registers while component c-1 is
+    // being transformed
+    float2 nxt[LD];
+    auto fetch = [&](int c) {
         const float2* src = in + (((size_t)s * q + c) * M) * N * H + (size_t)iy * H + c0;
-        for (int t = threadIdx.x; t < M * COLS; t += kThreads) a[t] = src[(size_t)(t / COLS) * N * H + t % COLS];
+#pragma unroll
+        for (int k = 0; k < LD; ++k) {
+            const int t = k * kThreads + (int)threadIdx.x;
+            if ((M * COLS) % kThreads == 0 || t < M * COLS) nxt[k] = src[(size_t)(t / COLS) * N * H + t % COLS];
+        }
+    };
+    fetch(0);
+    for (int c = 0; c < q; ++c) {
+#pragma unroll
+        for (int k = 0; k < LD; ++k) {
+            const int t = k * kThreads + (int)threadIdx.x;
+            if ((M * COLS) % kThreads == 0 || t < M * COLS) a[t] = nxt[k];
+        }
+        if (c + 1 < q) fetch(c + 1);
         __syncthreads();
-        const float2* res = fft_cols<M, -1, COLS, false>(a, b, twl);
+        fft_cols<M, -1, COLS, false>(a, twl);
         const float* vt = vtab + (size_t)c * m2n;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
@@ -591,7 +650,7 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
                 if (si >= 0) {
                     const int mz = o < N / 2 ? o : o - N, mx = c0 + cc;
                     const float v = vt[mx * mx + my * my + mz * mz];
-                    const float2 g = res[si * COLS + cc];
+                    const float2 g = a[si * COLS + cc];
                     acc[k].x += v * g.x;
                     acc[k].y += v * g.y;
                 }
@@ -610,8 +669,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __res
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
     extern __shared__ float2 lds[];
     float2* a = lds;
-    float2* b = a + M * COLS;
-    float2* twl = b + M * COLS;
+    float2* twl = a + M * COLS;
     const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
     float2* dst = spec + (size_t)s * N * N * H + (size_t)iy * H + c0;
     if (iy == N / 2) {
@@ -621,7 +679,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __res
     }
     load_table<M>(twl, twm);
     float2 acc[PER];
-    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, b, twl, acc);
+    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, twl, acc);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int t = threadIdx.x + k * kThreads;
@@ -646,8 +704,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
     extern __shared__ float2 lds[];
     float2* a = lds;
-    float2* b = a + M * COLS;
-    float2* twl = b + M * COLS;
+    float2* twl = a + M * COLS;
     float2* twnl = twl + M;
     const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
     float2* dst = out + (size_t)s * N * N * H + (size_t)iy * H + c0;
@@ -659,7 +716,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
     load_table<M>(twl, twm);
     load_table<N>(twnl, twn);
     float2 acc[PER];
-    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, b, twl, acc);
+    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, twl, acc);
     const double2 py = phase[N + iy];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -674,8 +731,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
         }
     }
     __syncthreads();
-    const float2* res = fft_cols<N, 1, COLS, false>(a, b, twnl);
-    for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * N * H + t % COLS] = res[t];
+    fft_cols<N, 1, COLS, false>(a, twnl);
+    for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * N * H + t % COLS] = a[t];
 }
 
 // a5: inverse y over [s][z][my][mx] -> [s][z][y][mx].
@@ -685,17 +742,16 @@ __global__ __launch_bounds__(kThreads) void k_ifft_y(const float2* __restrict__ 
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ICOLS;
     extern __shared__ float2 lds[];
     float2* a = lds;
-    float2* b = lds + N * COLS;
-    float2* twl = b + N * COLS;
+    float2* twl = a + N * COLS;
     load_table<N>(twl, twn);
     const int c0 = blockIdx.x * COLS;
     const size_t plane = (size_t)blockIdx.z * N + blockIdx.y;
     const float2* src = in + plane * N * H + c0;
     for (int t = threadIdx.x; t < N * COLS; t += kThreads) a[t] = src[(size_t)(t / COLS) * H + t % COLS];
     __syncthreads();
-    const float2* res = fft_cols<N, 1, COLS, false>(a, b, twl);
+    fft_cols<N, 1, COLS, false>(a, twl);
     float2* dst = out + plane * N * H + c0;
-    for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * H + t % COLS] = res[t];
+    for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * H + t % COLS] = a[t];
 }
 
 // a5: inverse x, half-complex to real.  Two lines X1, X2 share one complex
@@ -712,8 +768,7 @@ __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ 
     __shared__ float red_v[kThreads];
     __shared__ int red_i[kThreads];
     float2* a = lds;
-    float2* b = lds + COLS * SC;
-    float2* twl = b + COLS * SC;
+    float2* twl = a + COLS * SC;
     load_table<N>(twl, twn);
     const int s = blockIdx.y;
     const size_t line0 = (size_t)blockIdx.x * 2 * COLS;
@@ -741,7 +796,8 @@ __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ 
         a[c * SC + mm] = z;
     }
     __syncthreads();
-    const float2* res = fft_cols<N, 1, COLS, true>(a, b, twl);
+    fft_cols<N, 1, COLS, true>(a, twl);
+    const float2* res = a;
     float best = -INFINITY;
     int besti = 0x7fffffff;
     float* dst = scores ? scores + (size_t)s * N * N * N + line0 * N : nullptr;
@@ -890,14 +946,14 @@ hipError_t launch_bin_sort(const Geom& g, int S, int64_t nk, int q, const int* d
 
 size_t max_lds_bytes(const Geom& g, int qmax) {
     size_t need = 0;
-    with_m(g.m, [&](auto mc) {
+    (void)with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         constexpr int N = M / 2;
         using C = ColShape<M>;
         need = std::max(need, spread_lds_t<M>(g.w, qmax));
-        need = std::max(need, sizeof(float2) * ((size_t)2 * M * C::COLS + M + N));
-        need = std::max(need, sizeof(float2) * ((size_t)2 * N * C::ICOLS + N));
-        need = std::max(need, sizeof(float2) * ((size_t)2 * C::XCOLS * (N + 1) + N) + 8 * kThreads);
+        need = std::max(need, sizeof(float2) * ((size_t)M * C::COLS + M + N));
+        need = std::max(need, sizeof(float2) * ((size_t)N * C::ICOLS + N));
+        need = std::max(need, sizeof(float2) * ((size_t)C::XCOLS * (N + 1) + N) + 8 * kThreads);
     });
     return need;
 }
@@ -921,7 +977,7 @@ hipError_t launch_fft_y(const Geom& g, const float2* d_in, int slabs, float2* d_
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
         hipLaunchKernelGGL(k_fft_y<M>, dim3(C::H / C::COLS, M, slabs), dim3(kThreads),
-                           sizeof(float2) * ((size_t)2 * M * C::COLS + M), st, d_in, d_out, d_twm);
+                           sizeof(float2) * ((size_t)M * C::COLS + M), st, d_in, d_out, d_twm);
     });
 }
 
@@ -931,7 +987,7 @@ hipError_t launch_fft_z_spectrum(const Geom& g, const float2* d_in, int S, int q
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
         hipLaunchKernelGGL(k_fft_z_spectrum<M>, dim3(C::H / C::COLS, C::N, S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)2 * M * C::COLS + M), st, d_in, q, d_vtab, g.m2n, d_deconv,
+                           sizeof(float2) * ((size_t)M * C::COLS + M), st, d_in, q, d_vtab, g.m2n, d_deconv,
                            d_spec, d_twm);
     });
 }
@@ -943,7 +999,7 @@ hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q,
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
         hipLaunchKernelGGL(k_fft_z_product<M>, dim3(C::H / C::COLS, C::N, S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)2 * M * C::COLS + M + C::N), st, d_in, q, d_vtab, g.m2n,
+                           sizeof(float2) * ((size_t)M * C::COLS + M + C::N), st, d_in, q, d_vtab, g.m2n,
                            d_phase, d_fa, d_out, d_twm, d_twn);
     });
 }
@@ -954,13 +1010,13 @@ hipError_t launch_ifft_y(const Geom& g, const float2* d_in, int S, float2* d_out
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
         hipLaunchKernelGGL(k_ifft_y<M>, dim3(C::H / C::ICOLS, C::N, S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)2 * C::N * C::ICOLS + C::N), st, d_in, d_out, d_twn);
+                           sizeof(float2) * ((size_t)C::N * C::ICOLS + C::N), st, d_in, d_out, d_twn);
     });
 }
 
 int ifft_x_blocks(const Geom& g) {
     int nb = 0;
-    with_m(g.m, [&](auto mc) {
+    (void)with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
         nb = C::N * C::N / (2 * C::XCOLS);
@@ -974,7 +1030,7 @@ hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scor
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
         hipLaunchKernelGGL(k_ifft_x<M>, dim3(C::N * C::N / (2 * C::XCOLS), S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)2 * C::XCOLS * (C::N + 1) + C::N), st, d_in, d_scores, d_pval,
+                           sizeof(float2) * ((size_t)C::XCOLS * (C::N + 1) + C::N), st, d_in, d_scores, d_pval,
                            d_pidx, d_twn);
     });
 }
