@@ -277,13 +277,16 @@ struct WsReq {
     size_t nk = 1, nkw = 1, nkq = 1;  // knots, knots*3w, knots*q per slot
     size_t counts = 1, bins = 1;    // m * sort blocks, m + 1 per slot
     size_t blocks = 1;              // inverse-x blocks per slot
+    size_t tiles = 1;               // spreading tiles (m z rows x y tiles) per slot
     void merge(const WsReq& o) {
         buf0 = std::max(buf0, o.buf0); buf1 = std::max(buf1, o.buf1);
         nk = std::max(nk, o.nk); nkw = std::max(nkw, o.nkw); nkq = std::max(nkq, o.nkq);
         counts = std::max(counts, o.counts); bins = std::max(bins, o.bins); blocks = std::max(blocks, o.blocks);
+        tiles = std::max(tiles, o.tiles);
     }
     size_t slot_bytes() const {
-        return 4 * buf0 + 8 * buf1 + 4 * (3 * nk + nkw + nkq) + 12 * nkw + 4 * (counts + bins) + 8 * blocks + 32;
+        return 4 * buf0 + 8 * buf1 + 4 * (3 * nk + nkw + nkq) + 12 * nkw + 4 * (counts + bins) + 8 * blocks + tiles +
+               32;
     }
 };
 
@@ -298,6 +301,7 @@ struct Workspace {
     int* rank = nullptr;           // [slots][nk] rank within its sort block and z-cell
     int* counts = nullptr;         // [slots][m][blocks] counts, then offsets
     int* bin_start = nullptr;      // [slots][m + 1]
+    unsigned char* tile_live = nullptr;  // [slots][m][y tiles] spreading tiles that some knot reaches
     int* scell = nullptr;          // [slots][nk] sorted by z-cell: packed cell
     float* skbw = nullptr;         // [slots][nk][3][w]              window weights
     float* swts = nullptr;         // [slots][nk][q]                 component weights
@@ -318,6 +322,7 @@ struct Workspace {
         rank = mem.alloc<int>(S * r.nk);
         counts = mem.alloc<int>(S * r.counts);
         bin_start = mem.alloc<int>(S * r.bins);
+        tile_live = mem.alloc<unsigned char>(S * r.tiles);
         scell = mem.alloc<int>(S * r.nk);
         skbw = mem.alloc<float>(S * r.nkw);
         swts = mem.alloc<float>(S * r.nkq);
@@ -469,6 +474,14 @@ void stage(corr_ctx* c, int id, const char* what, L&& launch) {
     }
 }
 
+corr::Occupancy occupancy(const corr_ctx* c, const Shape& s) {
+    corr::Occupancy o;
+    o.bin_start = c->ws->bin_start;
+    o.tile_live = c->ws->tile_live;
+    o.nk = s.n;
+    return o;
+}
+
 // Stages a0..a3 for S rotations of one shape; quats are device [S][4].
 void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int S) {
     const Geom& g = c->g;
@@ -481,11 +494,12 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
                                      c->ws->skbw, c->ws->swts, c->stream);
     });
     stage(c, CORR_STAGE_SPREAD_FFT_X, "spread + fft x", [&] {
-        return corr::launch_spread_fftx(g, S, s.n, c->ws->bin_start, c->ws->scell, c->ws->skbw, c->ws->swts, q,
+        return corr::launch_spread_fftx(g, S, occupancy(c, s), c->ws->scell, c->ws->skbw, c->ws->swts, q,
                                         s.fix_scale, c->ws->buf1, c->twm, c->stream);
     });
     stage(c, CORR_STAGE_FFT_Y, "fft y", [&] {
-        return corr::launch_fft_y(g, c->ws->buf1, S * q, reinterpret_cast<float2*>(c->ws->buf0), c->twm, c->stream);
+        return corr::launch_fft_y(g, S, q, occupancy(c, s), c->ws->buf1, reinterpret_cast<float2*>(c->ws->buf0),
+                                  c->twm, c->stream);
     });
 }
 
@@ -496,7 +510,8 @@ void prepare_a(corr_ctx* c) {
     stage_quats(c, ident, 1);
     run_spectrum_stages(c, c->A, c->ws->quats, 1);
     stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z (A)", [&] {
-        return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->ws->buf0), 1, c->A.ex.q, c->A.vtab, c->deconv,
+        return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->ws->buf0), 1, c->A.ex.q,
+                                           occupancy(c, c->A), c->A.vtab, c->deconv,
                                            c->fa, c->twm, c->stream);
     });
 }
@@ -613,6 +628,7 @@ corr::WsReq ws_req(const corr_ctx* c) {
     r.counts = (size_t)g.m * corr::bin_blocks(c->nkmax);
     r.bins = (size_t)g.m + 1;
     r.blocks = (size_t)corr::ifft_x_blocks(g);
+    r.tiles = (size_t)g.m * corr::spread_tiles(g);
     return r;
 }
 
@@ -631,7 +647,8 @@ void eval_impl(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* score
         stage_quats(c, quat_wxyz + 4 * r0, S);
         run_spectrum_stages(c, c->B, c->ws->quats, S);
         stage(c, CORR_STAGE_FFT_Z_PRODUCT, "fft z product", [&] {
-            return corr::launch_fft_z_product(g, reinterpret_cast<float2*>(c->ws->buf0), S, c->B.ex.q, c->B.vtab,
+            return corr::launch_fft_z_product(g, reinterpret_cast<float2*>(c->ws->buf0), S, c->B.ex.q,
+                                              occupancy(c, c->B), c->B.vtab,
                                               c->phase, c->fa, c->ws->buf1, c->twm, c->twn, c->stream);
         });
         stage(c, CORR_STAGE_IFFT_Y, "ifft y", [&] {
@@ -743,7 +760,8 @@ int corr_spectrum(corr_ctx* c, int32_t which, const double* quat_wxyz, float* ou
         stage_quats(c, q, 1);
         run_spectrum_stages(c, s, c->ws->quats, 1);
         stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z spectrum", [&] {
-            return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->ws->buf0), 1, s.ex.q, s.vtab, c->deconv,
+            return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->ws->buf0), 1, s.ex.q,
+                                               occupancy(c, s), s.vtab, c->deconv,
                                                reinterpret_cast<float2*>(out_dev), c->twm, c->stream);
         });
     });

@@ -21,6 +21,19 @@ struct Geom {
     double inv_hf = 0.0;      // 1 / spreading-cell size
 };
 
+// Which parts of a rotation's spreading grid hold knots.  z row z is live iff
+// some knot's z-window reaches it, which the z-sorted bin starts tell directly;
+// y tile t of a live row is live iff some knot's window reaches it, which the
+// spreading pass records in tile_live.  The passes after it read only live rows
+// and tiles: the others are zero by construction and are never written.
+struct Occupancy {
+    const int* bin_start = nullptr;         // [S][m + 1] first sorted knot of each z-cell
+    unsigned char* tile_live = nullptr;     // [S][m][spread_tiles(g)]
+    int64_t nk = 0;                         // knots per rotation
+};
+// y tiles per z row of the spreading pass.
+int spread_tiles(const Geom& g);
+
 // ---- table builders (FP64 on the device) ---------------------------------
 hipError_t launch_deconv_tables(const Geom& g, double box, const double origin[3],
                                 double* d_deconv /*[n]*/, double2* d_phase /*[3][n]*/,
@@ -43,23 +56,24 @@ hipError_t launch_bin_sort(const Geom& g, int S, int64_t nk, int q, const int* d
 // writes [S][q][z][y][mx] without a spreading grid in HBM.
 // Sums are exact 64-bit fixed point; fix_scale is a power of two with
 // fix_scale * sum_i max_c |wts[c][i]| <= 2^61.
-hipError_t launch_spread_fftx(const Geom& g, int S, int64_t nk, const int* d_bin_start, const int* d_scell,
+// Tiles that no knot reaches only record that in occ.tile_live.
+hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, const int* d_scell,
                               const float* d_skbw, const float* d_swts, int q, float fix_scale, float2* d_out,
                               const float2* d_twm, hipStream_t st);
 // Largest dynamic LDS any stage asks for.
 size_t max_lds_bytes(const Geom& g, int qmax);
-// a2: pruned forward y pass.
-hipError_t launch_fft_y(const Geom& g, const float2* d_in, int slabs, float2* d_out,
+// a2: pruned forward y pass of S rotations x q components (live rows only).
+hipError_t launch_fft_y(const Geom& g, int S, int q, const Occupancy& occ, const float2* d_in, float2* d_out,
                         const float2* d_twm, hipStream_t st);
 // a2 (z) + a3: z transform of every component, the radius-expansion sum with the
 // ball-transform table, and the deconvolution; writes the shape spectrum.
-hipError_t launch_fft_z_spectrum(const Geom& g, const float2* d_in, int S, int q,
+hipError_t launch_fft_z_spectrum(const Geom& g, const float2* d_in, int S, int q, const Occupancy& occ,
                                  const float* d_vtab, const double* d_deconv, float2* d_spec,
                                  const float2* d_twm, hipStream_t st);
 // a2 (z) + a3 + a4 + first inverse pass of a5: as above for the rotated shape,
 // times the fixed shape's spectrum, the origin phase and 1/L^3, then the
 // inverse z transform.
-hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q,
+hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q, const Occupancy& occ,
                                 const float* d_vtab, const double2* d_phase, const float2* d_fa,
                                 float2* d_out, const float2* d_twm, const float2* d_twn,
                                 hipStream_t st);

@@ -368,6 +368,32 @@ __global__ __launch_bounds__(kBinBlock) void k_bin_scatter(const int* __restrict
 // result does not depend on scheduling.  The fixed-point scale is a power of
 // two chosen per shape so that no sum can overflow.
 // ---------------------------------------------------------------------------
+// The knots whose z-windows reach z row z0 are those of z-cells
+// z0 - w/2 .. z0 + w/2 - 1 on the periodic axis: one or two ranges
+// [r0a, r0a + n0) and [r1a, ...) of the z-sorted order.  Returns the total.
+__device__ __forceinline__ int zrow_ranges(const int* __restrict__ bs, int64_t nk, int m, int w, int z0, int& r0a,
+                                           int& n0, int& r1a) {
+    const int zlo = z0 - w / 2, zhi = z0 + w / 2 - 1;  // inclusive range of z-cells
+    int a0 = 0, b0 = 0, a1 = 0, b1 = 0;                // an empty shape has no bins to read
+    if (nk == 0) {
+    } else if (zlo < 0) {
+        a0 = bs[zlo + m]; b0 = bs[m]; a1 = bs[0]; b1 = bs[zhi + 1];
+    } else if (zhi >= m) {
+        a0 = bs[zlo]; b0 = bs[m]; a1 = bs[0]; b1 = bs[zhi - m + 1];
+    } else {
+        a0 = bs[zlo]; b0 = bs[zhi + 1];
+    }
+    r0a = a0;
+    n0 = b0 - a0;
+    r1a = a1;
+    return n0 + (b1 - a1);
+}
+
+__device__ __forceinline__ bool zrow_live(const int* __restrict__ bs, int64_t nk, int m, int w, int z0) {
+    int r0a, n0, r1a;
+    return zrow_ranges(bs, nk, m, w, z0, r0a, n0, r1a) > 0;
+}
+
 struct SpreadStage {
     int* cell;    // [cap] packed cell
     float* wx;    // [cap][w]
@@ -447,6 +473,7 @@ __device__ __forceinline__ float fixed_to_float(unsigned long long u, float inv)
 
 template <int M>
 __global__ __launch_bounds__(kThreads) void k_spread_fftx(const int* __restrict__ bin_start,
+                                                          unsigned char* __restrict__ tile_live,
                                                           const int* __restrict__ scell, const float* __restrict__ skbw,
                                                           const float* __restrict__ swts, int64_t nk, int q, int w,
                                                           int cap, float fix_scale, float fix_inv,
@@ -471,25 +498,17 @@ __global__ __launch_bounds__(kThreads) void k_spread_fftx(const int* __restrict_
     const int lo = w / 2 - 1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int dmul = (65536 + w - 1) / w;  // t / w for t < w*w by a multiply
-    load_table<M>(twl, twm);
-    for (int t = threadIdx.x; t < 2 * TY * LS; t += kThreads) acc[t] = 0ull;
-    const int* bs = bin_start + (size_t)s * (M + 1);
-    const int zlo = z0 - w / 2, zhi = z0 + lo;  // inclusive range of z-cells
-    int r0a = 0, r0b = 0, r1a = 0, r1b = 0;    // an empty shape has no bins to read
-    if (nk == 0) {
-    } else if (zlo < 0) {
-        r0a = bs[zlo + M]; r0b = bs[M]; r1a = bs[0]; r1b = bs[zhi + 1];
-    } else if (zhi >= M) {
-        r0a = bs[zlo]; r0b = bs[M]; r1a = bs[0]; r1b = bs[zhi - M + 1];
-    } else {
-        r0a = bs[zlo]; r0b = bs[zhi + 1];
-    }
-    const int n0 = r0b - r0a, ncand = n0 + (r1b - r1a);
+    int r0a, n0, r1a;
+    const int ncand = zrow_ranges(bin_start + (size_t)s * (M + 1), nk, M, w, z0, r0a, n0, r1a);
     const int* sc_ = scell + (int64_t)s * nk;
     const float* kb_ = skbw + (int64_t)s * nk * 3 * w;
     const float* wq_ = swts + (int64_t)s * nk * q;
     const int nfilt = ncand ? stage_knots(sc_, kb_, wq_, q, M, w, TY, y0, z0, r0a, n0, r1a, ncand, 0, cap, st, wave_tot)
                             : 0;
+    if (threadIdx.x == 0) tile_live[((size_t)s * M + z0) * (M / TY) + blockIdx.x] = nfilt > 0;
+    if (nfilt == 0) return;  // the tile's spectrum is zero and is not written
+    load_table<M>(twl, twm);
+    for (int t = threadIdx.x; t < 2 * TY * LS; t += kThreads) acc[t] = 0ull;
     const int rounds = (nfilt + cap - 1) / cap;
     __syncthreads();
     for (int cp = 0; cp < q; cp += 2) {
@@ -577,19 +596,32 @@ struct ColShape {
     static constexpr int XCOLS = cmin<N * N / 2, 4096 / N>(); // inverse x pass (line pairs)
 };
 
-// a2: y pass over [slab][z][y][mx] -> [slab][z][my][mx], M points pruned to N.
+// a2: y pass over [slab][z][y][mx] -> [slab][z][my][mx], M points pruned to N,
+// slab = rotation * q + component.  Dead z rows are skipped (their output is
+// never read); rows of dead y tiles are zero.
 template <int M>
 __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ in, float2* __restrict__ out,
-                                                    const float2* __restrict__ twm) {
+                                                    const float2* __restrict__ twm, int q,
+                                                    const int* __restrict__ bin_start,
+                                                    const unsigned char* __restrict__ tile_live, int64_t nk, int w) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS;
+    constexpr int TY = SpreadShape<M>::TY, NT = M / TY;
     extern __shared__ float2 lds[];
+    __shared__ unsigned char live[NT];
     float2* a = lds;
     float2* twl = a + M * COLS;
+    const int z = blockIdx.y, s = blockIdx.z / q;
+    if (!zrow_live(bin_start + (size_t)s * (M + 1), nk, M, w, z)) return;
     load_table<M>(twl, twm);
+    for (int t = threadIdx.x; t < NT; t += kThreads) live[t] = tile_live[((size_t)s * M + z) * NT + t];
+    __syncthreads();
     const int c0 = blockIdx.x * COLS;
-    const size_t plane = (size_t)blockIdx.z * M + blockIdx.y;  // slab * M + z
+    const size_t plane = (size_t)blockIdx.z * M + z;  // slab * M + z
     const float2* src = in + plane * M * H + c0;
-    for (int t = threadIdx.x; t < M * COLS; t += kThreads) a[t] = src[(size_t)(t / COLS) * H + t % COLS];
+    for (int t = threadIdx.x; t < M * COLS; t += kThreads) {
+        const int y = t / COLS;
+        a[t] = live[y / TY] ? src[(size_t)y * H + t % COLS] : make_float2(0.f, 0.f);
+    }
     __syncthreads();
     fft_cols<M, -1, COLS, false>(a, twl);
     const float2* res = a;
@@ -610,10 +642,12 @@ struct ZAcc {
     static constexpr int PER = (N * COLS + kThreads - 1) / kThreads;
 };
 
+// zlive[z] (LDS) tells which z rows the y pass wrote; the others are zero.
 template <int M>
 __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int s, int q, int iy, int c0,
                                              const float* __restrict__ vtab, int m2n, float2* a,
-                                             const float2* twl, float2 (&acc)[ZAcc<M>::PER]) {
+                                             const float2* twl, const unsigned char* zlive,
+                                             float2 (&acc)[ZAcc<M>::PER]) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
     constexpr int LD = (M * COLS + kThreads - 1) / kThreads;  // column values per thread
     const int my = iy < N / 2 ? iy : iy - N;
@@ -627,7 +661,10 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
 #pragma unroll
         for (int k = 0; k < LD; ++k) {
             const int t = k * kThreads + (int)threadIdx.x;
-            if ((M * COLS) % kThreads == 0 || t < M * COLS) nxt[k] = src[(size_t)(t / COLS) * N * H + t % COLS];
+            if ((M * COLS) % kThreads == 0 || t < M * COLS) {
+                const int z = t / COLS;
+                nxt[k] = zlive[z] ? src[(size_t)z * N * H + t % COLS] : make_float2(0.f, 0.f);
+            }
         }
     };
     fetch(0);
@@ -665,9 +702,11 @@ template <int M>
 __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __restrict__ in, int q,
                                                              const float* __restrict__ vtab, int m2n,
                                                              const double* __restrict__ deconv,
-                                                             float2* __restrict__ spec, const float2* __restrict__ twm) {
+                                                             float2* __restrict__ spec, const float2* __restrict__ twm,
+                                                             const int* __restrict__ bin_start, int64_t nk, int w) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
     extern __shared__ float2 lds[];
+    __shared__ unsigned char zlive[M];
     float2* a = lds;
     float2* twl = a + M * COLS;
     const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
@@ -678,8 +717,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __res
         return;
     }
     load_table<M>(twl, twm);
+    for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live(bin_start + (size_t)s * (M + 1), nk, M, w, t);
+    __syncthreads();
     float2 acc[PER];
-    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, twl, acc);
+    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, twl, zlive, acc);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int t = threadIdx.x + k * kThreads;
@@ -700,9 +741,11 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
                                                             const double2* __restrict__ phase,
                                                             const float2* __restrict__ fa, float2* __restrict__ out,
                                                             const float2* __restrict__ twm,
-                                                            const float2* __restrict__ twn) {
+                                                            const float2* __restrict__ twn,
+                                                            const int* __restrict__ bin_start, int64_t nk, int w) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
     extern __shared__ float2 lds[];
+    __shared__ unsigned char zlive[M];
     float2* a = lds;
     float2* twl = a + M * COLS;
     float2* twnl = twl + M;
@@ -715,8 +758,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
     }
     load_table<M>(twl, twm);
     load_table<N>(twnl, twn);
+    for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live(bin_start + (size_t)s * (M + 1), nk, M, w, t);
+    __syncthreads();
     float2 acc[PER];
-    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, twl, acc);
+    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, twl, zlive, acc);
     const double2 py = phase[N + iy];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -958,49 +1003,61 @@ size_t max_lds_bytes(const Geom& g, int qmax) {
     return need;
 }
 
-hipError_t launch_spread_fftx(const Geom& g, int S, int64_t nk, const int* d_bin_start, const int* d_scell,
-                              const float* d_skbw, const float* d_swts, int q, float fix_scale, float2* d_out,
-                              const float2* d_twm, hipStream_t st) {
+int spread_tiles(const Geom& g) {
+    int t = 0;
+    (void)with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        t = M / SpreadShape<M>::TY;
+    });
+    return t;
+}
+
+hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, const int* d_scell, const float* d_skbw,
+                              const float* d_swts, int q, float fix_scale, float2* d_out, const float2* d_twm,
+                              hipStream_t st) {
     if (S == 0) return hipSuccess;
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         constexpr int TY = SpreadShape<M>::TY;
         hipLaunchKernelGGL(k_spread_fftx<M>, dim3(M / TY, M, S), dim3(kThreads), spread_lds_t<M>(g.w, q), st,
-                           d_bin_start, d_scell, d_skbw, d_swts, nk, q, g.w, spread_cap_t<M>(g.w, q), fix_scale,
-                           1.0f / fix_scale, d_out, d_twm);
+                           occ.bin_start, occ.tile_live, d_scell, d_skbw, d_swts, occ.nk, q, g.w,
+                           spread_cap_t<M>(g.w, q), fix_scale, 1.0f / fix_scale, d_out, d_twm);
     });
 }
 
-hipError_t launch_fft_y(const Geom& g, const float2* d_in, int slabs, float2* d_out, const float2* d_twm,
-                        hipStream_t st) {
+hipError_t launch_fft_y(const Geom& g, int S, int q, const Occupancy& occ, const float2* d_in, float2* d_out,
+                        const float2* d_twm, hipStream_t st) {
+    if (S == 0 || q == 0) return hipSuccess;
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
-        hipLaunchKernelGGL(k_fft_y<M>, dim3(C::H / C::COLS, M, slabs), dim3(kThreads),
-                           sizeof(float2) * ((size_t)M * C::COLS + M), st, d_in, d_out, d_twm);
+        hipLaunchKernelGGL(k_fft_y<M>, dim3(C::H / C::COLS, M, S * q), dim3(kThreads),
+                           sizeof(float2) * ((size_t)M * C::COLS + M), st, d_in, d_out, d_twm, q, occ.bin_start,
+                           occ.tile_live, occ.nk, g.w);
     });
 }
 
-hipError_t launch_fft_z_spectrum(const Geom& g, const float2* d_in, int S, int q, const float* d_vtab,
-                                 const double* d_deconv, float2* d_spec, const float2* d_twm, hipStream_t st) {
+hipError_t launch_fft_z_spectrum(const Geom& g, const float2* d_in, int S, int q, const Occupancy& occ,
+                                 const float* d_vtab, const double* d_deconv, float2* d_spec, const float2* d_twm,
+                                 hipStream_t st) {
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
         hipLaunchKernelGGL(k_fft_z_spectrum<M>, dim3(C::H / C::COLS, C::N, S), dim3(kThreads),
                            sizeof(float2) * ((size_t)M * C::COLS + M), st, d_in, q, d_vtab, g.m2n, d_deconv,
-                           d_spec, d_twm);
+                           d_spec, d_twm, occ.bin_start, occ.nk, g.w);
     });
 }
 
-hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q, const float* d_vtab,
-                                const double2* d_phase, const float2* d_fa, float2* d_out, const float2* d_twm,
-                                const float2* d_twn, hipStream_t st) {
+hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q, const Occupancy& occ,
+                                const float* d_vtab, const double2* d_phase, const float2* d_fa, float2* d_out,
+                                const float2* d_twm, const float2* d_twn, hipStream_t st) {
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
         hipLaunchKernelGGL(k_fft_z_product<M>, dim3(C::H / C::COLS, C::N, S), dim3(kThreads),
                            sizeof(float2) * ((size_t)M * C::COLS + M + C::N), st, d_in, q, d_vtab, g.m2n,
-                           d_phase, d_fa, d_out, d_twm, d_twn);
+                           d_phase, d_fa, d_out, d_twm, d_twn, occ.bin_start, occ.nk, g.w);
     });
 }
 
