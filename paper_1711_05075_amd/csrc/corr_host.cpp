@@ -275,7 +275,7 @@ namespace corr {
 struct WsReq {
     size_t buf0 = 0, buf1 = 0;      // floats, float2 per slot
     size_t nk = 1, nkw = 1, nkq = 1;  // knots, knots*3w, knots*q per slot
-    size_t counts = 1, bins = 1;    // m * sort blocks, m + 1 per slot
+    size_t counts = 1, bins = 1;    // sort keys, keys + 1 per slot
     size_t blocks = 1;              // inverse-x blocks per slot
     size_t tiles = 1;               // spreading tiles (m z rows x y tiles) per slot
     void merge(const WsReq& o) {
@@ -298,9 +298,9 @@ struct Workspace {
     float2* buf1 = nullptr;        // [slots][q][m^2][half] (after spread + x; reused after product)
     int* cell = nullptr;           // [slots][nk] packed cell of each knot
     float* kbw = nullptr;          // [slots][nk][3][w] window weights
-    int* rank = nullptr;           // [slots][nk] rank within its sort block and z-cell
-    int* counts = nullptr;         // [slots][m][blocks] counts, then offsets
-    int* bin_start = nullptr;      // [slots][m + 1]
+    int* rank = nullptr;           // [slots][nk] rank among the knots of its sort key
+    int* counts = nullptr;         // [slots][keys] knots per sort key; zero between passes
+    int* bin_start = nullptr;      // [slots][keys + 1] first sorted knot of each key
     unsigned char* tile_live = nullptr;  // [slots][m][y tiles] spreading tiles that some knot reaches
     int* scell = nullptr;          // [slots][nk] sorted by z-cell: packed cell
     float* skbw = nullptr;         // [slots][nk][3][w]              window weights
@@ -321,6 +321,8 @@ struct Workspace {
         kbw = mem.alloc<float>(S * r.nkw);
         rank = mem.alloc<int>(S * r.nk);
         counts = mem.alloc<int>(S * r.counts);
+        // the sort's counters start at zero; every scan clears them again
+        hip_check(hipMemsetAsync(counts, 0, sizeof(int) * S * r.counts, st), "hipMemsetAsync");
         bin_start = mem.alloc<int>(S * r.bins);
         tile_live = mem.alloc<unsigned char>(S * r.tiles);
         scell = mem.alloc<int>(S * r.nk);
@@ -625,8 +627,8 @@ corr::WsReq ws_req(const corr_ctx* c) {
     r.nk = (size_t)c->nkmax;
     r.nkw = (size_t)c->nkmax * 3 * g.w;
     r.nkq = (size_t)c->nkmax * c->qmax;
-    r.counts = (size_t)g.m * corr::bin_blocks(c->nkmax);
-    r.bins = (size_t)g.m + 1;
+    r.counts = (size_t)corr::bin_keys(g.m);
+    r.bins = (size_t)corr::bin_keys(g.m) + 1;
     r.blocks = (size_t)corr::ifft_x_blocks(g);
     r.tiles = (size_t)g.m * corr::spread_tiles(g);
     return r;

@@ -27,7 +27,7 @@ struct Geom {
 // spreading pass records in tile_live.  The passes after it read only live rows
 // and tiles: the others are zero by construction and are never written.
 struct Occupancy {
-    const int* bin_start = nullptr;         // [S][m + 1] first sorted knot of each z-cell
+    const int* bin_start = nullptr;         // [S][keys + 1] first sorted knot of each key
     unsigned char* tile_live = nullptr;     // [S][m][spread_tiles(g)]
     int64_t nk = 0;                         // knots per rotation
 };
@@ -42,13 +42,17 @@ hipError_t launch_ball_table(const Geom& g, double dk, const double* d_nodes, co
                              int p, int q, double rhi, float* d_vtab /*[q][m2n]*/, hipStream_t st);
 
 // ---- pipeline stages -----------------------------------------------------
-// a0, binned: rotate, place, window weights, and the per-block ranks and
-// counts of a stable counting sort of the knots by z-cell ...
-inline int bin_blocks(int64_t nk) { return (int)((nk + 255) / 256); }
+// Knots are sorted by key = z-cell * (m / ygroup) + y-cell / ygroup, with
+// y-groups of ygroup(m) cells chosen so that there are at most 8192 keys.
+constexpr int bin_ygroup(int m) { return m * m / 8192 > 1 ? m * m / 8192 : 1; }
+constexpr int bin_keys(int m) { return m * (m / bin_ygroup(m)); }
+// a0, binned: rotate, place, window weights, and each knot's rank among the
+// knots of its key from atomic counters (d_counts [S][keys], zero on entry) ...
 hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const double* d_pos, int64_t nk,
                              int* d_cell, float* d_kbw, int* d_rank, int* d_counts, hipStream_t st);
-// ... then the scan of the counts and the scatter of every knot's record (cell,
-// window weights, q component weights) into sorted order.
+// ... then the scan of the counts into d_bin_start [S][keys + 1] (which clears
+// the counters) and the scatter of every knot's record (cell, window weights,
+// q component weights) into sorted order.
 hipError_t launch_bin_sort(const Geom& g, int S, int64_t nk, int q, const int* d_cell, const float* d_kbw,
                            const float* d_wts, const int* d_rank, int* d_counts, int* d_bin_start, int* d_scell,
                            float* d_skbw, float* d_swts, hipStream_t st);

@@ -91,7 +91,7 @@ __device__ __forceinline__ void dft8(float2* v) {
 // written back over the same buffer.  All sizes are compile-time powers of
 // two.  tw[j] = exp(-2 pi i j / LEN) is an LDS table.
 // ---------------------------------------------------------------------------
-template <int LEN, int NS, int SIGN, int COLS, int SI, int SC>
+template <int LEN, int NS, int SIGN, int COLS, int SI, int SC, int NT>
 __device__ __forceinline__ void fft_passes(float2* a, const float2* tw) {
     if constexpr (NS < LEN) {
         constexpr int REM = LEN / NS;
@@ -99,12 +99,12 @@ __device__ __forceinline__ void fft_passes(float2* a, const float2* tw) {
         constexpr int NB = LEN / R;
         constexpr int TWS = LEN / (NS * R);
         constexpr int WORK = NB * COLS;
-        constexpr int NBF = (WORK + kThreads - 1) / kThreads;
+        constexpr int NBF = (WORK + NT - 1) / NT;
         float2 v[NBF][R];
 #pragma unroll
         for (int u = 0; u < NBF; ++u) {
-            const int t = u * kThreads + (int)threadIdx.x;
-            if (WORK % kThreads == 0 || t < WORK) {
+            const int t = u * NT + (int)threadIdx.x;
+            if (WORK % NT == 0 || t < WORK) {
                 const int c = t % COLS, j = t / COLS;
                 const int k = j % NS;
 #pragma unroll
@@ -125,8 +125,8 @@ __device__ __forceinline__ void fft_passes(float2* a, const float2* tw) {
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < NBF; ++u) {
-            const int t = u * kThreads + (int)threadIdx.x;
-            if (WORK % kThreads == 0 || t < WORK) {
+            const int t = u * NT + (int)threadIdx.x;
+            if (WORK % NT == 0 || t < WORK) {
                 const int c = t % COLS, j = t / COLS;
                 const int k = j % NS;
                 const int o = (j / NS) * NS * R + k;
@@ -135,21 +135,22 @@ __device__ __forceinline__ void fft_passes(float2* a, const float2* tw) {
             }
         }
         __syncthreads();
-        fft_passes<LEN, NS * R, SIGN, COLS, SI, SC>(a, tw);
+        fft_passes<LEN, NS * R, SIGN, COLS, SI, SC, NT>(a, tw);
     }
 }
 
 // Unnormalised DFT sum_i x_i exp(SIGN 2 pi i i s / LEN) of every column, in
-// place.  Entered by the whole workgroup once the input in `a` and the table
-// are visible; the result is visible to the whole workgroup on return.
-template <int LEN, int SIGN, int COLS, bool LINES>
+// place, by a workgroup of NT threads.  Entered by the whole workgroup once the
+// input in `a` and the table are visible; the result is visible to the whole
+// workgroup on return.
+template <int LEN, int SIGN, int COLS, bool LINES, int NT = kThreads>
 __device__ __forceinline__ void fft_cols(float2* a, const float2* tw) {
-    fft_passes<LEN, 1, SIGN, COLS, (LINES ? 1 : COLS), (LINES ? LEN + 1 : 1)>(a, tw);
+    fft_passes<LEN, 1, SIGN, COLS, (LINES ? 1 : COLS), (LINES ? LEN + 1 : 1), NT>(a, tw);
 }
 
-template <int LEN>
+template <int LEN, int NT = kThreads>
 __device__ __forceinline__ void load_table(float2* dst, const float2* __restrict__ src) {
-    for (int t = threadIdx.x; t < LEN; t += kThreads) dst[t] = src[t];
+    for (int t = threadIdx.x; t < LEN; t += NT) dst[t] = src[t];
 }
 
 template <int A, int B>
@@ -238,117 +239,106 @@ __global__ void k_ball_table(int m2n, double dk, const double* __restrict__ node
 }
 
 // ---------------------------------------------------------------------------
-// a0 (binned form): rotate + place + window weights, and a stable counting sort
-// of the knots by z-cell, so that a spreading tile finds the knots that reach
-// it as one or two contiguous ranges.
+// a0 (binned form): rotate + place + window weights, and a counting sort of the
+// knots by key = z-cell * nyb + y-cell / ygroup, so that a spreading tile finds
+// the knots that reach it as a few short ranges of the sorted order.  Ranks come
+// from atomic counters, so equal keys are ordered by scheduling: every later
+// sum over knots is exact integer arithmetic, so results do not depend on it.
+// The counters are zero on entry and are cleared again by the scan.
 // ---------------------------------------------------------------------------
 constexpr int kBinBlock = 256;
 
 __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restrict__ quats,
                                                           const double* __restrict__ pos, int64_t nk, double inv_hf,
-                                                          int m, int w, float beta, float inv_i0beta,
-                                                          int* __restrict__ cell, float* __restrict__ kbw,
-                                                          int* __restrict__ rank, int* __restrict__ counts, int nblk) {
-    __shared__ int zc[kBinBlock];
-    __shared__ int hist[512];
+                                                          int m, int w, float beta, float inv_i0beta, int yshift,
+                                                          int nyb, int* __restrict__ cell, float* __restrict__ kbw,
+                                                          int* __restrict__ rank, int* __restrict__ counts) {
     const int64_t j = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
     const int s = blockIdx.y;
-    for (int b = threadIdx.x; b < m; b += kBinBlock) hist[b] = 0;
-    int cz = -1;
-    if (j < nk) {
-        const double* q = quats + 4 * s;
-        double nn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-        double qw = q[0] / nn, x = q[1] / nn, y = q[2] / nn, z = q[3] / nn;
-        double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - qw * z),    2 * (x * z + qw * y),
-                       2 * (x * y + qw * z),    1 - 2 * (x * x + z * z), 2 * (y * z - qw * x),
-                       2 * (x * z - qw * y),    2 * (y * z + qw * x),    1 - 2 * (x * x + y * y)};
-        double px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
-        double u[3] = {(R[0] * px + R[1] * py + R[2] * pz) * inv_hf, (R[3] * px + R[4] * py + R[5] * pz) * inv_hf,
-                       (R[6] * px + R[7] * py + R[8] * pz) * inv_hf};
-        const float tw = 2.0f / (float)w;
-        const int lo = w / 2 - 1;
-        int c[3];
-        float* kw = kbw + ((int64_t)s * nk + j) * 3 * w;
-        for (int d = 0; d < 3; ++d) {
-            double fl = floor(u[d]);
-            float f = (float)(u[d] - fl);
-            long long ci = (long long)fl % m;
-            if (ci < 0) ci += m;
-            c[d] = (int)ci;
-            if (f >= 1.0f) {
-                f = 0.0f;
-                c[d] = (c[d] + 1) % m;
-            }
-            for (int i = 0; i < w; ++i) kw[d * w + i] = kb_window(f - (float)(i - lo), tw, beta, inv_i0beta);
+    if (j >= nk) return;
+    const double* q = quats + 4 * s;
+    double nn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    double qw = q[0] / nn, x = q[1] / nn, y = q[2] / nn, z = q[3] / nn;
+    double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - qw * z),    2 * (x * z + qw * y),
+                   2 * (x * y + qw * z),    1 - 2 * (x * x + z * z), 2 * (y * z - qw * x),
+                   2 * (x * z - qw * y),    2 * (y * z + qw * x),    1 - 2 * (x * x + y * y)};
+    double px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
+    double u[3] = {(R[0] * px + R[1] * py + R[2] * pz) * inv_hf, (R[3] * px + R[4] * py + R[5] * pz) * inv_hf,
+                   (R[6] * px + R[7] * py + R[8] * pz) * inv_hf};
+    const float tw = 2.0f / (float)w;
+    const int lo = w / 2 - 1;
+    int c[3];
+    float* kw = kbw + ((int64_t)s * nk + j) * 3 * w;
+    for (int d = 0; d < 3; ++d) {
+        double fl = floor(u[d]);
+        float f = (float)(u[d] - fl);
+        long long ci = (long long)fl % m;
+        if (ci < 0) ci += m;
+        c[d] = (int)ci;
+        if (f >= 1.0f) {
+            f = 0.0f;
+            c[d] = (c[d] + 1) % m;
         }
-        cell[(int64_t)s * nk + j] = c[0] | (c[1] << 10) | (c[2] << 20);
-        cz = c[2];
+        for (int i = 0; i < w; ++i) kw[d * w + i] = kb_window(f - (float)(i - lo), tw, beta, inv_i0beta);
     }
-    zc[threadIdx.x] = cz;
-    __syncthreads();
-    if (j < nk) {
-        int r = 0;
-        for (int k = 0; k < (int)threadIdx.x; ++k) r += (zc[k] == cz);
-        rank[(int64_t)s * nk + j] = r;
-        atomicAdd(&hist[cz], 1);
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < m; b += kBinBlock) counts[((size_t)s * m + b) * nblk + blockIdx.x] = hist[b];
+    cell[(int64_t)s * nk + j] = c[0] | (c[1] << 10) | (c[2] << 20);
+    const int key = c[2] * nyb + (c[1] >> yshift);
+    rank[(int64_t)s * nk + j] = atomicAdd(&counts[(size_t)s * m * nyb + key], 1);
 }
 
-// Exclusive scan of counts[s][bin][block] (bin-major) into offsets, one
-// workgroup per rotation; bin_start[s][bin] = first sorted position of a bin.
-__global__ __launch_bounds__(1024) void k_bin_scan(int* __restrict__ counts, int m, int nblk, int64_t nk,
-                                                   int* __restrict__ bin_start) {
-    __shared__ int part[1024];
+// Exclusive scan of counts[s][key] into bin_start[s][key] (bin_start[s][keys]
+// = nk), one workgroup per rotation; the counters are cleared for the next use.
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_bin_scan(int* __restrict__ counts, int keys, int64_t nk,
+                                                           int* __restrict__ bin_start) {
+    __shared__ int wsum[kScanThreads / 64];
     const int s = blockIdx.x;
-    int* c = counts + (size_t)s * m * nblk;
-    const int total = m * nblk;
-    const int per = (total + 1023) / 1024;
-    const int b0 = threadIdx.x * per, b1 = min(total, b0 + per);
+    int* c = counts + (size_t)s * keys;
+    int* bs = bin_start + (size_t)s * (keys + 1);
+    const int per = (keys + kScanThreads - 1) / kScanThreads;
+    const int b0 = min(keys, (int)threadIdx.x * per), b1 = min(keys, b0 + per);
     int sum = 0;
     for (int i = b0; i < b1; ++i) sum += c[i];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int t = 0; t < 1024; ++t) {
-            int v = part[t];
-            part[t] = run;
-            run += v;
-        }
+    // inclusive scan of the per-thread sums: within each wave, then over waves
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += v;
     }
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    int run = part[threadIdx.x];
+    int before = 0;
+    for (int v = 0; v < wave; ++v) before += wsum[v];
+    int run = before + incl - sum;
     for (int i = b0; i < b1; ++i) {
-        int v = c[i];
-        c[i] = run;
+        const int v = c[i];
+        bs[i] = run;
+        c[i] = 0;
         run += v;
     }
-    __syncthreads();
-    int* bs = bin_start + (size_t)s * (m + 1);
-    for (int b = threadIdx.x; b < m; b += 1024) bs[b] = c[b * nblk];
-    if (threadIdx.x == 0) bs[m] = (int)nk;
+    if (threadIdx.x == 0) bs[keys] = (int)nk;
 }
 
 // Scatter each knot's record into sorted position: its packed cell, its window
-// weights and its q component weights, so that a spreading tile reads the knots
-// of its z-cells as contiguous memory.
+// weights and its q component weights.
 __global__ __launch_bounds__(kBinBlock) void k_bin_scatter(const int* __restrict__ cell, const float* __restrict__ kbw,
                                                            const float* __restrict__ wts, const int* __restrict__ rank,
-                                                           const int* __restrict__ offsets, int64_t nk, int m, int w,
-                                                           int q, int nblk, int* __restrict__ scell,
+                                                           const int* __restrict__ bin_start, int64_t nk, int keys,
+                                                           int yshift, int nyb, int w, int q, int* __restrict__ scell,
                                                            float* __restrict__ skbw, float* __restrict__ swts) {
     const int64_t j = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
     const int s = blockIdx.y;
     if (j >= nk) return;
     const int packed = cell[(int64_t)s * nk + j];
-    const int cz = (packed >> 20) & 1023;
-    const int64_t p = (int64_t)s * nk + offsets[((size_t)s * m + cz) * nblk + blockIdx.x] + rank[(int64_t)s * nk + j];
+    const int key = ((packed >> 20) & 1023) * nyb + (((packed >> 10) & 1023) >> yshift);
+    const int64_t p = (int64_t)s * nk + bin_start[(size_t)s * (keys + 1) + key] + rank[(int64_t)s * nk + j];
     scell[p] = packed;
-    const float* src = kbw + ((int64_t)s * nk + j) * 3 * w;
-    float* dst = skbw + p * 3 * w;
-    for (int i = 0; i < 3 * w; ++i) dst[i] = src[i];
+    const float2* src = reinterpret_cast<const float2*>(kbw + ((int64_t)s * nk + j) * 3 * w);
+    float2* dst = reinterpret_cast<float2*>(skbw + p * 3 * w);
+    for (int i = 0; i < 3 * w / 2; ++i) dst[i] = src[i];
     for (int c = 0; c < q; ++c) swts[p * q + c] = wts[(size_t)c * nk + j];
 }
 
@@ -359,68 +349,131 @@ __global__ __launch_bounds__(kBinBlock) void k_bin_scatter(const int* __restrict
 // in the imaginary part), transforms the lines along x in LDS and separates the
 // two half spectra:
 //   X_c = (Z_m + conj Z_{M-m}) / 2,  X_{c+1} = (Z_m - conj Z_{M-m}) / 2i.
-// The knots that reach z row z0 are those of z-cells z0-w/2 .. z0+w/2-1: one or
-// two contiguous ranges of the sorted order.  Those whose window also reaches
-// the tile's y rows are compacted in order (wave ballots + a block scan) and
-// staged in LDS with their window and component weights.  Each wave applies
-// staged knots, a lane per window point, adding into 64-bit fixed-point sums
-// with LDS integer atomics: integer addition is exact and associative, so the
-// result does not depend on scheduling.  The fixed-point scale is a power of
-// two chosen per shape so that no sum can overflow.
+// The knots that can reach the tile are those of the z-cells z0-w/2 ..
+// z0+w/2-1 and of the y-groups that hold y-cells y0-w/2 .. y0+TY+w/2-2: at
+// most two key ranges per z-cell of the sorted order.  Those whose window
+// reaches the tile's rows are compacted in order (wave ballots + a block scan)
+// and staged in LDS with their window weights; the component weights of each
+// pair are then read by sorted position.  Each wave applies staged knots, a
+// lane per window point, adding into 64-bit fixed-point sums with LDS integer
+// atomics: integer addition is exact and associative, so the result does not
+// depend on scheduling.  The fixed-point scale is a power of two chosen per
+// shape so that no sum can overflow.  A tile that no knot reaches only records
+// that in tile_live.
 // ---------------------------------------------------------------------------
-// The knots whose z-windows reach z row z0 are those of z-cells
-// z0 - w/2 .. z0 + w/2 - 1 on the periodic axis: one or two ranges
-// [r0a, r0a + n0) and [r1a, ...) of the z-sorted order.  Returns the total.
-__device__ __forceinline__ int zrow_ranges(const int* __restrict__ bs, int64_t nk, int m, int w, int z0, int& r0a,
-                                           int& n0, int& r1a) {
-    const int zlo = z0 - w / 2, zhi = z0 + w / 2 - 1;  // inclusive range of z-cells
-    int a0 = 0, b0 = 0, a1 = 0, b1 = 0;                // an empty shape has no bins to read
-    if (nk == 0) {
-    } else if (zlo < 0) {
-        a0 = bs[zlo + m]; b0 = bs[m]; a1 = bs[0]; b1 = bs[zhi + 1];
-    } else if (zhi >= m) {
-        a0 = bs[zlo]; b0 = bs[m]; a1 = bs[0]; b1 = bs[zhi - m + 1];
-    } else {
-        a0 = bs[zlo]; b0 = bs[zhi + 1];
-    }
-    r0a = a0;
-    n0 = b0 - a0;
-    r1a = a1;
-    return n0 + (b1 - a1);
+template <int M>
+struct SpreadShape {
+    static constexpr int TY = cmin<2048 / M, M>();
+    static constexpr int SC = M + 1;  // padded FFT line (float2)
+    static constexpr int NPTS = TY * M;
+    // fixed-point sums: a plane of int64 real parts and one of imaginary parts,
+    // lines padded by 8 words so that consecutive lines of a window use the
+    // two different halves of the LDS banks; the FFT input overlays them
+    static constexpr int LS = M + 8;
+    static constexpr int G = bin_ygroup(M), NYB = M / G, KEYS = M * NYB;
+    // the sums (and FFT input) and the twiddle table; the staged knots follow
+    static constexpr size_t FIXED = 16 * (size_t)TY * LS + 8 * (size_t)M;
+    static_assert(8 * (size_t)TY * SC <= 16 * (size_t)TY * LS, "FFT input must fit over the sums");
+};
+constexpr int kMaxRanges = 24;  // two key ranges per z-cell of a window of <= 12 cells
+constexpr int kSpreadThreads = 512;
+
+// z row z0 is live iff some knot's z-cell lies in z0-w/2 .. z0+w/2-1 on the
+// periodic axis; bs are the rotation's key starts (z-cell c owns the keys
+// c*NYB .. c*NYB+NYB-1).
+template <int M>
+__device__ __forceinline__ bool zrow_live(const int* __restrict__ bs, int64_t nk, int w, int z0) {
+    constexpr int NYB = SpreadShape<M>::NYB;
+    if (nk == 0) return false;
+    const int zlo = z0 - w / 2, zhi = z0 + w / 2 - 1;
+    if (zlo < 0) return bs[M * NYB] - bs[(zlo + M) * NYB] + bs[(zhi + 1) * NYB] - bs[0] > 0;
+    if (zhi >= M) return bs[M * NYB] - bs[zlo * NYB] + bs[(zhi - M + 1) * NYB] - bs[0] > 0;
+    return bs[(zhi + 1) * NYB] - bs[zlo * NYB] > 0;
 }
 
-__device__ __forceinline__ bool zrow_live(const int* __restrict__ bs, int64_t nk, int m, int w, int z0) {
-    int r0a, n0, r1a;
-    return zrow_ranges(bs, nk, m, w, z0, r0a, n0, r1a) > 0;
-}
-
+// Staged knot: packed cell, sorted position, window weights along x and y, the
+// z weight of the tile's row, and (per component pair) the two component
+// weights times the z weight and the fixed-point scale.
 struct SpreadStage {
-    int* cell;    // [cap] packed cell
-    float* wx;    // [cap][w]
-    float* wy;    // [cap][w]
-    float* wz;    // [cap] weight of this z row
-    float* wq;    // [cap][q] component weights
+    float2* wq;  // [cap]
+    int* cell;   // [cap]
+    int* pos;    // [cap]
+    float* wz;   // [cap]
+    float* wx;   // [cap][w]
+    float* wy;   // [cap][w]
 };
 
+// Key ranges of the tile's candidate knots, by wave 0: rstart[r], and the
+// prefix sums rpre[0..2w] of their lengths.
+template <int M>
+__device__ void tile_ranges(const int* __restrict__ bs, int w, int y0, int z0, int* rstart, int* rpre) {
+    using SS = SpreadShape<M>;
+    constexpr int TY = SS::TY, G = SS::G, NYB = SS::NYB;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x >= 64) return;
+    int start = 0, len = 0;
+    if (lane < 2 * w) {
+        const int zc = (z0 - w / 2 + (lane >> 1) + M) & (M - 1);
+        const int ylo = y0 - w / 2, yhi = y0 + TY + w / 2 - 2;  // y-cells whose windows reach the tile
+        int ga[2] = {0, 0}, gb[2] = {NYB - 1, -1};             // inclusive group ranges; gb < ga is empty
+        if (TY + w - 1 < M) {
+            if (ylo < 0) {
+                ga[0] = (ylo + M) / G; gb[1] = yhi / G;
+            } else if (yhi >= M) {
+                ga[0] = ylo / G; gb[1] = (yhi - M) / G;
+            } else {
+                ga[0] = ylo / G; gb[0] = yhi / G;
+            }
+            if (gb[1] >= ga[0]) {  // the two pieces meet: every group
+                ga[0] = 0; gb[0] = NYB - 1; gb[1] = -1;
+            }
+        }
+        const int part = lane & 1;
+        if (gb[part] >= ga[part]) {
+            start = bs[zc * NYB + ga[part]];
+            len = bs[zc * NYB + gb[part] + 1] - start;
+        }
+    }
+    int incl = len;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        const int v = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += v;
+    }
+    if (lane < 2 * w) {
+        rstart[lane] = start;
+        rpre[lane + 1] = incl;
+    }
+    if (lane == 0) rpre[0] = 0;
+}
+
 // Stage the filtered knots with filtered rank in [first, first + cap); returns
-// the total number of filtered knots.  sc_, kb_, wq_ point at this rotation's
-// sorted records.
-__device__ int stage_knots(const int* __restrict__ sc_, const float* __restrict__ kb_, const float* __restrict__ wq_,
-                           int q, int m, int w, int ty, int y0, int z0, int r0a, int n0, int r1a, int ncand, int first,
-                           int cap, SpreadStage st, int* wave_tot) {
+// the total number of filtered knots.  Entered and left by the whole workgroup.
+template <int M>
+__device__ int stage_knots(const int* __restrict__ sc_, const float* __restrict__ kb_, int w, int y0, int z0,
+                           const int* rstart, const int* rpre, int nr, int first, int cap, SpreadStage st,
+                           int* wave_tot) {
+    constexpr int TY = SpreadShape<M>::TY;
     const int lo = w / 2 - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ncand = rpre[nr];
     int running = 0;
-    for (int base = 0; base < ncand; base += kThreads) {
+    for (int base = 0; base < ncand; base += kSpreadThreads) {
         const int ci = base + threadIdx.x;
         int p = 0, packed = 0;
         bool keep = false;
         if (ci < ncand) {
-            p = ci < n0 ? r0a + ci : r1a + (ci - n0);
+            int r0 = 0, r1 = nr;  // the range holding ci: rpre[r0] <= ci < rpre[r0 + 1]
+            while (r1 - r0 > 1) {
+                const int mid = (r0 + r1) >> 1;
+                if (rpre[mid] <= ci) r0 = mid;
+                else r1 = mid;
+            }
+            p = rstart[r0] + (ci - rpre[r0]);
             packed = sc_[p];
             const int cy = (packed >> 10) & 1023;
-            const int ry = (cy - lo - y0 + 2 * m) & (m - 1);
-            keep = ry < ty || ry > m - w;
+            const int ry = (cy - lo - y0 + 2 * M) & (M - 1);
+            keep = ry < TY || ry > M - w;
         }
         const unsigned long long mask = __ballot(keep);
         const int before = __popcll(mask & ((1ull << lane) - 1ull));
@@ -428,41 +481,29 @@ __device__ int stage_knots(const int* __restrict__ sc_, const float* __restrict_
         __syncthreads();
         int off = running, total = 0;
 #pragma unroll
-        for (int v = 0; v < kThreads / 64; ++v) {
+        for (int v = 0; v < kSpreadThreads / 64; ++v) {
             off += v < wave ? wave_tot[v] : 0;
             total += wave_tot[v];
         }
         const int rk = off + before - first;
         if (keep && rk >= 0 && rk < cap) {
             st.cell[rk] = packed;
-            const float* kw = kb_ + (int64_t)p * 3 * w;
-            for (int d = 0; d < w; ++d) {
-                st.wx[rk * w + d] = kw[d];
-                st.wy[rk * w + d] = kw[w + d];
+            st.pos[rk] = p;
+            const float2* kw = reinterpret_cast<const float2*>(kb_ + (int64_t)p * 3 * w);
+            float2* dx = reinterpret_cast<float2*>(st.wx + rk * w);
+            float2* dy = reinterpret_cast<float2*>(st.wy + rk * w);
+            for (int d = 0; d < w / 2; ++d) {
+                dx[d] = kw[d];
+                dy[d] = kw[w / 2 + d];
             }
             const int cz = (packed >> 20) & 1023;
-            st.wz[rk] = kw[2 * w + ((z0 - cz + lo + m) & (m - 1))];
-            for (int c = 0; c < q; ++c) st.wq[rk * q + c] = wq_[(int64_t)p * q + c];
+            st.wz[rk] = kb_[(int64_t)p * 3 * w + 2 * w + ((z0 - cz + lo + M) & (M - 1))];
         }
         running += total;
         __syncthreads();
     }
     return running;
 }
-
-template <int M>
-struct SpreadShape {
-    static constexpr int TY = cmin<2048 / M, M>();
-    static constexpr int SC = M + 1;
-    static constexpr int NPTS = TY * M;
-    // fixed-point sums: a plane of int64 real parts and one of imaginary
-    // parts, lines padded by 8 words so that consecutive lines of a window use
-    // the two different halves of the LDS banks
-    static constexpr int LS = M + 8;  // int64 words per line
-    // fixed-point sums, the padded FFT input, the twiddle table; the staged
-    // knots follow
-    static constexpr size_t FIXED = 16 * (size_t)TY * LS + 8 * (size_t)TY * SC + 8 * (size_t)M;
-};
 
 // Exact int64 -> double split (hi * 2^32 + lo), then one rounding to float.
 __device__ __forceinline__ float fixed_to_float(unsigned long long u, float inv) {
@@ -472,7 +513,7 @@ __device__ __forceinline__ float fixed_to_float(unsigned long long u, float inv)
 }
 
 template <int M>
-__global__ __launch_bounds__(kThreads) void k_spread_fftx(const int* __restrict__ bin_start,
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __restrict__ bin_start,
                                                           unsigned char* __restrict__ tile_live,
                                                           const int* __restrict__ scell, const float* __restrict__ skbw,
                                                           const float* __restrict__ swts, int64_t nk, int q, int w,
@@ -481,90 +522,105 @@ __global__ __launch_bounds__(kThreads) void k_spread_fftx(const int* __restrict_
     constexpr int H = M / 4;  // half of the n = M/2 kept modes along x
     using SS = SpreadShape<M>;
     constexpr int TY = SS::TY, SC = SS::SC, NPTS = SS::NPTS, LS = SS::LS;
-    constexpr int NW = kThreads / 64;
-    constexpr int U = 2;  // staged knots in flight per wave
+    constexpr int NT = kSpreadThreads, NW = NT / 64;
+    constexpr int U = 4;         // staged knots in flight per wave
+    constexpr int CV = NPTS / NT;  // sums converted per thread
+    static_assert(NPTS % NT == 0, "tile must split evenly over the workgroup");
     extern __shared__ float2 lds[];
     __shared__ int wave_tot[NW];
+    __shared__ int rstart[kMaxRanges], rpre[kMaxRanges + 1];
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds);  // [2][TY][LS]
-    float2* a = lds + 2 * TY * LS;
-    float2* twl = a + TY * SC;
+    float2* a = lds;                                                       // [TY][SC] over the sums
+    float2* twl = lds + 2 * TY * LS;                                       // after both planes
     SpreadStage st;
-    st.cell = reinterpret_cast<int*>(twl + M);
-    st.wx = reinterpret_cast<float*>(st.cell + cap);
+    st.wq = twl + M;
+    st.cell = reinterpret_cast<int*>(st.wq + cap);
+    st.pos = st.cell + cap;
+    st.wz = reinterpret_cast<float*>(st.pos + cap);
+    st.wx = st.wz + cap;
     st.wy = st.wx + cap * w;
-    st.wz = st.wy + cap * w;
-    st.wq = st.wz + cap;
     const int y0 = blockIdx.x * TY, z0 = blockIdx.y, s = blockIdx.z;
     const int lo = w / 2 - 1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int dmul = (65536 + w - 1) / w;  // t / w for t < w*w by a multiply
-    int r0a, n0, r1a;
-    const int ncand = zrow_ranges(bin_start + (size_t)s * (M + 1), nk, M, w, z0, r0a, n0, r1a);
+    const int nr = 2 * w;
+    int nfilt = 0;
+    if (nk > 0) {
+        tile_ranges<M>(bin_start + (size_t)s * (SS::KEYS + 1), w, y0, z0, rstart, rpre);
+        __syncthreads();
+        const int* sc_ = scell + (int64_t)s * nk;
+        const float* kb_ = skbw + (int64_t)s * nk * 3 * w;
+        if (rpre[nr] > 0) nfilt = stage_knots<M>(sc_, kb_, w, y0, z0, rstart, rpre, nr, 0, cap, st, wave_tot);
+    }
+    if (threadIdx.x == 0) tile_live[((size_t)s * M + z0) * (M / TY) + blockIdx.x] = nfilt > 0;
+    if (nfilt == 0) return;  // the tile's spectrum is zero and is not written
     const int* sc_ = scell + (int64_t)s * nk;
     const float* kb_ = skbw + (int64_t)s * nk * 3 * w;
     const float* wq_ = swts + (int64_t)s * nk * q;
-    const int nfilt = ncand ? stage_knots(sc_, kb_, wq_, q, M, w, TY, y0, z0, r0a, n0, r1a, ncand, 0, cap, st, wave_tot)
-                            : 0;
-    if (threadIdx.x == 0) tile_live[((size_t)s * M + z0) * (M / TY) + blockIdx.x] = nfilt > 0;
-    if (nfilt == 0) return;  // the tile's spectrum is zero and is not written
-    load_table<M>(twl, twm);
-    for (int t = threadIdx.x; t < 2 * TY * LS; t += kThreads) acc[t] = 0ull;
+    load_table<M, NT>(twl, twm);
+    for (int t = threadIdx.x; t < 2 * TY * LS; t += NT) acc[t] = 0ull;
     const int rounds = (nfilt + cap - 1) / cap;
-    __syncthreads();
     for (int cp = 0; cp < q; cp += 2) {
         for (int r = 0; r < rounds; ++r) {
             if (rounds > 1 && (r > 0 || cp > 0))
-                stage_knots(sc_, kb_, wq_, q, M, w, TY, y0, z0, r0a, n0, r1a, ncand, r * cap, cap, st, wave_tot);
+                stage_knots<M>(sc_, kb_, w, y0, z0, rstart, rpre, nr, r * cap, cap, st, wave_tot);
             const int nst = min(cap, nfilt - r * cap);
+            // this pair's component weights, times the z weight and the scale
+            for (int i = threadIdx.x; i < nst; i += NT) {
+                const float* wp = wq_ + (int64_t)st.pos[i] * q + cp;
+                const float f = st.wz[i] * fix_scale;
+                st.wq[i] = make_float2(wp[0] * f, cp + 1 < q ? wp[1] * f : 0.0f);
+            }
+            __syncthreads();
             // each wave takes U staged knots at a time, a lane per window point;
-            // the reads of all U are issued before their atomic adds
+            // the LDS reads of all U (at clamped, valid indices) are issued
+            // together, then the atomic adds of the lanes that land in the tile
             for (int i0 = wave; i0 < nst; i0 += U * NW) {
                 for (int t0 = 0; t0 < w * w; t0 += 64) {
                     const int t = t0 + lane;
-                    const int ddy = (t * dmul) >> 16, ddx = t - ddy * w;
-                    int off[U];
-                    float v0[U], v1[U];
+                    const int ddy = min((t * dmul) >> 16, w - 1), ddx = t - ((t * dmul) >> 16) * w;
+                    int packed[U];
+                    float wyx[U];
+                    float2 c2[U];
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const int i = i0 + u * NW;
-                        off[u] = -1;
-                        v0[u] = v1[u] = 0.f;
-                        if (i < nst && t < w * w) {
-                            const int packed = st.cell[i];
-                            const int cx = packed & 1023, cy = (packed >> 10) & 1023;
-                            const int l = (cy - lo - y0 + ddy + 2 * M) & (M - 1);
-                            if (l < TY) {
-                                const int x = (cx - lo + ddx + M) & (M - 1);
-                                const float v = st.wy[i * w + ddy] * st.wx[i * w + ddx] * st.wz[i] * fix_scale;
-                                v0[u] = st.wq[i * q + cp] * v;
-                                v1[u] = (cp + 1 < q) ? st.wq[i * q + cp + 1] * v : 0.0f;
-                                off[u] = l * LS + x;
-                            }
-                        }
+                        const int i = min(i0 + u * NW, nst - 1);
+                        packed[u] = st.cell[i];
+                        wyx[u] = st.wy[i * w + ddy] * st.wx[i * w + ddx];
+                        c2[u] = st.wq[i];
                     }
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        if (off[u] < 0) continue;
-                        atomicAdd(acc + off[u], (unsigned long long)__float2ll_rn(v0[u]));
-                        atomicAdd(acc + TY * LS + off[u], (unsigned long long)__float2ll_rn(v1[u]));
+                        const int cx = packed[u] & 1023, cy = (packed[u] >> 10) & 1023;
+                        const int l = (cy - lo - y0 + ddy + 2 * M) & (M - 1);
+                        if (i0 + u * NW < nst && t < w * w && l < TY) {
+                            const int off = l * LS + ((cx - lo + ddx + M) & (M - 1));
+                            atomicAdd(acc + off, (unsigned long long)__float2ll_rn(c2[u].x * wyx[u]));
+                            atomicAdd(acc + TY * LS + off, (unsigned long long)__float2ll_rn(c2[u].y * wyx[u]));
+                        }
                     }
                 }
             }
             __syncthreads();
         }
-        // sums -> FFT input, clearing the sums for the next component pair
-        for (int t = threadIdx.x; t < NPTS; t += kThreads) {
-            const int l = t / M, x = t % M;
-            unsigned long long* e = acc + l * LS + x;
-            const unsigned long long re = e[0], im = e[TY * LS];
-            e[0] = 0ull;
-            e[TY * LS] = 0ull;
-            a[l * SC + x] = make_float2(fixed_to_float(re, fix_inv), fixed_to_float(im, fix_inv));
+        // sums -> FFT input over the same memory
+        float2 cv[CV];
+#pragma unroll
+        for (int k = 0; k < CV; ++k) {
+            const int t = k * NT + threadIdx.x;
+            const int e = (t / M) * LS + t % M;
+            cv[k] = make_float2(fixed_to_float(acc[e], fix_inv), fixed_to_float(acc[TY * LS + e], fix_inv));
         }
         __syncthreads();
-        fft_cols<M, -1, TY, true>(a, twl);
+#pragma unroll
+        for (int k = 0; k < CV; ++k) {
+            const int t = k * NT + threadIdx.x;
+            a[(t / M) * SC + t % M] = cv[k];
+        }
+        __syncthreads();
+        fft_cols<M, -1, TY, true, NT>(a, twl);
         constexpr int PER = TY * H;
-        for (int t = threadIdx.x; t < 2 * PER; t += kThreads) {
+        for (int t = threadIdx.x; t < 2 * PER; t += NT) {
             const int comp = t >= PER;
             const int r = t - comp * PER;
             const int l = r / H, mm = r % H;
@@ -575,7 +631,10 @@ __global__ __launch_bounds__(kThreads) void k_spread_fftx(const int* __restrict_
                                   : make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
             out[((((size_t)s * q + cp + comp) * M + z0) * M + y0 + l) * H + mm] = o;
         }
-        __syncthreads();
+        if (cp + 2 < q) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < 2 * TY * LS; t += NT) acc[t] = 0ull;
+        }
     }
 }
 
@@ -611,7 +670,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ i
     float2* a = lds;
     float2* twl = a + M * COLS;
     const int z = blockIdx.y, s = blockIdx.z / q;
-    if (!zrow_live(bin_start + (size_t)s * (M + 1), nk, M, w, z)) return;
+    if (!zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, z)) return;
     load_table<M>(twl, twm);
     for (int t = threadIdx.x; t < NT; t += kThreads) live[t] = tile_live[((size_t)s * M + z) * NT + t];
     __syncthreads();
@@ -717,7 +776,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __res
         return;
     }
     load_table<M>(twl, twm);
-    for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live(bin_start + (size_t)s * (M + 1), nk, M, w, t);
+    for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, t);
     __syncthreads();
     float2 acc[PER];
     z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, twl, zlive, acc);
@@ -758,7 +817,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
     }
     load_table<M>(twl, twm);
     load_table<N>(twnl, twn);
-    for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live(bin_start + (size_t)s * (M + 1), nk, M, w, t);
+    for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, t);
     __syncthreads();
     float2 acc[PER];
     z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, twl, zlive, acc);
@@ -936,19 +995,21 @@ hipError_t with_m(int m, F&& f) {
 
 constexpr size_t kSpreadLds = 80 * 1024;  // two spreading workgroups per CU
 
+// bytes of one staged knot: component pair, cell, position, z weight, x and y weights
+inline size_t staged_bytes(int w) { return 20 + 8 * (size_t)w; }
+
 template <int M>
-int spread_cap_t(int w, int q) {
-    const size_t per = sizeof(float) * (2 + 2 * (size_t)w + q);
+int spread_cap_t(int w) {
     const size_t fixed = SpreadShape<M>::FIXED;
     const size_t room = fixed < kSpreadLds ? kSpreadLds - fixed : 0;
-    int cap = (int)std::min<size_t>(512, room / per);
+    int cap = (int)std::min<size_t>(512, room / staged_bytes(w));
     cap &= ~63;
     return cap < 64 ? 64 : cap;
 }
 
 template <int M>
-size_t spread_lds_t(int w, int q) {
-    return SpreadShape<M>::FIXED + (size_t)spread_cap_t<M>(w, q) * sizeof(float) * (2 + 2 * (size_t)w + q);
+size_t spread_lds_t(int w) {
+    return SpreadShape<M>::FIXED + (size_t)spread_cap_t<M>(w) * staged_bytes(w);
 }
 
 }  // namespace
@@ -967,12 +1028,21 @@ hipError_t launch_ball_table(const Geom& g, double dk, const double* d_nodes, co
     return hipGetLastError();
 }
 
+namespace {
+int log2i(int v) {
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+int bin_blocks(int64_t nk) { return (int)((nk + kBinBlock - 1) / kBinBlock); }
+}  // namespace
+
 hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const double* d_pos, int64_t nk,
                              int* d_cell, float* d_kbw, int* d_rank, int* d_counts, hipStream_t st) {
     if (nk == 0 || S == 0) return hipSuccess;
-    const int nblk = bin_blocks(nk);
-    hipLaunchKernelGGL(k_rotate_bin, dim3(nblk, S), dim3(kBinBlock), 0, st, d_quats, d_pos, nk, g.inv_hf, g.m, g.w,
-                       g.beta, g.inv_i0beta, d_cell, d_kbw, d_rank, d_counts, nblk);
+    const int G = bin_ygroup(g.m);
+    hipLaunchKernelGGL(k_rotate_bin, dim3(bin_blocks(nk), S), dim3(kBinBlock), 0, st, d_quats, d_pos, nk, g.inv_hf,
+                       g.m, g.w, g.beta, g.inv_i0beta, log2i(G), g.m / G, d_cell, d_kbw, d_rank, d_counts);
     return hipGetLastError();
 }
 
@@ -980,12 +1050,12 @@ hipError_t launch_bin_sort(const Geom& g, int S, int64_t nk, int q, const int* d
                            const float* d_wts, const int* d_rank, int* d_counts, int* d_bin_start, int* d_scell,
                            float* d_skbw, float* d_swts, hipStream_t st) {
     if (nk == 0 || S == 0) return hipSuccess;
-    const int nblk = bin_blocks(nk);
-    hipLaunchKernelGGL(k_bin_scan, dim3(S), dim3(1024), 0, st, d_counts, g.m, nblk, nk, d_bin_start);
+    const int G = bin_ygroup(g.m), keys = bin_keys(g.m);
+    hipLaunchKernelGGL(k_bin_scan, dim3(S), dim3(kScanThreads), 0, st, d_counts, keys, nk, d_bin_start);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_scatter, dim3(nblk, S), dim3(kBinBlock), 0, st, d_cell, d_kbw, d_wts, d_rank, d_counts,
-                       nk, g.m, g.w, q, nblk, d_scell, d_skbw, d_swts);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(bin_blocks(nk), S), dim3(kBinBlock), 0, st, d_cell, d_kbw, d_wts, d_rank,
+                       d_bin_start, nk, keys, log2i(G), g.m / G, g.w, q, d_scell, d_skbw, d_swts);
     return hipGetLastError();
 }
 
@@ -995,7 +1065,7 @@ size_t max_lds_bytes(const Geom& g, int qmax) {
         constexpr int M = decltype(mc)::value;
         constexpr int N = M / 2;
         using C = ColShape<M>;
-        need = std::max(need, spread_lds_t<M>(g.w, qmax));
+        need = std::max(need, spread_lds_t<M>(g.w));
         need = std::max(need, sizeof(float2) * ((size_t)M * C::COLS + M + N));
         need = std::max(need, sizeof(float2) * ((size_t)N * C::ICOLS + N));
         need = std::max(need, sizeof(float2) * ((size_t)C::XCOLS * (N + 1) + N) + 8 * kThreads);
@@ -1019,9 +1089,9 @@ hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, const 
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         constexpr int TY = SpreadShape<M>::TY;
-        hipLaunchKernelGGL(k_spread_fftx<M>, dim3(M / TY, M, S), dim3(kThreads), spread_lds_t<M>(g.w, q), st,
+        hipLaunchKernelGGL(k_spread_fftx<M>, dim3(M / TY, M, S), dim3(kSpreadThreads), spread_lds_t<M>(g.w), st,
                            occ.bin_start, occ.tile_live, d_scell, d_skbw, d_swts, occ.nk, q, g.w,
-                           spread_cap_t<M>(g.w, q), fix_scale, 1.0f / fix_scale, d_out, d_twm);
+                           spread_cap_t<M>(g.w), fix_scale, 1.0f / fix_scale, d_out, d_twm);
     });
 }
 
