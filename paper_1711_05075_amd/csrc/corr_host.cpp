@@ -278,15 +278,17 @@ struct WsReq {
     size_t counts = 1, bins = 1;    // sort keys, keys + 1 per slot
     size_t blocks = 1;              // inverse-x blocks per slot
     size_t tiles = 1;               // spreading tiles (m z rows x y tiles) per slot
+    size_t list = 1;                // live-tile list entries per slot
     void merge(const WsReq& o) {
         buf0 = std::max(buf0, o.buf0); buf1 = std::max(buf1, o.buf1);
         nk = std::max(nk, o.nk); nkw = std::max(nkw, o.nkw); nkq = std::max(nkq, o.nkq);
         counts = std::max(counts, o.counts); bins = std::max(bins, o.bins); blocks = std::max(blocks, o.blocks);
         tiles = std::max(tiles, o.tiles);
+        list = std::max(list, o.list);
     }
     size_t slot_bytes() const {
         return 4 * buf0 + 8 * buf1 + 4 * (3 * nk + nkw + nkq) + 12 * nkw + 4 * (counts + bins) + 8 * blocks + tiles +
-               32;
+               4 * list + 32;
     }
 };
 
@@ -302,6 +304,8 @@ struct Workspace {
     int* counts = nullptr;         // [slots][keys] knots per sort key; zero between passes
     int* bin_start = nullptr;      // [slots][keys + 1] first sorted knot of each key
     unsigned char* tile_live = nullptr;  // [slots][m][y tiles] spreading tiles that some knot reaches
+    int* plan = nullptr;           // bucket sizes and work counter of the spreading pass's live-tile plan
+    int* list = nullptr;           // [buckets][slots * tiles] live tiles
     int* scell = nullptr;          // [slots][nk] sorted by z-cell: packed cell
     float* skbw = nullptr;         // [slots][nk][3][w]              window weights
     float* swts = nullptr;         // [slots][nk][q]                 component weights
@@ -325,6 +329,8 @@ struct Workspace {
         hip_check(hipMemsetAsync(counts, 0, sizeof(int) * S * r.counts, st), "hipMemsetAsync");
         bin_start = mem.alloc<int>(S * r.bins);
         tile_live = mem.alloc<unsigned char>(S * r.tiles);
+        plan = mem.alloc<int>(corr::plan_words());
+        list = mem.alloc<int>(S * r.list);
         scell = mem.alloc<int>(S * r.nk);
         skbw = mem.alloc<float>(S * r.nkw);
         swts = mem.alloc<float>(S * r.nkq);
@@ -492,12 +498,15 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
         return corr::launch_rotate_bin(g, d_quats, S, s.pos, s.n, c->ws->cell, c->ws->kbw, c->ws->rank, c->ws->counts, c->stream);
     });
     stage(c, CORR_STAGE_BIN, "bin", [&] {
-        return corr::launch_bin_sort(g, S, s.n, q, c->ws->cell, c->ws->kbw, s.wts, c->ws->rank, c->ws->counts, c->ws->bin_start, c->ws->scell,
-                                     c->ws->skbw, c->ws->swts, c->stream);
+        hip_check(corr::launch_bin_sort(g, S, s.n, q, c->ws->cell, c->ws->kbw, s.wts, c->ws->rank, c->ws->counts,
+                                        c->ws->bin_start, c->ws->scell, c->ws->skbw, c->ws->swts, c->ws->plan,
+                                        c->stream),
+                  "bin");
+        return corr::launch_tile_plan(g, S, occupancy(c, s), c->ws->plan, c->ws->list, c->stream);
     });
     stage(c, CORR_STAGE_SPREAD_FFT_X, "spread + fft x", [&] {
-        return corr::launch_spread_fftx(g, S, occupancy(c, s), c->ws->scell, c->ws->skbw, c->ws->swts, q,
-                                        s.fix_scale, c->ws->buf1, c->twm, c->stream);
+        return corr::launch_spread_fftx(g, S, occupancy(c, s), c->ws->plan, c->ws->list, c->ws->scell, c->ws->skbw,
+                                        c->ws->swts, q, s.fix_scale, c->ws->buf1, c->twm, c->stream);
     });
     stage(c, CORR_STAGE_FFT_Y, "fft y", [&] {
         return corr::launch_fft_y(g, S, q, occupancy(c, s), c->ws->buf1, reinterpret_cast<float2*>(c->ws->buf0),
@@ -582,6 +591,9 @@ corr_ctx* plan_pair(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t 
         g.beta = (float)beta;
         g.inv_i0beta = (float)(1.0 / std::cyl_bessel_i(0.0, (double)g.beta));
         g.inv_hf = g.m / gr.box;
+        int cus = 0;
+        hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device), "CU count");
+        g.spread_wgs = 2 * std::max(cus, 1);
         const double dk = 2.0 * M_PI / gr.box;
 
         setup_shape(c, c->A, A, nA, dk);
@@ -631,6 +643,7 @@ corr::WsReq ws_req(const corr_ctx* c) {
     r.bins = (size_t)corr::bin_keys(g.m) + 1;
     r.blocks = (size_t)corr::ifft_x_blocks(g);
     r.tiles = (size_t)g.m * corr::spread_tiles(g);
+    r.list = (size_t)corr::plan_buckets() * r.tiles;
     return r;
 }
 

@@ -19,6 +19,7 @@ struct Geom {
     float beta = 0.f;         // window shape
     float inv_i0beta = 0.f;   // 1 / I0(beta): window normalised to 1 at its centre
     double inv_hf = 0.0;      // 1 / spreading-cell size
+    int spread_wgs = 0;       // workgroups of the persistent spreading pass (two per CU)
 };
 
 // Which parts of a rotation's spreading grid hold knots.  z row z is live iff
@@ -33,6 +34,10 @@ struct Occupancy {
 };
 // y tiles per z row of the spreading pass.
 int spread_tiles(const Geom& g);
+// ints of a spreading pass's plan counters; its live-tile list holds
+// plan_buckets() * S * m * spread_tiles(g) ints.
+int plan_words();
+constexpr int plan_buckets() { return 8; }
 
 // ---- table builders (FP64 on the device) ---------------------------------
 hipError_t launch_deconv_tables(const Geom& g, double box, const double origin[3],
@@ -55,15 +60,20 @@ hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const 
 // q component weights) into sorted order.
 hipError_t launch_bin_sort(const Geom& g, int S, int64_t nk, int q, const int* d_cell, const float* d_kbw,
                            const float* d_wts, const int* d_rank, int* d_counts, int* d_bin_start, int* d_scell,
-                           float* d_skbw, float* d_swts, hipStream_t st);
+                           float* d_skbw, float* d_swts, int* d_plan, hipStream_t st);
+// Live-tile plan: marks the tiles that no knot's window can reach dead in
+// occ.tile_live and lists the others in d_list by the size of their candidate
+// sets (d_plan: bucket sizes and a work counter, zeroed by launch_bin_sort).
+hipError_t launch_tile_plan(const Geom& g, int S, const Occupancy& occ, int* d_plan, int* d_list, hipStream_t st);
 // a1 + a2 (x): gather-spreading of the sorted knots fused with the x transform;
 // writes [S][q][z][y][mx] without a spreading grid in HBM.
 // Sums are exact 64-bit fixed point; fix_scale is a power of two with
 // fix_scale * sum_i max_c |wts[c][i]| <= 2^61.
-// Tiles that no knot reaches only record that in occ.tile_live.
-hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, const int* d_scell,
-                              const float* d_skbw, const float* d_swts, int q, float fix_scale, float2* d_out,
-                              const float2* d_twm, hipStream_t st);
+// Runs g.spread_wgs persistent workgroups over the plan's tiles; a listed tile
+// that no knot reaches only records that in occ.tile_live.
+hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, int* d_plan, const int* d_list,
+                              const int* d_scell, const float* d_skbw, const float* d_swts, int q, float fix_scale,
+                              float2* d_out, const float2* d_twm, hipStream_t st);
 // Largest dynamic LDS any stage asks for.
 size_t max_lds_bytes(const Geom& g, int qmax);
 // a2: pruned forward y pass of S rotations x q components (live rows only).

@@ -291,7 +291,8 @@ __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restri
 constexpr int kScanThreads = 1024;
 
 __global__ __launch_bounds__(kScanThreads) void k_bin_scan(int* __restrict__ counts, int keys, int64_t nk,
-                                                           int* __restrict__ bin_start) {
+                                                           int* __restrict__ bin_start, int* __restrict__ plan,
+                                                           int nplan) {
     __shared__ int wsum[kScanThreads / 64];
     const int s = blockIdx.x;
     int* c = counts + (size_t)s * keys;
@@ -320,6 +321,7 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_scan(int* __restrict__ cou
         run += v;
     }
     if (threadIdx.x == 0) bs[keys] = (int)nk;
+    if (s == 0 && (int)threadIdx.x < nplan) plan[threadIdx.x] = 0;  // counters of the tile plan that follows
 }
 
 // Scatter each knot's record into sorted position: its packed cell, its window
@@ -403,37 +405,47 @@ struct SpreadStage {
     float* wy;   // [cap][w]
 };
 
-// Key ranges of the tile's candidate knots, by wave 0: rstart[r], and the
-// prefix sums rpre[0..2w] of their lengths.
+// Key range j (0 .. 2w-1) of a tile's candidate knots, [start, start + len):
+// z-cell j/2 of the z row's window and, of the y-groups that hold y-cells whose
+// windows reach rows y0 .. y0+TY-1, the piece j%2 (the groups wrap around the
+// periodic axis at most once).
 template <int M>
-__device__ void tile_ranges(const int* __restrict__ bs, int w, int y0, int z0, int* rstart, int* rpre) {
+__device__ __forceinline__ void tile_range(const int* __restrict__ bs, int w, int y0, int z0, int j, int& start,
+                                           int& len) {
     using SS = SpreadShape<M>;
     constexpr int TY = SS::TY, G = SS::G, NYB = SS::NYB;
+    const int zc = (z0 - w / 2 + (j >> 1) + M) & (M - 1);
+    const int ylo = y0 - w / 2, yhi = y0 + TY + w / 2 - 2;
+    int ga[2] = {0, 0}, gb[2] = {NYB - 1, -1};  // inclusive group ranges; gb < ga is empty
+    if (TY + w - 1 < M) {
+        if (ylo < 0) {
+            ga[0] = (ylo + M) / G; gb[1] = yhi / G;
+        } else if (yhi >= M) {
+            ga[0] = ylo / G; gb[1] = (yhi - M) / G;
+        } else {
+            ga[0] = ylo / G; gb[0] = yhi / G;
+        }
+        if (gb[1] >= ga[0]) {  // the two pieces meet: every group
+            ga[0] = 0; gb[0] = NYB - 1; gb[1] = -1;
+        }
+    }
+    const int part = j & 1;
+    start = 0;
+    len = 0;
+    if (gb[part] >= ga[part]) {
+        start = bs[zc * NYB + ga[part]];
+        len = bs[zc * NYB + gb[part] + 1] - start;
+    }
+}
+
+// All key ranges of a tile, by wave 0: rstart[r], and the prefix sums
+// rpre[0..2w] of their lengths.
+template <int M>
+__device__ void tile_ranges(const int* __restrict__ bs, int w, int y0, int z0, int* rstart, int* rpre) {
     const int lane = threadIdx.x & 63;
     if (threadIdx.x >= 64) return;
     int start = 0, len = 0;
-    if (lane < 2 * w) {
-        const int zc = (z0 - w / 2 + (lane >> 1) + M) & (M - 1);
-        const int ylo = y0 - w / 2, yhi = y0 + TY + w / 2 - 2;  // y-cells whose windows reach the tile
-        int ga[2] = {0, 0}, gb[2] = {NYB - 1, -1};             // inclusive group ranges; gb < ga is empty
-        if (TY + w - 1 < M) {
-            if (ylo < 0) {
-                ga[0] = (ylo + M) / G; gb[1] = yhi / G;
-            } else if (yhi >= M) {
-                ga[0] = ylo / G; gb[1] = (yhi - M) / G;
-            } else {
-                ga[0] = ylo / G; gb[0] = yhi / G;
-            }
-            if (gb[1] >= ga[0]) {  // the two pieces meet: every group
-                ga[0] = 0; gb[0] = NYB - 1; gb[1] = -1;
-            }
-        }
-        const int part = lane & 1;
-        if (gb[part] >= ga[part]) {
-            start = bs[zc * NYB + ga[part]];
-            len = bs[zc * NYB + gb[part] + 1] - start;
-        }
-    }
+    if (lane < 2 * w) tile_range<M>(bs, w, y0, z0, lane, start, len);
     int incl = len;
 #pragma unroll
     for (int d = 1; d < 32; d <<= 1) {
@@ -445,6 +457,53 @@ __device__ void tile_ranges(const int* __restrict__ bs, int w, int y0, int z0, i
         rpre[lane + 1] = incl;
     }
     if (lane == 0) rpre[0] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Live-tile plan of a spreading pass.  Every tile's candidate count comes from
+// the key starts; tiles without candidates are marked dead and the others are
+// appended to one of kPlanBuckets lists by the size of their candidate set
+// (bucket b holds counts in [2^(b+3), 2^(b+4)), the first and the last
+// open-ended), so that the spreading workgroups take the largest tiles first.
+// plan[0 .. kPlanBuckets) are the bucket sizes and plan[kPlanBuckets] the
+// spreading pass's work counter; the bin scan zeroes them.  A list entry is
+// rotation * tiles + tile, tile = z row * (M / TY) + y tile.
+// ---------------------------------------------------------------------------
+constexpr int kPlanBuckets = plan_buckets();
+
+template <int M>
+__global__ __launch_bounds__(256) void k_tile_plan(const int* __restrict__ bin_start, int w,
+                                                   unsigned char* __restrict__ tile_live, int* __restrict__ plan,
+                                                   int* __restrict__ list, int list_cap) {
+    using SS = SpreadShape<M>;
+    constexpr int TY = SS::TY, NTY = M / TY, TILES = M * NTY;
+    const int tile = blockIdx.x * 256 + threadIdx.x, s = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    int bucket = -1;
+    if (tile < TILES) {
+        const int* bs = bin_start + (size_t)s * (SS::KEYS + 1);
+        const int z0 = tile / NTY, y0 = (tile % NTY) * TY;
+        int ncand = 0;
+        for (int j = 0; j < 2 * w; ++j) {
+            int st0, len;
+            tile_range<M>(bs, w, y0, z0, j, st0, len);
+            ncand += len;
+        }
+        if (ncand == 0) tile_live[(size_t)s * TILES + tile] = 0;
+        else bucket = min(max(31 - __clz(ncand) - 3, 0), kPlanBuckets - 1);
+    }
+    // one atomic per (wave, bucket)
+    unsigned long long todo = __ballot(bucket >= 0);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int b = __shfl(bucket, leader, 64);
+        const unsigned long long same = __ballot(bucket == b);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&plan[b], __popcll(same));
+        base = __shfl(base, leader, 64);
+        if (bucket == b) list[(size_t)b * list_cap + base + __popcll(same & ((1ull << lane) - 1ull))] = s * TILES + tile;
+        todo &= ~same;
+    }
 }
 
 // Stage the filtered knots with filtered rank in [first, first + cap); returns
@@ -512,13 +571,14 @@ __device__ __forceinline__ float fixed_to_float(unsigned long long u, float inv)
     return (float)(d * (double)inv);
 }
 
+// One spreading tile (z row z0, y rows y0 .. y0+TY-1 of rotation s).  Entered
+// by the whole workgroup; the LDS regions are laid out by the caller.
 template <int M>
-__global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __restrict__ bin_start,
-                                                          unsigned char* __restrict__ tile_live,
-                                                          const int* __restrict__ scell, const float* __restrict__ skbw,
-                                                          const float* __restrict__ swts, int64_t nk, int q, int w,
-                                                          int cap, float fix_scale, float fix_inv,
-                                                          float2* __restrict__ out, const float2* __restrict__ twm) {
+__device__ void spread_tile(int s, int z0, int y0, int yt, const int* __restrict__ bin_start,
+                            unsigned char* __restrict__ tile_live, const int* __restrict__ scell,
+                            const float* __restrict__ skbw, const float* __restrict__ swts, int64_t nk, int q, int w,
+                            int cap, float fix_scale, float fix_inv, float2* __restrict__ out, float2* lds,
+                            int* wave_tot, int* rstart, int* rpre) {
     constexpr int H = M / 4;  // half of the n = M/2 kept modes along x
     using SS = SpreadShape<M>;
     constexpr int TY = SS::TY, SC = SS::SC, NPTS = SS::NPTS, LS = SS::LS;
@@ -526,9 +586,6 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __res
     constexpr int U = 4;         // staged knots in flight per wave
     constexpr int CV = NPTS / NT;  // sums converted per thread
     static_assert(NPTS % NT == 0, "tile must split evenly over the workgroup");
-    extern __shared__ float2 lds[];
-    __shared__ int wave_tot[NW];
-    __shared__ int rstart[kMaxRanges], rpre[kMaxRanges + 1];
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds);  // [2][TY][LS]
     float2* a = lds;                                                       // [TY][SC] over the sums
     float2* twl = lds + 2 * TY * LS;                                       // after both planes
@@ -539,39 +596,45 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __res
     st.wz = reinterpret_cast<float*>(st.pos + cap);
     st.wx = st.wz + cap;
     st.wy = st.wx + cap * w;
-    const int y0 = blockIdx.x * TY, z0 = blockIdx.y, s = blockIdx.z;
     const int lo = w / 2 - 1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int dmul = (65536 + w - 1) / w;  // t / w for t < w*w by a multiply
     const int nr = 2 * w;
-    int nfilt = 0;
-    if (nk > 0) {
-        tile_ranges<M>(bin_start + (size_t)s * (SS::KEYS + 1), w, y0, z0, rstart, rpre);
-        __syncthreads();
-        const int* sc_ = scell + (int64_t)s * nk;
-        const float* kb_ = skbw + (int64_t)s * nk * 3 * w;
-        if (rpre[nr] > 0) nfilt = stage_knots<M>(sc_, kb_, w, y0, z0, rstart, rpre, nr, 0, cap, st, wave_tot);
-    }
-    if (threadIdx.x == 0) tile_live[((size_t)s * M + z0) * (M / TY) + blockIdx.x] = nfilt > 0;
-    if (nfilt == 0) return;  // the tile's spectrum is zero and is not written
     const int* sc_ = scell + (int64_t)s * nk;
     const float* kb_ = skbw + (int64_t)s * nk * 3 * w;
     const float* wq_ = swts + (int64_t)s * nk * q;
-    load_table<M, NT>(twl, twm);
+    tile_ranges<M>(bin_start + (size_t)s * (SS::KEYS + 1), w, y0, z0, rstart, rpre);
+    __syncthreads();
+    const int nfilt = rpre[nr] > 0 ? stage_knots<M>(sc_, kb_, w, y0, z0, rstart, rpre, nr, 0, cap, st, wave_tot) : 0;
+    if (threadIdx.x == 0) tile_live[((size_t)s * M + z0) * (M / TY) + yt] = nfilt > 0;
+    if (nfilt == 0) return;  // the tile's spectrum is zero and is not written
     for (int t = threadIdx.x; t < 2 * TY * LS; t += NT) acc[t] = 0ull;
     const int rounds = (nfilt + cap - 1) / cap;
+    // component weights of the pair starting at component c for staged knot i,
+    // times the z weight and the fixed-point scale
+    auto pair_weights = [&](int i, int c) {
+        const float* wp = wq_ + (int64_t)st.pos[i] * q + c;
+        const float f = st.wz[i] * fix_scale;
+        return make_float2(wp[0] * f, c + 1 < q ? wp[1] * f : 0.0f);
+    };
+    if (rounds == 1) {
+        for (int i = threadIdx.x; i < nfilt; i += NT) st.wq[i] = pair_weights(i, 0);
+    }
     for (int cp = 0; cp < q; cp += 2) {
+        // with every knot staged, the next pair's weights are read while this
+        // pair is spread (a thread per staged knot)
+        const bool prefetch = rounds == 1 && cp + 2 < q && (int)threadIdx.x < nfilt;
+        float2 nxt = make_float2(0.f, 0.f);
+        static_assert(kSpreadThreads >= 512, "one staged knot per thread");
         for (int r = 0; r < rounds; ++r) {
-            if (rounds > 1 && (r > 0 || cp > 0))
-                stage_knots<M>(sc_, kb_, w, y0, z0, rstart, rpre, nr, r * cap, cap, st, wave_tot);
-            const int nst = min(cap, nfilt - r * cap);
-            // this pair's component weights, times the z weight and the scale
-            for (int i = threadIdx.x; i < nst; i += NT) {
-                const float* wp = wq_ + (int64_t)st.pos[i] * q + cp;
-                const float f = st.wz[i] * fix_scale;
-                st.wq[i] = make_float2(wp[0] * f, cp + 1 < q ? wp[1] * f : 0.0f);
+            if (rounds > 1) {
+                if (r > 0 || cp > 0)
+                    stage_knots<M>(sc_, kb_, w, y0, z0, rstart, rpre, nr, r * cap, cap, st, wave_tot);
+                for (int i = threadIdx.x; i < min(cap, nfilt - r * cap); i += NT) st.wq[i] = pair_weights(i, cp);
             }
+            if (prefetch) nxt = pair_weights(threadIdx.x, cp + 2);
             __syncthreads();
+            const int nst = min(cap, nfilt - r * cap);
             // each wave takes U staged knots at a time, a lane per window point;
             // the LDS reads of all U (at clamped, valid indices) are issued
             // together, then the atomic adds of the lanes that land in the tile
@@ -603,6 +666,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __res
             }
             __syncthreads();
         }
+        if (prefetch) st.wq[threadIdx.x] = nxt;  // read from the next pair on, after the barriers below
         // sums -> FFT input over the same memory
         float2 cv[CV];
 #pragma unroll
@@ -635,6 +699,48 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __res
             __syncthreads();
             for (int t = threadIdx.x; t < 2 * TY * LS; t += NT) acc[t] = 0ull;
         }
+    }
+}
+
+// Persistent spreading pass: each workgroup takes tiles of the plan's lists
+// (largest candidate sets first) from a shared counter until none are left.
+template <int M>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __restrict__ bin_start,
+                                                                unsigned char* __restrict__ tile_live,
+                                                                int* __restrict__ plan, const int* __restrict__ list,
+                                                                int list_cap, const int* __restrict__ scell,
+                                                                const float* __restrict__ skbw,
+                                                                const float* __restrict__ swts, int64_t nk, int q,
+                                                                int w, int cap, float fix_scale, float fix_inv,
+                                                                float2* __restrict__ out,
+                                                                const float2* __restrict__ twm) {
+    using SS = SpreadShape<M>;
+    constexpr int NTY = M / SS::TY, TILES = M * NTY;
+    extern __shared__ float2 lds[];
+    __shared__ int wave_tot[kSpreadThreads / 64];
+    __shared__ int rstart[kMaxRanges], rpre[kMaxRanges + 1];
+    __shared__ int first[kPlanBuckets], size[kPlanBuckets], cur, total;
+    load_table<M, kSpreadThreads>(lds + 2 * SS::TY * SS::LS, twm);
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int b = kPlanBuckets - 1; b >= 0; --b) {
+            first[b] = run;
+            size[b] = plan[b];
+            run += size[b];
+        }
+        total = run;
+    }
+    for (;;) {
+        if (threadIdx.x == 0) cur = atomicAdd(&plan[kPlanBuckets], 1);
+        __syncthreads();
+        const int k = cur;
+        if (k >= total) break;
+        int b = kPlanBuckets - 1;
+        while (k >= first[b] + size[b]) --b;
+        const int id = list[(size_t)b * list_cap + (k - first[b])];
+        const int s = id / TILES, tile = id % TILES;
+        spread_tile<M>(s, tile / NTY, (tile % NTY) * SS::TY, tile % NTY, bin_start, tile_live, scell, skbw, swts,
+                       nk, q, w, cap, fix_scale, fix_inv, out, lds, wave_tot, rstart, rpre);
     }
 }
 
@@ -993,7 +1099,9 @@ hipError_t with_m(int m, F&& f) {
     return hipGetLastError();
 }
 
-constexpr size_t kSpreadLds = 80 * 1024;  // two spreading workgroups per CU
+// two spreading workgroups per CU: dynamic LDS plus the kernel's static arrays
+// must fit in half of the 160 KB
+constexpr size_t kSpreadLds = 79 * 1024;
 
 // bytes of one staged knot: component pair, cell, position, z weight, x and y weights
 inline size_t staged_bytes(int w) { return 20 + 8 * (size_t)w; }
@@ -1048,15 +1156,28 @@ hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const 
 
 hipError_t launch_bin_sort(const Geom& g, int S, int64_t nk, int q, const int* d_cell, const float* d_kbw,
                            const float* d_wts, const int* d_rank, int* d_counts, int* d_bin_start, int* d_scell,
-                           float* d_skbw, float* d_swts, hipStream_t st) {
+                           float* d_skbw, float* d_swts, int* d_plan, hipStream_t st) {
     if (nk == 0 || S == 0) return hipSuccess;
     const int G = bin_ygroup(g.m), keys = bin_keys(g.m);
-    hipLaunchKernelGGL(k_bin_scan, dim3(S), dim3(kScanThreads), 0, st, d_counts, keys, nk, d_bin_start);
+    hipLaunchKernelGGL(k_bin_scan, dim3(S), dim3(kScanThreads), 0, st, d_counts, keys, nk, d_bin_start, d_plan,
+                       plan_words());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_scatter, dim3(bin_blocks(nk), S), dim3(kBinBlock), 0, st, d_cell, d_kbw, d_wts, d_rank,
                        d_bin_start, nk, keys, log2i(G), g.m / G, g.w, q, d_scell, d_skbw, d_swts);
     return hipGetLastError();
+}
+
+int plan_words() { return kPlanBuckets + 1; }
+
+hipError_t launch_tile_plan(const Geom& g, int S, const Occupancy& occ, int* d_plan, int* d_list, hipStream_t st) {
+    if (occ.nk == 0 || S == 0) return hipSuccess;
+    return with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        constexpr int tiles = M * (M / SpreadShape<M>::TY);
+        hipLaunchKernelGGL(k_tile_plan<M>, dim3((tiles + 255) / 256, S), dim3(256), 0, st, occ.bin_start, g.w,
+                           occ.tile_live, d_plan, d_list, S * tiles);
+    });
 }
 
 size_t max_lds_bytes(const Geom& g, int qmax) {
@@ -1082,16 +1203,17 @@ int spread_tiles(const Geom& g) {
     return t;
 }
 
-hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, const int* d_scell, const float* d_skbw,
-                              const float* d_swts, int q, float fix_scale, float2* d_out, const float2* d_twm,
-                              hipStream_t st) {
-    if (S == 0) return hipSuccess;
+hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, int* d_plan, const int* d_list,
+                              const int* d_scell, const float* d_skbw, const float* d_swts, int q, float fix_scale,
+                              float2* d_out, const float2* d_twm, hipStream_t st) {
+    if (S == 0 || occ.nk == 0) return hipSuccess;
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
-        constexpr int TY = SpreadShape<M>::TY;
-        hipLaunchKernelGGL(k_spread_fftx<M>, dim3(M / TY, M, S), dim3(kSpreadThreads), spread_lds_t<M>(g.w), st,
-                           occ.bin_start, occ.tile_live, d_scell, d_skbw, d_swts, occ.nk, q, g.w,
-                           spread_cap_t<M>(g.w), fix_scale, 1.0f / fix_scale, d_out, d_twm);
+        constexpr int tiles = M * (M / SpreadShape<M>::TY);
+        hipLaunchKernelGGL(k_spread_fftx<M>, dim3(std::max(1, g.spread_wgs)), dim3(kSpreadThreads),
+                           spread_lds_t<M>(g.w), st, occ.bin_start, occ.tile_live, d_plan, d_list, S * tiles, d_scell,
+                           d_skbw, d_swts, occ.nk, q, g.w, spread_cap_t<M>(g.w), fix_scale, 1.0f / fix_scale, d_out,
+                           d_twm);
     });
 }
 
