@@ -126,8 +126,8 @@ int corr_spectrum(corr_ctx* ctx, int32_t which, const double* quat_wxyz, float* 
 int corr_info(const corr_ctx* ctx, corr_info_t* out);
 
 /* Stage ids reported by corr_profile_read. */
-#define CORR_STAGE_ROTATE         0  /* a0: turn and place the knots, window weights  */
-#define CORR_STAGE_BIN            1  /* a0: stable counting sort of knots by z-cell    */
+#define CORR_STAGE_ROTATE         0  /* a0: turn, place, window weights, sort keys    */
+#define CORR_STAGE_BIN            1  /* a0: sorted knot records + live-tile plan      */
 #define CORR_STAGE_SPREAD_FFT_X   2  /* a1 + a2: spreading fused with the x pass      */
 #define CORR_STAGE_FFT_Y          3  /* a2: forward y pass                            */
 #define CORR_STAGE_FFT_Z_SPECTRUM 4  /* a2 z pass + a3, for A or corr_spectrum        */

@@ -305,6 +305,7 @@ struct Workspace {
     int* bin_start = nullptr;      // [slots][keys + 1] first sorted knot of each key
     unsigned char* tile_live = nullptr;  // [slots][m][y tiles] spreading tiles that some knot reaches
     int* plan = nullptr;           // bucket sizes and work counter of the spreading pass's live-tile plan
+    int* done = nullptr;           // [slots] arrival counters of the sort's workgroups; zero between passes
     int* list = nullptr;           // [buckets][slots * tiles] live tiles
     int* scell = nullptr;          // [slots][nk] sorted by z-cell: packed cell
     float* skbw = nullptr;         // [slots][nk][3][w]              window weights
@@ -330,6 +331,8 @@ struct Workspace {
         bin_start = mem.alloc<int>(S * r.bins);
         tile_live = mem.alloc<unsigned char>(S * r.tiles);
         plan = mem.alloc<int>(corr::plan_words());
+        done = mem.alloc<int>(S);
+        hip_check(hipMemsetAsync(done, 0, sizeof(int) * S, st), "hipMemsetAsync");
         list = mem.alloc<int>(S * r.list);
         scell = mem.alloc<int>(S * r.nk);
         skbw = mem.alloc<float>(S * r.nkw);
@@ -495,14 +498,12 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
     const Geom& g = c->g;
     const int q = s.ex.q;
     stage(c, CORR_STAGE_ROTATE, "rotate", [&] {
-        return corr::launch_rotate_bin(g, d_quats, S, s.pos, s.n, c->ws->cell, c->ws->kbw, c->ws->rank, c->ws->counts, c->stream);
+        return corr::launch_rotate_bin(g, d_quats, S, s.pos, s.n, c->ws->cell, c->ws->kbw, c->ws->rank, c->ws->counts,
+                                       c->ws->done, c->ws->bin_start, c->ws->plan, c->stream);
     });
     stage(c, CORR_STAGE_BIN, "bin", [&] {
-        hip_check(corr::launch_bin_sort(g, S, s.n, q, c->ws->cell, c->ws->kbw, s.wts, c->ws->rank, c->ws->counts,
-                                        c->ws->bin_start, c->ws->scell, c->ws->skbw, c->ws->swts, c->ws->plan,
-                                        c->stream),
-                  "bin");
-        return corr::launch_tile_plan(g, S, occupancy(c, s), c->ws->plan, c->ws->list, c->stream);
+        return corr::launch_scatter_plan(g, S, q, occupancy(c, s), c->ws->cell, c->ws->kbw, s.wts, c->ws->rank,
+                                         c->ws->scell, c->ws->skbw, c->ws->swts, c->ws->plan, c->ws->list, c->stream);
     });
     stage(c, CORR_STAGE_SPREAD_FFT_X, "spread + fft x", [&] {
         return corr::launch_spread_fftx(g, S, occupancy(c, s), c->ws->plan, c->ws->list, c->ws->scell, c->ws->skbw,

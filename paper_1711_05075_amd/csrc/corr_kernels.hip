@@ -248,92 +248,125 @@ __global__ void k_ball_table(int m2n, double dk, const double* __restrict__ node
 // ---------------------------------------------------------------------------
 constexpr int kBinBlock = 256;
 
-__global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restrict__ quats,
-                                                          const double* __restrict__ pos, int64_t nk, double inv_hf,
-                                                          int m, int w, float beta, float inv_i0beta, int yshift,
-                                                          int nyb, int* __restrict__ cell, float* __restrict__ kbw,
-                                                          int* __restrict__ rank, int* __restrict__ counts) {
-    const int64_t j = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
-    const int s = blockIdx.y;
-    if (j >= nk) return;
-    const double* q = quats + 4 * s;
-    double nn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    double qw = q[0] / nn, x = q[1] / nn, y = q[2] / nn, z = q[3] / nn;
-    double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - qw * z),    2 * (x * z + qw * y),
-                   2 * (x * y + qw * z),    1 - 2 * (x * x + z * z), 2 * (y * z - qw * x),
-                   2 * (x * z - qw * y),    2 * (y * z + qw * x),    1 - 2 * (x * x + y * y)};
-    double px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
-    double u[3] = {(R[0] * px + R[1] * py + R[2] * pz) * inv_hf, (R[3] * px + R[4] * py + R[5] * pz) * inv_hf,
-                   (R[6] * px + R[7] * py + R[8] * pz) * inv_hf};
-    const float tw = 2.0f / (float)w;
-    const int lo = w / 2 - 1;
-    int c[3];
-    float* kw = kbw + ((int64_t)s * nk + j) * 3 * w;
-    for (int d = 0; d < 3; ++d) {
-        double fl = floor(u[d]);
-        float f = (float)(u[d] - fl);
-        long long ci = (long long)fl % m;
-        if (ci < 0) ci += m;
-        c[d] = (int)ci;
-        if (f >= 1.0f) {
-            f = 0.0f;
-            c[d] = (c[d] + 1) % m;
-        }
-        for (int i = 0; i < w; ++i) kw[d * w + i] = kb_window(f - (float)(i - lo), tw, beta, inv_i0beta);
-    }
-    cell[(int64_t)s * nk + j] = c[0] | (c[1] << 10) | (c[2] << 20);
-    const int key = c[2] * nyb + (c[1] >> yshift);
-    rank[(int64_t)s * nk + j] = atomicAdd(&counts[(size_t)s * m * nyb + key], 1);
-}
-
-// Exclusive scan of counts[s][key] into bin_start[s][key] (bin_start[s][keys]
-// = nk), one workgroup per rotation; the counters are cleared for the next use.
-constexpr int kScanThreads = 1024;
-
-__global__ __launch_bounds__(kScanThreads) void k_bin_scan(int* __restrict__ counts, int keys, int64_t nk,
-                                                           int* __restrict__ bin_start, int* __restrict__ plan,
-                                                           int nplan) {
-    __shared__ int wsum[kScanThreads / 64];
-    const int s = blockIdx.x;
-    int* c = counts + (size_t)s * keys;
-    int* bs = bin_start + (size_t)s * (keys + 1);
-    const int per = (keys + kScanThreads - 1) / kScanThreads;
-    const int b0 = min(keys, (int)threadIdx.x * per), b1 = min(keys, b0 + per);
-    int sum = 0;
-    for (int i = b0; i < b1; ++i) sum += c[i];
-    // inclusive scan of the per-thread sums: within each wave, then over waves
+// Exclusive scan of the per-thread values v over a kBinBlock-thread block;
+// returns the sum over lower threads.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* wsum) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int incl = sum;
+    int incl = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        const int v = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += v;
+        const int u = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += u;
     }
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
     int before = 0;
-    for (int v = 0; v < wave; ++v) before += wsum[v];
-    int run = before + incl - sum;
-    for (int i = b0; i < b1; ++i) {
-        const int v = c[i];
-        bs[i] = run;
-        c[i] = 0;
-        run += v;
-    }
-    if (threadIdx.x == 0) bs[keys] = (int)nk;
-    if (s == 0 && (int)threadIdx.x < nplan) plan[threadIdx.x] = 0;  // counters of the tile plan that follows
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    return before + incl - v;
 }
 
-// Scatter each knot's record into sorted position: its packed cell, its window
-// weights and its q component weights.
-__global__ __launch_bounds__(kBinBlock) void k_bin_scatter(const int* __restrict__ cell, const float* __restrict__ kbw,
-                                                           const float* __restrict__ wts, const int* __restrict__ rank,
-                                                           const int* __restrict__ bin_start, int64_t nk, int keys,
-                                                           int yshift, int nyb, int w, int q, int* __restrict__ scell,
-                                                           float* __restrict__ skbw, float* __restrict__ swts) {
+// Key starts from the counts of one rotation, PER consecutive keys per thread
+// of a kBinBlock-thread block; clears the counts.
+template <int PER>
+__device__ __forceinline__ void scan_counts(int* __restrict__ cs, int* __restrict__ bs, int* wsum) {
+    static_assert(PER % 4 == 0, "whole int4 per thread");
+    const int b0 = threadIdx.x * PER;
+    int v[PER];
+#pragma unroll
+    for (int k = 0; k < PER / 4; ++k) {
+        const int4 x = reinterpret_cast<const int4*>(cs + b0)[k];
+        v[4 * k] = x.x; v[4 * k + 1] = x.y; v[4 * k + 2] = x.z; v[4 * k + 3] = x.w;
+    }
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) sum += v[k];
+    int run = block_exclusive_scan(sum, wsum);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int c = v[k];
+        v[k] = run;
+        run += c;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) bs[b0 + k] = v[k];  // bs rows are keys + 1 long: not 16-byte aligned
+#pragma unroll
+    for (int k = 0; k < PER / 4; ++k) reinterpret_cast<int4*>(cs + b0)[k] = make_int4(0, 0, 0, 0);
+}
+
+// Rotate + place + window weights + counts per key.  The last workgroup of a
+// rotation to finish (a per-rotation counter, reset afterwards) turns that
+// rotation's counts into the key starts bin_start[s][0 .. keys] and clears the
+// counts.  Workgroup (0, 0) also clears the tile plan's counters.
+__global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restrict__ quats,
+                                                          const double* __restrict__ pos, int64_t nk, double inv_hf,
+                                                          int m, int w, float beta, float inv_i0beta, int yshift,
+                                                          int nyb, int* __restrict__ cell, float* __restrict__ kbw,
+                                                          int* __restrict__ rank, int* __restrict__ counts,
+                                                          int* __restrict__ done, int* __restrict__ bin_start,
+                                                          int* __restrict__ plan, int nplan) {
+    __shared__ int last;
+    __shared__ int wsum[kBinBlock / 64];
     const int64_t j = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
     const int s = blockIdx.y;
-    if (j >= nk) return;
+    const int keys = m * nyb;
+    if (blockIdx.x == 0 && s == 0 && (int)threadIdx.x < nplan) plan[threadIdx.x] = 0;
+    if (j < nk) {
+        const double* q = quats + 4 * s;
+        double nn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        double qw = q[0] / nn, x = q[1] / nn, y = q[2] / nn, z = q[3] / nn;
+        double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - qw * z),    2 * (x * z + qw * y),
+                       2 * (x * y + qw * z),    1 - 2 * (x * x + z * z), 2 * (y * z - qw * x),
+                       2 * (x * z - qw * y),    2 * (y * z + qw * x),    1 - 2 * (x * x + y * y)};
+        double px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
+        double u[3] = {(R[0] * px + R[1] * py + R[2] * pz) * inv_hf, (R[3] * px + R[4] * py + R[5] * pz) * inv_hf,
+                       (R[6] * px + R[7] * py + R[8] * pz) * inv_hf};
+        const float tw = 2.0f / (float)w;
+        const int lo = w / 2 - 1;
+        int c[3];
+        float* kw = kbw + ((int64_t)s * nk + j) * 3 * w;
+        for (int d = 0; d < 3; ++d) {
+            double fl = floor(u[d]);
+            float f = (float)(u[d] - fl);
+            long long ci = (long long)fl % m;
+            if (ci < 0) ci += m;
+            c[d] = (int)ci;
+            if (f >= 1.0f) {
+                f = 0.0f;
+                c[d] = (c[d] + 1) % m;
+            }
+            for (int i = 0; i < w; ++i) kw[d * w + i] = kb_window(f - (float)(i - lo), tw, beta, inv_i0beta);
+        }
+        cell[(int64_t)s * nk + j] = c[0] | (c[1] << 10) | (c[2] << 20);
+        const int key = c[2] * nyb + (c[1] >> yshift);
+        rank[(int64_t)s * nk + j] = atomicAdd(&counts[(size_t)s * keys + key], 1);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&done[s], 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // acquire: the other workgroups' counts are visible to plain loads
+    int* cs = counts + (size_t)s * keys;
+    int* bs = bin_start + (size_t)s * (keys + 1);
+    switch (keys / kBinBlock) {  // keys is 1024, 4096 or 8192
+        case 4: scan_counts<4>(cs, bs, wsum); break;
+        case 16: scan_counts<16>(cs, bs, wsum); break;
+        default: scan_counts<32>(cs, bs, wsum); break;
+    }
+    if (threadIdx.x == 0) {
+        bs[keys] = (int)nk;
+        done[s] = 0;
+    }
+}
+
+// Scatter knot j of rotation s into sorted position: its packed cell, its
+// window weights and its q component weights.
+__device__ __forceinline__ void bin_scatter(int64_t j, int s, const int* __restrict__ cell,
+                                            const float* __restrict__ kbw, const float* __restrict__ wts,
+                                            const int* __restrict__ rank, const int* __restrict__ bin_start,
+                                            int64_t nk, int keys, int yshift, int nyb, int w, int q,
+                                            int* __restrict__ scell, float* __restrict__ skbw,
+                                            float* __restrict__ swts) {
     const int packed = cell[(int64_t)s * nk + j];
     const int key = ((packed >> 20) & 1023) * nyb + (((packed >> 10) & 1023) >> yshift);
     const int64_t p = (int64_t)s * nk + bin_start[(size_t)s * (keys + 1) + key] + rank[(int64_t)s * nk + j];
@@ -472,12 +505,11 @@ __device__ void tile_ranges(const int* __restrict__ bs, int w, int y0, int z0, i
 constexpr int kPlanBuckets = plan_buckets();
 
 template <int M>
-__global__ __launch_bounds__(256) void k_tile_plan(const int* __restrict__ bin_start, int w,
-                                                   unsigned char* __restrict__ tile_live, int* __restrict__ plan,
-                                                   int* __restrict__ list, int list_cap) {
+__device__ __forceinline__ void tile_plan(int tile, int s, const int* __restrict__ bin_start, int w,
+                                          unsigned char* __restrict__ tile_live, int* __restrict__ plan,
+                                          int* __restrict__ list, int list_cap) {
     using SS = SpreadShape<M>;
     constexpr int TY = SS::TY, NTY = M / TY, TILES = M * NTY;
-    const int tile = blockIdx.x * 256 + threadIdx.x, s = blockIdx.y;
     const int lane = threadIdx.x & 63;
     int bucket = -1;
     if (tile < TILES) {
@@ -504,6 +536,27 @@ __global__ __launch_bounds__(256) void k_tile_plan(const int* __restrict__ bin_s
         if (bucket == b) list[(size_t)b * list_cap + base + __popcll(same & ((1ull << lane) - 1ull))] = s * TILES + tile;
         todo &= ~same;
     }
+}
+
+// The scatter of the sorted records (workgroups x < nscatter) and the live-tile
+// plan (the others) of one spreading pass, both reading the key starts.
+template <int M>
+__global__ __launch_bounds__(256) void k_scatter_plan(const int* __restrict__ cell, const float* __restrict__ kbw,
+                                                      const float* __restrict__ wts, const int* __restrict__ rank,
+                                                      const int* __restrict__ bin_start, int64_t nk, int yshift,
+                                                      int nyb, int w, int q, int* __restrict__ scell,
+                                                      float* __restrict__ skbw, float* __restrict__ swts,
+                                                      int nscatter, unsigned char* __restrict__ tile_live,
+                                                      int* __restrict__ plan, int* __restrict__ list, int list_cap) {
+    const int s = blockIdx.y;
+    if ((int)blockIdx.x < nscatter) {
+        const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+        if (j < nk)
+            bin_scatter(j, s, cell, kbw, wts, rank, bin_start, nk, SpreadShape<M>::KEYS, yshift, nyb, w, q, scell,
+                        skbw, swts);
+        return;
+    }
+    tile_plan<M>(((int)blockIdx.x - nscatter) * 256 + threadIdx.x, s, bin_start, w, tile_live, plan, list, list_cap);
 }
 
 // Stage the filtered knots with filtered rank in [first, first + cap); returns
@@ -756,45 +809,51 @@ __device__ __forceinline__ int kept_source(int o) {
 template <int M>
 struct ColShape {
     static constexpr int N = M / 2, H = N / 2;
-    static constexpr int COLS = cmin<H, 4096 / M>();          // forward y / z passes
+    static constexpr int COLS = cmin<H, 4096 / M>();          // forward y pass
+    static constexpr int ZCOLS = cmin<H, 2048 / M>();         // z passes
+    static constexpr int YZB = 1;                              // z rows per y-pass workgroup
     static constexpr int ICOLS = cmin<H, 4096 / N>();         // inverse y pass
     static constexpr int XCOLS = cmin<N * N / 2, 4096 / N>(); // inverse x pass (line pairs)
 };
 
 // a2: y pass over [slab][z][y][mx] -> [slab][z][my][mx], M points pruned to N,
-// slab = rotation * q + component.  Dead z rows are skipped (their output is
-// never read); rows of dead y tiles are zero.
+// slab = rotation * q + component.  A workgroup takes YZB z rows of one slab
+// and column block; dead z rows are skipped (their output is never read) and
+// rows of dead y tiles are zero.
 template <int M>
 __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ in, float2* __restrict__ out,
                                                     const float2* __restrict__ twm, int q,
                                                     const int* __restrict__ bin_start,
                                                     const unsigned char* __restrict__ tile_live, int64_t nk, int w) {
-    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS;
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, YZB = ColShape<M>::YZB;
     constexpr int TY = SpreadShape<M>::TY, NT = M / TY;
     extern __shared__ float2 lds[];
     __shared__ unsigned char live[NT];
     float2* a = lds;
     float2* twl = a + M * COLS;
-    const int z = blockIdx.y, s = blockIdx.z / q;
-    if (!zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, z)) return;
-    load_table<M>(twl, twm);
-    for (int t = threadIdx.x; t < NT; t += kThreads) live[t] = tile_live[((size_t)s * M + z) * NT + t];
-    __syncthreads();
+    const int s = blockIdx.z / q;
+    const int* bs = bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1);
     const int c0 = blockIdx.x * COLS;
-    const size_t plane = (size_t)blockIdx.z * M + z;  // slab * M + z
-    const float2* src = in + plane * M * H + c0;
-    for (int t = threadIdx.x; t < M * COLS; t += kThreads) {
-        const int y = t / COLS;
-        a[t] = live[y / TY] ? src[(size_t)y * H + t % COLS] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    fft_cols<M, -1, COLS, false>(a, twl);
-    const float2* res = a;
-    float2* dst = out + plane * N * H + c0;
-    for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
-        const int o = t / COLS, c = t % COLS;
-        const int si = kept_source<N, M>(o);
-        dst[(size_t)o * H + c] = si < 0 ? make_float2(0.f, 0.f) : res[si * COLS + c];
+    load_table<M>(twl, twm);
+    for (int z = blockIdx.y * YZB; z < blockIdx.y * YZB + YZB; ++z) {
+        if (!zrow_live<M>(bs, nk, w, z)) continue;
+        __syncthreads();  // the previous row's output has been read out of `a`
+        for (int t = threadIdx.x; t < NT; t += kThreads) live[t] = tile_live[((size_t)s * M + z) * NT + t];
+        __syncthreads();
+        const size_t plane = (size_t)blockIdx.z * M + z;  // slab * M + z
+        const float2* src = in + plane * M * H + c0;
+        for (int t = threadIdx.x; t < M * COLS; t += kThreads) {
+            const int y = t / COLS;
+            a[t] = live[y / TY] ? src[(size_t)y * H + t % COLS] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        fft_cols<M, -1, COLS, false>(a, twl);
+        float2* dst = out + plane * N * H + c0;
+        for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
+            const int o = t / COLS, c = t % COLS;
+            const int si = kept_source<N, M>(o);
+            dst[(size_t)o * H + c] = si < 0 ? make_float2(0.f, 0.f) : a[si * COLS + c];
+        }
     }
 }
 
@@ -803,7 +862,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ i
 // (thread t holds entries t + k*kThreads of the [mz][col] block).
 template <int M>
 struct ZAcc {
-    static constexpr int N = M / 2, COLS = ColShape<M>::COLS;
+    static constexpr int N = M / 2, COLS = ColShape<M>::ZCOLS;
     static constexpr int PER = (N * COLS + kThreads - 1) / kThreads;
 };
 
@@ -813,7 +872,7 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
                                              const float* __restrict__ vtab, int m2n, float2* a,
                                              const float2* twl, const unsigned char* zlive,
                                              float2 (&acc)[ZAcc<M>::PER]) {
-    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ZCOLS, PER = ZAcc<M>::PER;
     constexpr int LD = (M * COLS + kThreads - 1) / kThreads;  // column values per thread
     const int my = iy < N / 2 ? iy : iy - N;
 #pragma unroll
@@ -832,6 +891,19 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
             }
         }
     };
+    // the ball-transform entries of every kept output, read one component ahead
+    int vidx[PER];
+    float vcur[PER], vnxt[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * kThreads;
+        const int o = t / COLS, cc = t % COLS;
+        const int mz = o < N / 2 ? o : o - N, mx = c0 + cc;
+        const bool kept = t < N * COLS && kept_source<N, M>(o) >= 0;
+        vidx[k] = kept ? mx * mx + my * my + mz * mz : -1;
+        vcur[k] = kept ? vtab[vidx[k]] : 0.f;
+        vnxt[k] = 0.f;
+    }
     fetch(0);
     for (int c = 0; c < q; ++c) {
 #pragma unroll
@@ -839,24 +911,24 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
             const int t = k * kThreads + (int)threadIdx.x;
             if ((M * COLS) % kThreads == 0 || t < M * COLS) a[t] = nxt[k];
         }
-        if (c + 1 < q) fetch(c + 1);
+        if (c + 1 < q) {
+            fetch(c + 1);
+            const float* vt = vtab + (size_t)(c + 1) * m2n;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) vnxt[k] = vidx[k] >= 0 ? vt[vidx[k]] : 0.f;
+        }
         __syncthreads();
         fft_cols<M, -1, COLS, false>(a, twl);
-        const float* vt = vtab + (size_t)c * m2n;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int t = threadIdx.x + k * kThreads;
-            if (t < N * COLS) {
+            if (vidx[k] >= 0) {
+                const int t = threadIdx.x + k * kThreads;
                 const int o = t / COLS, cc = t % COLS;
-                const int si = kept_source<N, M>(o);
-                if (si >= 0) {
-                    const int mz = o < N / 2 ? o : o - N, mx = c0 + cc;
-                    const float v = vt[mx * mx + my * my + mz * mz];
-                    const float2 g = a[si * COLS + cc];
-                    acc[k].x += v * g.x;
-                    acc[k].y += v * g.y;
-                }
+                const float2 g = a[kept_source<N, M>(o) * COLS + cc];
+                acc[k].x += vcur[k] * g.x;
+                acc[k].y += vcur[k] * g.y;
             }
+            vcur[k] = vnxt[k];
         }
         __syncthreads();
     }
@@ -869,7 +941,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __res
                                                              const double* __restrict__ deconv,
                                                              float2* __restrict__ spec, const float2* __restrict__ twm,
                                                              const int* __restrict__ bin_start, int64_t nk, int w) {
-    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ZCOLS, PER = ZAcc<M>::PER;
     extern __shared__ float2 lds[];
     __shared__ unsigned char zlive[M];
     float2* a = lds;
@@ -908,7 +980,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
                                                             const float2* __restrict__ twm,
                                                             const float2* __restrict__ twn,
                                                             const int* __restrict__ bin_start, int64_t nk, int w) {
-    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, PER = ZAcc<M>::PER;
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ZCOLS, PER = ZAcc<M>::PER;
     extern __shared__ float2 lds[];
     __shared__ unsigned char zlive[M];
     float2* a = lds;
@@ -1146,37 +1218,30 @@ int bin_blocks(int64_t nk) { return (int)((nk + kBinBlock - 1) / kBinBlock); }
 }  // namespace
 
 hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const double* d_pos, int64_t nk,
-                             int* d_cell, float* d_kbw, int* d_rank, int* d_counts, hipStream_t st) {
+                             int* d_cell, float* d_kbw, int* d_rank, int* d_counts, int* d_done, int* d_bin_start,
+                             int* d_plan, hipStream_t st) {
     if (nk == 0 || S == 0) return hipSuccess;
     const int G = bin_ygroup(g.m);
     hipLaunchKernelGGL(k_rotate_bin, dim3(bin_blocks(nk), S), dim3(kBinBlock), 0, st, d_quats, d_pos, nk, g.inv_hf,
-                       g.m, g.w, g.beta, g.inv_i0beta, log2i(G), g.m / G, d_cell, d_kbw, d_rank, d_counts);
-    return hipGetLastError();
-}
-
-hipError_t launch_bin_sort(const Geom& g, int S, int64_t nk, int q, const int* d_cell, const float* d_kbw,
-                           const float* d_wts, const int* d_rank, int* d_counts, int* d_bin_start, int* d_scell,
-                           float* d_skbw, float* d_swts, int* d_plan, hipStream_t st) {
-    if (nk == 0 || S == 0) return hipSuccess;
-    const int G = bin_ygroup(g.m), keys = bin_keys(g.m);
-    hipLaunchKernelGGL(k_bin_scan, dim3(S), dim3(kScanThreads), 0, st, d_counts, keys, nk, d_bin_start, d_plan,
-                       plan_words());
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_scatter, dim3(bin_blocks(nk), S), dim3(kBinBlock), 0, st, d_cell, d_kbw, d_wts, d_rank,
-                       d_bin_start, nk, keys, log2i(G), g.m / G, g.w, q, d_scell, d_skbw, d_swts);
+                       g.m, g.w, g.beta, g.inv_i0beta, log2i(G), g.m / G, d_cell, d_kbw, d_rank, d_counts, d_done,
+                       d_bin_start, d_plan, plan_words());
     return hipGetLastError();
 }
 
 int plan_words() { return kPlanBuckets + 1; }
 
-hipError_t launch_tile_plan(const Geom& g, int S, const Occupancy& occ, int* d_plan, int* d_list, hipStream_t st) {
+hipError_t launch_scatter_plan(const Geom& g, int S, int q, const Occupancy& occ, const int* d_cell,
+                               const float* d_kbw, const float* d_wts, const int* d_rank, int* d_scell, float* d_skbw,
+                               float* d_swts, int* d_plan, int* d_list, hipStream_t st) {
     if (occ.nk == 0 || S == 0) return hipSuccess;
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         constexpr int tiles = M * (M / SpreadShape<M>::TY);
-        hipLaunchKernelGGL(k_tile_plan<M>, dim3((tiles + 255) / 256, S), dim3(256), 0, st, occ.bin_start, g.w,
-                           occ.tile_live, d_plan, d_list, S * tiles);
+        const int G = bin_ygroup(M);
+        const int nscatter = bin_blocks(occ.nk);
+        hipLaunchKernelGGL(k_scatter_plan<M>, dim3(nscatter + (tiles + 255) / 256, S), dim3(256), 0, st, d_cell, d_kbw,
+                           d_wts, d_rank, occ.bin_start, occ.nk, log2i(G), M / G, g.w, q, d_scell, d_skbw, d_swts,
+                           nscatter, occ.tile_live, d_plan, d_list, S * tiles);
     });
 }
 
@@ -1223,7 +1288,7 @@ hipError_t launch_fft_y(const Geom& g, int S, int q, const Occupancy& occ, const
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
-        hipLaunchKernelGGL(k_fft_y<M>, dim3(C::H / C::COLS, M, S * q), dim3(kThreads),
+        hipLaunchKernelGGL(k_fft_y<M>, dim3(C::H / C::COLS, M / C::YZB, S * q), dim3(kThreads),
                            sizeof(float2) * ((size_t)M * C::COLS + M), st, d_in, d_out, d_twm, q, occ.bin_start,
                            occ.tile_live, occ.nk, g.w);
     });
@@ -1235,8 +1300,8 @@ hipError_t launch_fft_z_spectrum(const Geom& g, const float2* d_in, int S, int q
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
-        hipLaunchKernelGGL(k_fft_z_spectrum<M>, dim3(C::H / C::COLS, C::N, S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)M * C::COLS + M), st, d_in, q, d_vtab, g.m2n, d_deconv,
+        hipLaunchKernelGGL(k_fft_z_spectrum<M>, dim3(C::H / C::ZCOLS, C::N, S), dim3(kThreads),
+                           sizeof(float2) * ((size_t)M * C::ZCOLS + M), st, d_in, q, d_vtab, g.m2n, d_deconv,
                            d_spec, d_twm, occ.bin_start, occ.nk, g.w);
     });
 }
@@ -1247,8 +1312,8 @@ hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q,
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
-        hipLaunchKernelGGL(k_fft_z_product<M>, dim3(C::H / C::COLS, C::N, S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)M * C::COLS + M + C::N), st, d_in, q, d_vtab, g.m2n,
+        hipLaunchKernelGGL(k_fft_z_product<M>, dim3(C::H / C::ZCOLS, C::N, S), dim3(kThreads),
+                           sizeof(float2) * ((size_t)M * C::ZCOLS + M + C::N), st, d_in, q, d_vtab, g.m2n,
                            d_phase, d_fa, d_out, d_twm, d_twn, occ.bin_start, occ.nk, g.w);
     });
 }
