@@ -26,26 +26,56 @@ import synth  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
-def stage_bytes(info, n_rot_per_launch, n_b):
-    """Algorithmic HBM bytes of one launch of each stage: every stage reads its
-    input once and writes its output once (float32 grids, complex64 spectra)."""
-    n, m = info["n"], info["m"]
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1711_05075_amd", "csrc", "corr_kernels.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_spread_fftx_single_rotation_4096_n128.txt")
+
+
+def stage_bytes(info, pa, pb):
+    """Algorithmic HBM bytes of one launch of each stage for this workload.
+
+    pa / pb are the occupancy reports of the A and B spreading passes
+    (corr_pass_info): only live tiles are spread and written, and the later
+    passes read only live z rows.  Each stage reads its inputs once and writes
+    its outputs once: knot records (cell 4 B, window weights 12 w B, component
+    weights 4 q B), complex64 spectra, float32 scores.  Stages that run once per
+    shape (rotate, bin, spread, fft_y) are averaged over the A and B launches.
+    """
+    n, w = info["n"], info["kb_width"]
     h = n // 2
-    S = n_rot_per_launch
-    qb = info["q_b"]
-    w = info["kb_width"]
-    xout = 8 * qb * m * m * h
-    yout = 8 * qb * m * n * h
     spec = 8 * n * n * h
-    return {
-        "rotate": S * n_b * (24 + 8 + 12 * w),
-        "bin": S * n_b * 12,
-        "spread_fft_x": S * (n_b * (8 + 12 * w + 4 * qb) + xout),
-        "fft_y": S * (xout + yout),
-        "fft_z_product": S * (yout + 2 * spec) + spec,
-        "ifft_y": S * 2 * spec,
-        "ifft_x": S * (spec + 4 * n ** 3),
-    }
+
+    def per_shape(p):
+        q, k, ty, m = p["q"], p["knots"], p["tile_rows"], p["m"]
+        rec = k * (4 + 12 * w + 4 * q)
+        tile_out = p["live_tiles"] * ty * (m // 4) * 8 * q  # kept x modes of every line of a live tile
+        rows_out = p["live_rows"] * n * h * 8 * q             # kept y modes of every live z row
+        return {"rotate": k * (24 + 12 * w + 8), "bin": k * 4 + 2 * rec, "spread_fft_x": rec + tile_out,
+                "fft_y": tile_out + rows_out, "rows_out": rows_out}
+
+    a, b = per_shape(pa), per_shape(pb)
+    out = {k: (a[k] + b[k]) / 2 for k in ("rotate", "bin", "spread_fft_x", "fft_y")}
+    out["fft_z_spectrum"] = a["rows_out"] + spec
+    out["fft_z_product"] = b["rows_out"] + 2 * spec
+    out["ifft_y"] = 2 * spec
+    out["ifft_x"] = spec + 4 * n ** 3
+    return out
+
+
+def measured_traffic():
+    """HBM bytes per launch of the spreading kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != src:
+        return None
+    return float(fields["hbm_bytes_per_launch"])
 
 
 def main():
@@ -114,13 +144,16 @@ def main():
     value = rot_trans / (ms_step * 1e-3)
 
     info = c.info
-    # the A spectrum launches (S = 1 of shape A) share the forward kernels; the
-    # byte model for the B-side launches is used for the dominant-kernel roofline
-    nbytes = stage_bytes(info, 1, info["n_b"])
+    pkg.corr_prepare_a(c.ctx)
+    pass_a = c.pass_info()
+    pkg.corr_eval(c.ctx, q, scores.data_ptr(), pv.data_ptr(), pi.data_ptr())
+    pass_b = c.pass_info()
+    nbytes = stage_bytes(info, pass_a, pass_b)
     dom = max((k for k in prof if prof[k][1] > 0), key=lambda k: prof[k][0])
     dom_ms = prof[dom][0] / prof[dom][1]
     dom_bytes = nbytes.get(dom)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_bytes else None
+    traffic = measured_traffic() if dom == "spread_fft_x" else None
 
     out = {
         "metric": "rotations*translations scored/s at <=1e-4 rel err vs FP64",
@@ -140,8 +173,10 @@ def main():
                    "q_a": int(info["q_a"]), "q_b": int(info["q_b"])},
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in prof.items() if v[1]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                      "alg_bytes_per_launch": dom_bytes, "mean_launch_ms": dom_ms},
+        "occupancy": {"a": {k: pass_a[k] for k in ("tiles", "live_tiles", "live_rows")},
+                      "b": {k: pass_b[k] for k in ("tiles", "live_tiles", "live_rows")}},
     }
 
     if not args.no_cpu_baseline:

@@ -146,6 +146,26 @@ int corr_profile(corr_ctx* ctx, int32_t enable);
  * since the last read; clears the record. */
 int corr_profile_read(corr_ctx* ctx, double* ms, int64_t* launches, int32_t n_stages);
 
+/* Occupancy of the last spreading pass run by ctx (the rotations of the last
+ * batch of corr_eval, or one shape for corr_prepare_a / corr_spectrum).  The
+ * spreading grid of a rotation is cut into m z rows x (m / tile_rows) tiles of
+ * tile_rows y rows; a tile or z row is live when some knot's window reaches
+ * it.  Only live tiles are spread and transformed, and the later passes read
+ * only live rows.  Synchronises the context's stream.  With a batch, valid
+ * until any pair of the batch runs another pass. */
+typedef struct {
+    int32_t rotations;   /* rotations in the pass                            */
+    int32_t q;           /* radius-expansion components of the shape spread  */
+    int32_t tile_rows;   /* y rows per tile                                  */
+    int32_t m;           /* spreading grid per axis                          */
+    int64_t knots;       /* balls of the shape spread                        */
+    int64_t tiles;       /* rotations * m * (m / tile_rows)                  */
+    int64_t live_tiles;  /* tiles that some knot's window reaches            */
+    int64_t live_rows;   /* z rows (over all rotations) with a live tile     */
+} corr_pass_t;
+
+int corr_pass_info(corr_ctx* ctx, corr_pass_t* out);
+
 /* ---- uneven batches of pairs --------------------------------------------- */
 
 /* One shape pair with its own translation grid (grid.batch is ignored). */

@@ -29,7 +29,8 @@ CORR_EUNSUPPORTED = -4
 CORR_DETERMINISTIC = 1
 
 EXPORTS = ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
-           "corr_profile_read", "corr_destroy", "corr_last_error", "corr_batch_create", "corr_batch_eval",
+           "corr_profile_read", "corr_pass_info", "corr_destroy", "corr_last_error", "corr_batch_create",
+           "corr_batch_eval",
            "corr_batch_info", "corr_batch_destroy", "corr_batch_last_error")
 STAGES = ("rotate", "bin", "spread_fft_x", "fft_y", "fft_z_spectrum", "fft_z_product", "ifft_y", "ifft_x", "peak")
 
@@ -45,6 +46,12 @@ class corr_info_t(ctypes.Structure):
                 ("q_a", ctypes.c_int32), ("q_b", ctypes.c_int32), ("n_a", ctypes.c_int64),
                 ("n_b", ctypes.c_int64), ("batch", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
                 ("beta", ctypes.c_double), ("radius_err_a", ctypes.c_double), ("radius_err_b", ctypes.c_double)]
+
+
+class corr_pass_t(ctypes.Structure):
+    _fields_ = [("rotations", ctypes.c_int32), ("q", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("knots", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("live_tiles", ctypes.c_int64), ("live_rows", ctypes.c_int64)]
 
 
 class CorrError(RuntimeError):
@@ -72,11 +79,12 @@ def load_library(path: str = LIB_PATH):
     lib.corr_info.argtypes = [vp, ctypes.POINTER(corr_info_t)]
     lib.corr_profile.argtypes = [vp, i32]
     lib.corr_profile_read.argtypes = [vp, vp, vp, i32]
+    lib.corr_pass_info.argtypes = [vp, ctypes.POINTER(corr_pass_t)]
     lib.corr_destroy.argtypes = [vp]
     lib.corr_last_error.argtypes = [vp]
     lib.corr_last_error.restype = ctypes.c_char_p
     for name in ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
-                 "corr_profile_read", "corr_destroy"):
+                 "corr_profile_read", "corr_pass_info", "corr_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -136,6 +144,13 @@ def corr_profile_read(ctx) -> dict:
     return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(len(STAGES))}
 
 
+def corr_pass_info(ctx) -> dict:
+    """Occupancy of the last spreading pass (synchronises the stream)."""
+    r = corr_pass_t()
+    _check(load_library().corr_pass_info(ctx, ctypes.byref(r)), ctx)
+    return {k: getattr(r, k) for k, _ in corr_pass_t._fields_}
+
+
 def corr_destroy(ctx):
     load_library().corr_destroy(ctx)
 
@@ -186,6 +201,9 @@ class Correlator:
             corr_eval(self.ctx, q, s.data_ptr() if s is not None else None,
                       pv.data_ptr() if pv is not None else None, pi.data_ptr() if pi is not None else None)
         return s, pv, pi
+
+    def pass_info(self):
+        return corr_pass_info(self.ctx)
 
     def spectrum(self, which, quat=None):
         torch = self.torch

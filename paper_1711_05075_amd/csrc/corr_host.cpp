@@ -369,8 +369,12 @@ struct corr_ctx {
     double* deconv = nullptr;
     double2* phase = nullptr;
     float2* fa = nullptr;          // fixed shape's spectrum [n][n][half]
+    double* ident_q = nullptr;     // the identity quaternion (1, 0, 0, 0), device
     corr::Workspace* ws = nullptr;  // per-rotation buffers (shared by the pairs of a batch)
     bool own_ws = false;
+    // the last spreading pass: rotations, components, knots
+    int last_S = 0, last_q = 0;
+    int64_t last_nk = 0;
     // stage timing (corr_profile): event pairs recorded around each launch
     bool profiling = false;
     struct Mark { int stage; hipEvent_t a, b; };
@@ -497,6 +501,9 @@ corr::Occupancy occupancy(const corr_ctx* c, const Shape& s) {
 void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int S) {
     const Geom& g = c->g;
     const int q = s.ex.q;
+    c->last_S = S;
+    c->last_q = q;
+    c->last_nk = s.n;
     stage(c, CORR_STAGE_ROTATE, "rotate", [&] {
         return corr::launch_rotate_bin(g, d_quats, S, s.pos, s.n, c->ws->cell, c->ws->kbw, c->ws->rank, c->ws->counts,
                                        c->ws->done, c->ws->bin_start, c->ws->plan, c->stream);
@@ -518,9 +525,7 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
 void stage_quats(corr_ctx* c, const double* q, int S);
 
 void prepare_a(corr_ctx* c) {
-    static const double ident[4] = {1, 0, 0, 0};
-    stage_quats(c, ident, 1);
-    run_spectrum_stages(c, c->A, c->ws->quats, 1);
+    run_spectrum_stages(c, c->A, c->ident_q, 1);
     stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z (A)", [&] {
         return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->ws->buf0), 1, c->A.ex.q,
                                            occupancy(c, c->A), c->A.vtab, c->deconv,
@@ -625,6 +630,9 @@ corr_ctx* plan_pair(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t 
         upload_shape(c, c->A, A, dk);
         upload_shape(c, c->B, B, dk);
         c->fa = c->mem.alloc<float2>((size_t)g.n * g.n * g.half);
+        static const double ident[4] = {1, 0, 0, 0};
+        c->ident_q = c->mem.alloc<double>(4);
+        upload(c->ident_q, ident, sizeof ident, c->stream);
     } catch (...) {
         destroy_ctx(c);
         throw;
@@ -835,6 +843,36 @@ int corr_profile_read(corr_ctx* c, double* ms, int64_t* launches, int32_t n_stag
             c->spare.push_back(mk.b);
         }
         c->marks.clear();
+    });
+}
+
+int corr_pass_info(corr_ctx* c, corr_pass_t* out) {
+    if (!c) {
+        g_thread_error = "corr_pass_info: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] {
+        if (!out) fail(CORR_EINVAL, "out is NULL");
+        const int nty = corr::spread_tiles(c->g);
+        corr_pass_t r{};
+        r.rotations = c->last_S;
+        r.q = c->last_q;
+        r.m = c->g.m;
+        r.tile_rows = c->g.m / nty;
+        r.knots = c->last_nk;
+        r.tiles = (int64_t)c->last_S * c->g.m * nty;
+        if (r.tiles > 0 && r.knots > 0) {
+            std::vector<unsigned char> live((size_t)r.tiles);
+            hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+            hip_check(hipMemcpy(live.data(), c->ws->tile_live, live.size(), hipMemcpyDeviceToHost), "tile flags D2H");
+            for (int64_t row = 0; row < (int64_t)c->last_S * c->g.m; ++row) {
+                int64_t n = 0;
+                for (int t = 0; t < nty; ++t) n += live[(size_t)row * nty + t] != 0;
+                r.live_tiles += n;
+                r.live_rows += n > 0;
+            }
+        }
+        *out = r;
     });
 }
 

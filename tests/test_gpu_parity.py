@@ -234,3 +234,42 @@ def test_repeated_evaluation_is_bitwise_identical():
     torch.cuda.synchronize()
     assert torch.equal(s1, s2) and torch.equal(p1, p2) and torch.equal(i1, i2)
     c.close()
+
+
+def _reached_tiles(balls, R, m, box, w, ty):
+    """Tiles (z row, y tile) that some knot's window reaches, counted on the host
+    from the rotated centres: a knot in cell c covers cells c - w/2 + 1 .. c + w/2."""
+    u = (np.asarray(balls)[:, :3] @ np.asarray(R).T) * (m / box)
+    c = np.mod(np.floor(u).astype(np.int64), m)
+    lo = w // 2 - 1
+    hit = np.zeros((m, m // ty), dtype=bool)
+    for cy, cz in zip(c[:, 1], c[:, 2]):
+        zs = (cz - lo + np.arange(w)) % m
+        ts = np.unique(((cy - lo + np.arange(w)) % m) // ty)
+        hit[np.ix_(zs, ts)] = True
+    return hit
+
+
+def test_pass_info_counts_the_tiles_knots_reach():
+    # the spreading pass skips tiles no window reaches; its occupancy report
+    # must agree with the tiles reached, counted independently on the host
+    A = synth.mixture_balls(2000, 1400)
+    B = synth.mixture_balls(1500, 2400)
+    g = synth.grid_for(A, B, 64)
+    q = synth.random_quaternions(1, 3400)
+    _say("case: pass occupancy, 2000+1500 balls, n=64")
+    c = _corr(A, B, g, batch=1)
+    c.eval(q, peaks=False)
+    info = c.pass_info()
+    m, ty = info["m"], info["tile_rows"]
+    hit = _reached_tiles(B, oracle.quat_to_rot(q[0]), m, g.box, c.info["kb_width"], ty)
+    _say("  live tiles %d of %d (host count %d), live rows %d" % (info["live_tiles"], info["tiles"], hit.sum(),
+                                                                  info["live_rows"]))
+    assert info["tiles"] == hit.size and info["knots"] == len(B) and info["rotations"] == 1
+    assert info["live_tiles"] == int(hit.sum())
+    assert info["live_rows"] == int(hit.any(axis=1).sum())
+    c.prepare_a()
+    info = c.pass_info()
+    hit = _reached_tiles(A, np.eye(3), m, g.box, c.info["kb_width"], ty)
+    assert info["live_tiles"] == int(hit.sum()) and info["knots"] == len(A)
+    c.close()
