@@ -68,7 +68,8 @@ int prop_predict(prop_ctx* p, const float* X_dev, int64_t n, float* y_dev);
 
 /* Indices of the k inputs with the highest predicted score (ties: lower index
  * first), in decreasing order of score, into idx_dev[k] (device int64).
- * 1 <= k <= n <= 65536. */
+ * 1 <= k <= n <= 8192 (one workgroup sorts the scores in LDS); larger n
+ * returns CORR_EUNSUPPORTED. */
 int prop_rank(prop_ctx* p, const float* X_dev, int64_t n, int32_t k, int64_t* idx_dev);
 
 /* Mean-squared-error gradient of one batch of n <= batch samples without an
