@@ -168,3 +168,18 @@ def uneven_batch_case(n_pairs: int = 64, n_rot: int = 32, seed: int = 4000,
         q = random_quaternions(n_rot, 3000 + p)
         pairs.append((A, B, q, grid_for(A, B, int(ns[p]))))
     return pairs
+
+
+def proposal_pairs(n_pairs: int, seed: int, lo: int = 500, hi: int = 5000, n: int = 64):
+    """Pairs for the rotation-proposal workflow: mixture shapes with log-uniform
+    ball counts in [lo, hi] (the uneven batch's model with its upper count
+    capped so that generating training data stays short) on an n^3 grid."""
+    g = _rng(seed)
+    na = loguniform_int(g, lo, hi, n_pairs)
+    nb = loguniform_int(g, lo, hi, n_pairs)
+    pairs = []
+    for p in range(n_pairs):
+        A = mixture_balls(int(na[p]), seed + 1000 + p)
+        B = mixture_balls(int(nb[p]), seed + 2000 + p)
+        pairs.append((A, B, grid_for(A, B, n)))
+    return pairs
