@@ -305,7 +305,6 @@ struct Workspace {
     int* bin_start = nullptr;      // [slots][keys + 1] first sorted knot of each key
     unsigned char* tile_live = nullptr;  // [slots][m][y tiles] spreading tiles that some knot reaches
     int* plan = nullptr;           // bucket sizes and work counter of the spreading pass's live-tile plan
-    int* done = nullptr;           // [slots] arrival counters of the sort's workgroups; zero between passes
     int* list = nullptr;           // [buckets][slots * tiles] live tiles
     int* scell = nullptr;          // [slots][nk] sorted by z-cell: packed cell
     float* skbw = nullptr;         // [slots][nk][3][w]              window weights
@@ -331,8 +330,6 @@ struct Workspace {
         bin_start = mem.alloc<int>(S * r.bins);
         tile_live = mem.alloc<unsigned char>(S * r.tiles);
         plan = mem.alloc<int>(corr::plan_words());
-        done = mem.alloc<int>(S);
-        hip_check(hipMemsetAsync(done, 0, sizeof(int) * S, st), "hipMemsetAsync");
         list = mem.alloc<int>(S * r.list);
         scell = mem.alloc<int>(S * r.nk);
         skbw = mem.alloc<float>(S * r.nkw);
@@ -506,7 +503,7 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
     c->last_nk = s.n;
     stage(c, CORR_STAGE_ROTATE, "rotate", [&] {
         return corr::launch_rotate_bin(g, d_quats, S, s.pos, s.n, c->ws->cell, c->ws->kbw, c->ws->rank, c->ws->counts,
-                                       c->ws->done, c->ws->bin_start, c->ws->plan, c->stream);
+                                       c->ws->bin_start, c->ws->plan, c->stream);
     });
     stage(c, CORR_STAGE_BIN, "bin", [&] {
         return corr::launch_scatter_plan(g, S, q, occupancy(c, s), c->ws->cell, c->ws->kbw, s.wts, c->ws->rank,

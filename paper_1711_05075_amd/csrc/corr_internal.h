@@ -53,12 +53,11 @@ constexpr int bin_ygroup(int m) { return m * m / 8192 > 1 ? m * m / 8192 : 1; }
 constexpr int bin_keys(int m) { return m * (m / bin_ygroup(m)); }
 // a0, binned: rotate, place, window weights, and each knot's rank among the
 // knots of its key from atomic counters (d_counts [S][keys], zero on entry);
-// the last workgroup of each rotation turns the counts into d_bin_start
-// [S][keys + 1] and clears them (d_done [S], zero on entry, is its arrival
-// counter).  Also clears the live-tile plan's counters d_plan.
+// then the scan of the counts into d_bin_start [S][keys + 1], which clears
+// them.  Also clears the live-tile plan's counters d_plan.
 hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const double* d_pos, int64_t nk,
-                             int* d_cell, float* d_kbw, int* d_rank, int* d_counts, int* d_done, int* d_bin_start,
-                             int* d_plan, hipStream_t st);
+                             int* d_cell, float* d_kbw, int* d_rank, int* d_counts, int* d_bin_start, int* d_plan,
+                             hipStream_t st);
 // The scatter of every knot's record (cell, window weights, q component
 // weights) into sorted order, and the live-tile plan: tiles that no knot's
 // window can reach are marked dead in occ.tile_live and the others are listed

@@ -293,19 +293,14 @@ __device__ __forceinline__ void scan_counts(int* __restrict__ cs, int* __restric
     for (int k = 0; k < PER / 4; ++k) reinterpret_cast<int4*>(cs + b0)[k] = make_int4(0, 0, 0, 0);
 }
 
-// Rotate + place + window weights + counts per key.  The last workgroup of a
-// rotation to finish (a per-rotation counter, reset afterwards) turns that
-// rotation's counts into the key starts bin_start[s][0 .. keys] and clears the
-// counts.  Workgroup (0, 0) also clears the tile plan's counters.
+// Rotate + place + window weights + counts per key.  Workgroup (0, 0) also
+// clears the tile plan's counters.
 __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restrict__ quats,
                                                           const double* __restrict__ pos, int64_t nk, double inv_hf,
                                                           int m, int w, float beta, float inv_i0beta, int yshift,
                                                           int nyb, int* __restrict__ cell, float* __restrict__ kbw,
                                                           int* __restrict__ rank, int* __restrict__ counts,
-                                                          int* __restrict__ done, int* __restrict__ bin_start,
                                                           int* __restrict__ plan, int nplan) {
-    __shared__ int last;
-    __shared__ int wsum[kBinBlock / 64];
     const int64_t j = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
     const int s = blockIdx.y;
     const int keys = m * nyb;
@@ -340,12 +335,16 @@ __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restri
         const int key = c[2] * nyb + (c[1] >> yshift);
         rank[(int64_t)s * nk + j] = atomicAdd(&counts[(size_t)s * keys + key], 1);
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&done[s], 1) == (int)gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();  // acquire: the other workgroups' counts are visible to plain loads
+}
+
+// Key starts of each rotation from its counts (one workgroup per rotation,
+// keys / kBinBlock consecutive keys per thread); clears the counts.  Reading
+// the counts in a kernel of its own makes every workgroup's atomic increments
+// visible without device-wide fences.
+__global__ __launch_bounds__(kBinBlock) void k_bin_scan(int* __restrict__ counts, int keys, int64_t nk,
+                                                        int* __restrict__ bin_start) {
+    __shared__ int wsum[kBinBlock / 64];
+    const int s = blockIdx.x;
     int* cs = counts + (size_t)s * keys;
     int* bs = bin_start + (size_t)s * (keys + 1);
     switch (keys / kBinBlock) {  // keys is 1024, 4096 or 8192
@@ -353,10 +352,7 @@ __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restri
         case 16: scan_counts<16>(cs, bs, wsum); break;
         default: scan_counts<32>(cs, bs, wsum); break;
     }
-    if (threadIdx.x == 0) {
-        bs[keys] = (int)nk;
-        done[s] = 0;
-    }
+    if (threadIdx.x == 0) bs[keys] = (int)nk;
 }
 
 // Scatter knot j of rotation s into sorted position: its packed cell, its
@@ -1218,13 +1214,16 @@ int bin_blocks(int64_t nk) { return (int)((nk + kBinBlock - 1) / kBinBlock); }
 }  // namespace
 
 hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const double* d_pos, int64_t nk,
-                             int* d_cell, float* d_kbw, int* d_rank, int* d_counts, int* d_done, int* d_bin_start,
-                             int* d_plan, hipStream_t st) {
+                             int* d_cell, float* d_kbw, int* d_rank, int* d_counts, int* d_bin_start, int* d_plan,
+                             hipStream_t st) {
     if (nk == 0 || S == 0) return hipSuccess;
     const int G = bin_ygroup(g.m);
     hipLaunchKernelGGL(k_rotate_bin, dim3(bin_blocks(nk), S), dim3(kBinBlock), 0, st, d_quats, d_pos, nk, g.inv_hf,
-                       g.m, g.w, g.beta, g.inv_i0beta, log2i(G), g.m / G, d_cell, d_kbw, d_rank, d_counts, d_done,
-                       d_bin_start, d_plan, plan_words());
+                       g.m, g.w, g.beta, g.inv_i0beta, log2i(G), g.m / G, d_cell, d_kbw, d_rank, d_counts, d_plan,
+                       plan_words());
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_scan, dim3(S), dim3(kBinBlock), 0, st, d_counts, bin_keys(g.m), nk, d_bin_start);
     return hipGetLastError();
 }
 
