@@ -15,6 +15,8 @@ Two oracles, both written from Behandish & Ilies (CAD 2016):
   NDFT of the knots (Sec. 2.5 eq. eq_rhoPhat) weighted by each ball's transform,
   their correlation spectrum F_A conj(F_RB) (Sec. 3.2 eq. eq_ccghat), and an FP64
   inverse FFT onto an L-periodic translation grid, keeping |m_d| < N/2.
+* ``*_sc_*`` -- the shape-complementarity score (Sec. 4.2 eq. eq_score), built
+  from the two above by its definition.
 
 The heavy loops live in ``oracle.c`` (plain C, OpenMP), built on first use with
 gcc into ``liboracle.so`` next to this file.
@@ -164,6 +166,49 @@ def o2_eval_at(FA, FB, L, t) -> np.ndarray:
               * np.exp(1j * k * p[0])[None, None, :])
         out.append(np.real(np.sum(S * ph)))
     return np.array(out)
+
+
+# ---- shape-complementarity score (Sec. 4.2, eq. eq_score) ---------------------
+#
+# The affinity of a shape is F_S = i (f_{S (+) B0} - lam f_S).  For a union of
+# balls the offset by B0 = B(0, r0) is the union of the balls grown by r0, so
+# with F_S = i a_S the score G = F_RS2 star F_S1 equals <a_S1, a_(R,t)S2>: the
+# plain score of two signed unions.
+
+def sc_grown(balls, r0) -> np.ndarray:
+    """Every ball grown by r0 (the offset S (+) B(0, r0) of a union of balls)."""
+    b = _f64(balls).copy()
+    b[:, 3] += r0
+    return b
+
+
+def sc_affinity_balls(balls, r0, lam) -> np.ndarray:
+    """a_S = f_{S (+) B0} - lam f_S as one signed union: the grown balls with
+    their weights and the original balls with weights times -lam."""
+    b = _f64(balls)
+    neg = b.copy()
+    neg[:, 4] *= -lam
+    return np.vstack([sc_grown(b, r0), neg])
+
+
+def o1_sc_grid(A, B, R, origin, h, n, r0, lam) -> np.ndarray:
+    """Plain SC score, expanded into its four lens-sum terms:
+    G = g(A+, B+) - lam g(A+, B) - lam g(A, B+) + lam^2 g(A, B), '+' = grown by r0."""
+    Ag, Bg = sc_grown(A, r0), sc_grown(B, r0)
+    return (o1_grid(Ag, Bg, R, origin, h, n) - lam * o1_grid(Ag, B, R, origin, h, n)
+            - lam * o1_grid(A, Bg, R, origin, h, n) + lam * lam * o1_grid(A, B, R, origin, h, n))
+
+
+def o2_sc_spectrum(balls, R, n, L, r0, lam) -> np.ndarray:
+    """Spectrum of the affinity: F_{S (+) B0}(k) - lam F_S(k)."""
+    return o2_spectrum(sc_grown(balls, r0), R, n, L) - lam * o2_spectrum(balls, R, n, L)
+
+
+def o2_sc_scores(A, B, q, n, L, origin, r0, lam) -> np.ndarray:
+    """Band-limited SC score on the translation grid, [iz][iy][ix]."""
+    FA = o2_sc_spectrum(A, np.eye(3), n, L, r0, lam)
+    FB = o2_sc_spectrum(B, quat_to_rot(q), n, L, r0, lam)
+    return o2_scores_from_spectra(FA, FB, L, origin)
 
 
 def peak(scores) -> tuple:

@@ -390,3 +390,94 @@ def test_peak_ties_take_lowest_index():
     s[1, 1, 1, 1] = -0.5
     v, i = oracle.peak(s)
     assert list(v) == [3.0, 0.0] and list(i) == [5, 1]
+
+
+# --------------------------------------------------------------------------
+# Shape-complementarity score (Sec. 4.2, eq. eq_score)
+# --------------------------------------------------------------------------
+
+def test_sc_single_pair_by_monte_carlo():
+    # G(t) = integral of a_A(x) a_B(x - t) with a = 1[ball grown by r0] - lam 1[ball]:
+    # sampled directly from the two signed indicators, not from lens volumes
+    A = np.array([[0.0, 0.0, 0.0, 0.05, 1.0]])
+    B = np.array([[0.0, 0.0, 0.0, 0.035, 1.0]])
+    r0, lam = 0.015, 3.0
+    g = np.random.default_rng(17)
+    n = 4_000_000
+    for t in (np.array([0.02, 0.01, -0.01]), np.array([0.075, 0.0, 0.02])):
+        lo, hi = np.full(3, -0.07), np.full(3, 0.07)
+        p = lo + (hi - lo) * g.random((n, 3))
+        dA = np.sum(p ** 2, 1)
+        dB = np.sum((p - t) ** 2, 1)
+        aA = (dA <= (0.05 + r0) ** 2) - lam * (dA <= 0.05 ** 2)
+        aB = (dB <= (0.035 + r0) ** 2) - lam * (dB <= 0.035 ** 2)
+        vals = aA * aB
+        vol = np.prod(hi - lo)
+        mc, sd = vol * vals.mean(), vol * vals.std() / math.sqrt(n)
+        origin = t - np.array([0.0, 0.0, 0.0])
+        G = oracle.o1_sc_grid(A, B, np.eye(3), origin, 1.0, 1, r0, lam)[0, 0, 0]
+        assert abs(G - mc) < 4 * sd
+        assert abs(G) > 10 * sd
+
+
+def test_sc_four_terms_equal_the_signed_union():
+    # the four-term expansion against the plain score of the signed unions
+    A = synth.uniform_balls(12, 51) * [0.3, 0.3, 0.3, 0.5, 1]
+    B = synth.uniform_balls(9, 52) * [0.3, 0.3, 0.3, 0.5, 1]
+    R = oracle.quat_to_rot(synth.random_quaternions(1, 53)[0])
+    r0, lam = 0.012, 2.5
+    G = oracle.o1_sc_grid(A, B, R, (-0.4, -0.4, -0.4), 0.05, 16, r0, lam)
+    Gs = oracle.o1_grid(oracle.sc_affinity_balls(A, r0, lam), oracle.sc_affinity_balls(B, r0, lam), R,
+                        (-0.4, -0.4, -0.4), 0.05, 16)
+    np.testing.assert_allclose(G, Gs, rtol=1e-10, atol=1e-15)
+    assert G.min() < 0 < G.max()
+
+
+def test_sc_zero_offset_is_scaled_plain_score():
+    # r0 -> 0: a_S = (1 - lam) f_S, so G = (1 - lam)^2 g (O1 and O2)
+    A, B, q, g, plain = synth.tiny_case()
+    lam = 1.7
+    R = oracle.quat_to_rot(q[0])
+    lo = plain["origin"]
+    G1 = oracle.o1_sc_grid(A, B, R, lo, plain["h"], 8, 0.0, lam)
+    s1 = oracle.o1_grid(A, B, R, lo, plain["h"], 8)
+    np.testing.assert_allclose(G1, (1 - lam) ** 2 * s1, rtol=1e-12, atol=1e-18)
+    G2 = oracle.o2_sc_scores(A, B, q[0], g.n, g.box, g.origin, 0.0, lam)
+    s2 = oracle.o2_scores(A, B, q[0], g.n, g.box, g.origin)
+    np.testing.assert_allclose(G2, (1 - lam) ** 2 * s2, rtol=1e-9, atol=1e-12 * np.abs(s2).max())
+
+
+def test_sc_dc_term_is_product_of_affinity_integrals():
+    # sum_n G h^3 = (integral a_A)(integral a_B), integral a_S = sum c 4 pi/3 ((r + r0)^3 - lam r^3)
+    A, B, q, g, _ = synth.tiny_case()
+    r0, lam = 0.02, 2.0
+    G2 = oracle.o2_sc_scores(A, B, synth.random_quaternions(1, 8)[0], g.n, g.box, g.origin, r0, lam)
+    ia = np.sum(A[:, 4] * 4 * np.pi / 3 * ((A[:, 3] + r0) ** 3 - lam * A[:, 3] ** 3))
+    ib = np.sum(B[:, 4] * 4 * np.pi / 3 * ((B[:, 3] + r0) ** 3 - lam * B[:, 3] ** 3))
+    assert G2.sum() * g.h ** 3 == pytest.approx(ia * ib, rel=1e-11)
+
+
+def test_sc_o2_is_band_limited_projection_of_o1():
+    # as for the plain score: the band-limited SC score is the |m_d| < N/2
+    # projection of the periodic plain SC score, approached by finer sampling
+    # (the gap falls at the plain score's rate; with lam = 1 the cancellation
+    # between the terms is mild enough that 8x sampling reaches 1e-4)
+    A, B, q, g, _ = synth.tiny_case()
+    qr = synth.random_quaternions(1, 14)[0]
+    R = oracle.quat_to_rot(qr)
+    r0, lam = 0.015, 1.0
+    s2 = oracle.o2_sc_scores(A, B, qr, g.n, g.box, g.origin, r0, lam)
+    errs = []
+    for qf in (2, 4, 8):
+        M = qf * g.n
+        sf = oracle.o1_sc_grid(A, B, R, g.origin, g.box / M, M, r0, lam)
+        C = np.fft.fftn(sf) / M ** 3
+        m = oracle.mode_numbers(M)
+        mi = np.where(np.abs(m) < g.n // 2)[0]
+        Ck = np.zeros((g.n,) * 3, complex)
+        mn = m[mi] % g.n
+        Ck[np.ix_(mn, mn, mn)] = C[np.ix_(mi, mi, mi)]
+        sp = np.real(np.fft.ifftn(Ck)) * g.n ** 3
+        errs.append(np.abs(sp - s2).max() / np.abs(s2).max())
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-4
