@@ -50,6 +50,13 @@ extern "C" {
 #define CORR_DETERMINISTIC 1u /* bit-reproducible results; accepted for clarity: every
                                  run already is (spreading sums are exact 64-bit
                                  fixed point, independent of scheduling)           */
+#define CORR_SC_SCORE      2u /* score the shape complementarity of Sec. 4.2, eq.
+                                 eq_score, instead of the overlap: each shape's
+                                 defining function f_S becomes its affinity
+                                 a_S = f_{S (+) B(0, sc_offset)} - sc_lambda f_S, the
+                                 offset of a union of balls being the union of its
+                                 balls grown by sc_offset, and the score is
+                                 <a_A, a_{(R,t)B}> (the affinity's factor i cancels) */
 
 typedef struct {
     double x, y, z; /* centre                */
@@ -69,6 +76,11 @@ typedef struct {
     uint32_t flags;    /* CORR_DETERMINISTIC or 0                                  */
     int32_t batch;     /* rotations per pipeline pass, 1..256 (0 = largest that
                           fits a 4 GiB workspace, at most 64)                     */
+    double sc_offset;  /* with CORR_SC_SCORE: skin offset r0 >= 0 (length units);
+                          otherwise must be 0                                      */
+    double sc_lambda;  /* with CORR_SC_SCORE: penalty factor lambda >= 0; otherwise
+                          must be 0.  tol is then relative to the volume of the
+                          largest grown ball.                                      */
 } corr_grid;
 
 typedef struct corr_ctx corr_ctx;

@@ -60,9 +60,13 @@ double ball_shape_host(double x) {
     return 3.0 * (std::sin(x) - x * std::cos(x)) / (x * x * x);
 }
 
+// Separable expansion K(k; r) ~ (4 pi / 3) rref^3 sum_c v_c(k) u_c(r) of the per-ball
+// kernel K(k; r) = Bhat(k; r + r0) - lam Bhat(k; r) over the radius range
+// [rlo, rhi]; r0 = lam = 0 is the ball transform.
 struct Expansion {
     int p = 1, q = 1;
     double rlo = 1, rhi = 1, err = 0;
+    double r0 = 0, lam = 0, rref = 1;  // kernel parameters; rref = rhi + r0
     std::vector<double> nodes;  // [p]
     std::vector<double> basis;  // [p][q]
     std::vector<double> bary;   // barycentric weights [p]
@@ -124,10 +128,20 @@ void jacobi_eig(std::vector<double>& a, std::vector<double>& v, int p) {
     }
 }
 
-Expansion build_expansion(double rlo, double rhi, double dk, int m2n, double tol) {
+Expansion build_expansion(double rlo, double rhi, double dk, int m2n, double tol, double r0, double lam) {
     Expansion e;
     e.rlo = rlo;
     e.rhi = rhi;
+    e.r0 = r0;
+    e.lam = lam;
+    e.rref = rhi + r0;
+    // the kernel normalised by (4 pi / 3) rref^3
+    auto f = [&](double k, double r) {
+        const double rg = (r + r0) / e.rref, rr = r / e.rref;
+        double v = rg * rg * rg * ball_shape_host(k * (r + r0));
+        if (lam != 0.0) v -= lam * rr * rr * rr * ball_shape_host(k * r);
+        return v;
+    };
     if (!(rhi > rlo * (1.0 + 1e-12))) {
         e.p = e.q = 1;
         e.nodes = {rhi};
@@ -138,8 +152,7 @@ Expansion build_expansion(double rlo, double rhi, double dk, int m2n, double tol
         double worst = 0;
         for (int a = 0; a < 257; ++a) {
             double k = kmax * a / 256.0;
-            double rr = rlo / rhi;
-            worst = std::max(worst, std::fabs(rr * rr * rr * ball_shape_host(k * rlo) - ball_shape_host(k * rhi)));
+            worst = std::max(worst, std::fabs(f(k, rlo) - f(k, rhi)));
         }
         e.err = worst;
         return e;
@@ -152,10 +165,6 @@ Expansion build_expansion(double rlo, double rhi, double dk, int m2n, double tol
         e.nodes[b] = 0.5 * (rlo + rhi) + 0.5 * (rhi - rlo) * std::cos(M_PI * b / (p - 1));
         e.bary[b] = ((b % 2) ? -1.0 : 1.0) * ((b == 0 || b == p - 1) ? 0.5 : 1.0);
     }
-    auto f = [&](double k, double r) {
-        double rr = r / rhi;
-        return rr * rr * rr * ball_shape_host(k * r);
-    };
     // rows: every |m|^2 (all needed wavenumbers)
     std::vector<double> F((size_t)m2n * p);
     for (int a = 0; a < m2n; ++a) {
@@ -357,6 +366,7 @@ struct corr_ctx {
     hipStream_t stream = nullptr;
     Geom g;
     double box = 0, origin[3] = {0, 0, 0}, sigma = 2, tol = 1e-6;
+    double sc_r0 = 0, sc_lam = 0;  // shape-complementarity kernel parameters (0, 0: overlap score)
     uint32_t flags = 0;
     int qmax = 1;
     int64_t nkmax = 1;  // max(nA, nB, 1)
@@ -411,7 +421,7 @@ void setup_shape(corr_ctx* c, Shape& s, const corr_ball* balls, int64_t n, doubl
             rhi = std::max(rhi, balls[i].r);
         }
     }
-    s.ex = build_expansion(rlo, rhi, dk, c->g.m2n, c->tol);
+    s.ex = build_expansion(rlo, rhi, dk, c->g.m2n, c->tol, c->sc_r0, c->sc_lam);
 }
 
 void upload_shape(corr_ctx* c, Shape& s, const corr_ball* balls, double dk) {
@@ -429,7 +439,8 @@ void upload_shape(corr_ctx* c, Shape& s, const corr_ball* balls, double dk) {
             pos[3 * i + 1] = balls[i].y;
             pos[3 * i + 2] = balls[i].z;
             lagrange_row(e, std::min(std::max(balls[i].r, e.rlo), e.rhi), lrow.data());
-            if (e.p == 1) lrow[0] = std::pow(balls[i].r / e.rhi, 3.0);  // equal radii: exact volume ratio
+            // equal radii: exact volume ratio (with an offset the two terms scale differently)
+            if (e.p == 1 && e.r0 == 0.0) lrow[0] = std::pow(balls[i].r / e.rhi, 3.0);
             for (int q = 0; q < e.q; ++q) {
                 double u = 0;
                 for (int b = 0; b < e.p; ++b) u += lrow[b] * e.basis[(size_t)b * e.q + q];
@@ -456,7 +467,8 @@ void upload_shape(corr_ctx* c, Shape& s, const corr_ball* balls, double dk) {
     double* d_basis = c->mem.alloc<double>((size_t)e.p * e.q);
     upload(d_nodes, e.nodes.data(), sizeof(double) * e.p, c->stream);
     upload(d_basis, e.basis.data(), sizeof(double) * e.p * e.q, c->stream);
-    hip_check(corr::launch_ball_table(c->g, dk, d_nodes, d_basis, e.p, e.q, e.rhi, s.vtab, c->stream), "ball table");
+    hip_check(corr::launch_ball_table(c->g, dk, d_nodes, d_basis, e.p, e.q, e.rref, e.r0, e.lam, s.vtab, c->stream),
+              "ball table");
 }
 
 hipEvent_t take_event(corr_ctx* c) {
@@ -571,7 +583,13 @@ corr_ctx* plan_pair(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t 
     if (w < 4 || w > 12 || (w & 1)) fail(CORR_EUNSUPPORTED, "%skb_width = %d; supported: even 4..12", who, w);
     const double tol = gr.tol == 0 ? 1e-6 : gr.tol;
     if (!std::isfinite(tol) || !(tol > 0) || tol >= 1) fail(CORR_EINVAL, "%stol must be in (0, 1)", who);
-    if (gr.flags & ~CORR_DETERMINISTIC) fail(CORR_EINVAL, "%sunknown flag bits 0x%x", who, gr.flags);
+    if (gr.flags & ~(CORR_DETERMINISTIC | CORR_SC_SCORE)) fail(CORR_EINVAL, "%sunknown flag bits 0x%x", who, gr.flags);
+    if (gr.flags & CORR_SC_SCORE) {
+        if (!std::isfinite(gr.sc_offset) || gr.sc_offset < 0) fail(CORR_EINVAL, "%ssc_offset must be finite and >= 0", who);
+        if (!std::isfinite(gr.sc_lambda) || gr.sc_lambda < 0) fail(CORR_EINVAL, "%ssc_lambda must be finite and >= 0", who);
+    } else if (gr.sc_offset != 0 || gr.sc_lambda != 0) {
+        fail(CORR_EINVAL, "%ssc_offset and sc_lambda need CORR_SC_SCORE", who);
+    }
     if (gr.batch < 0 || gr.batch > 256) fail(CORR_EINVAL, "%sbatch = %d; allowed 0..256", who, gr.batch);
 
     corr_ctx* c = new corr_ctx();
@@ -583,6 +601,8 @@ corr_ctx* plan_pair(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t 
         c->sigma = sigma;
         c->tol = tol;
         c->flags = gr.flags;
+        c->sc_r0 = (gr.flags & CORR_SC_SCORE) ? gr.sc_offset : 0.0;
+        c->sc_lam = (gr.flags & CORR_SC_SCORE) ? gr.sc_lambda : 0.0;
         Geom& g = c->g;
         g.n = gr.n;
         g.m = (int)std::lround(sigma * gr.n);

@@ -43,8 +43,11 @@ constexpr int plan_buckets() { return 8; }
 hipError_t launch_deconv_tables(const Geom& g, double box, const double origin[3],
                                 double* d_deconv /*[n]*/, double2* d_phase /*[3][n]*/,
                                 hipStream_t st);
+// Per-ball kernel table: K(k; r) = Bhat(k; r + r0) - lam Bhat(k; r) expanded on
+// the radius basis (r0 = lam = 0: the ball transform), normalised by rref^3.
 hipError_t launch_ball_table(const Geom& g, double dk, const double* d_nodes, const double* d_basis,
-                             int p, int q, double rhi, float* d_vtab /*[q][m2n]*/, hipStream_t st);
+                             int p, int q, double rref, double r0, double lam,
+                             float* d_vtab /*[q][m2n]*/, hipStream_t st);
 
 // ---- pipeline stages -----------------------------------------------------
 // Knots are sorted by key = z-cell * (m / ygroup) + y-cell / ygroup, with

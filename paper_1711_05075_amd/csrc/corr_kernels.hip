@@ -219,22 +219,27 @@ __device__ double ball_shape(double x) {
     return 3.0 * (sn - x * cs) / (x * x * x);
 }
 
-// vtab[c][m2] = (4 pi / 3) rhi^3 sum_b (r_b / rhi)^3 Phi(k r_b) basis[b][c], k = dk sqrt(m2):
-// the k-factor of the separable radius expansion of the ball transform.
+// vtab[c][m2] = (4 pi / 3) rref^3 sum_b f(k, r_b) basis[b][c], k = dk sqrt(m2): the
+// k-factor of the separable radius expansion of the per-ball kernel
+//   K(k; r) = Bhat(k; r + r0) - lam Bhat(k; r) = (4 pi / 3) rref^3 f(k, r),
+//   f(k, r) = ((r + r0) / rref)^3 Phi(k (r + r0)) - lam (r / rref)^3 Phi(k r).
+// The overlap score is r0 = lam = 0 (the ball transform itself); the
+// shape-complementarity affinity (Sec. 4.2) has r0, lam > 0.
 __global__ void k_ball_table(int m2n, double dk, const double* __restrict__ nodes,
-                             const double* __restrict__ basis, int p, int q, double rhi,
-                             float* __restrict__ vtab) {
+                             const double* __restrict__ basis, int p, int q, double rref, double r0,
+                             double lam, float* __restrict__ vtab) {
     int m2 = blockIdx.x * blockDim.x + threadIdx.x;
     if (m2 >= m2n) return;
     double k = dk * sqrt((double)m2);
     double acc[32];
     for (int c = 0; c < q; ++c) acc[c] = 0.0;
     for (int b = 0; b < p; ++b) {
-        double rr = nodes[b] / rhi;
-        double f = rr * rr * rr * ball_shape(k * nodes[b]);
+        const double rg = (nodes[b] + r0) / rref, rr = nodes[b] / rref;
+        double f = rg * rg * rg * ball_shape(k * (nodes[b] + r0));
+        if (lam != 0.0) f -= lam * rr * rr * rr * ball_shape(k * nodes[b]);
         for (int c = 0; c < q; ++c) acc[c] += f * basis[b * q + c];
     }
-    double scale = 4.0 * M_PI / 3.0 * rhi * rhi * rhi;
+    double scale = 4.0 * M_PI / 3.0 * rref * rref * rref;
     for (int c = 0; c < q; ++c) vtab[(size_t)c * m2n + m2] = (float)(scale * acc[c]);
 }
 
@@ -1198,9 +1203,9 @@ hipError_t launch_deconv_tables(const Geom& g, double box, const double origin[3
 }
 
 hipError_t launch_ball_table(const Geom& g, double dk, const double* d_nodes, const double* d_basis, int p,
-                             int q, double rhi, float* d_vtab, hipStream_t st) {
+                             int q, double rref, double r0, double lam, float* d_vtab, hipStream_t st) {
     hipLaunchKernelGGL(k_ball_table, dim3((g.m2n + 127) / 128), dim3(128), 0, st, g.m2n, dk, d_nodes, d_basis,
-                       p, q, rhi, d_vtab);
+                       p, q, rref, r0, lam, d_vtab);
     return hipGetLastError();
 }
 

@@ -103,17 +103,18 @@ class Grid:
 
 
 def grid_for(A: np.ndarray, B: np.ndarray, n: int, sigma: float = 2.0, kb_width: int = 8,
-             tol: float = 1e-6) -> Grid:
+             tol: float = 1e-6, pad: float = 0.0) -> Grid:
     """Period L large enough that translated copies of the score never overlap.
 
     The score is non-zero only where some ball of A meets some ball of the moved
     B, i.e. for |t| < R_A + R_B + max r_A + max r_B with R_X the largest centre
-    distance from the origin.  L is twice that, rounded up to a multiple of 1/8,
-    and the grid is centred on the origin.
+    distance from the origin; pad widens that reach (balls grown by r0 on both
+    sides need pad = 2 r0).  L is twice the reach, rounded up to a multiple of
+    1/8, and the grid is centred on the origin.
     """
     ra = np.linalg.norm(A[:, :3], axis=1).max() + A[:, 3].max()
     rb = np.linalg.norm(B[:, :3], axis=1).max() + B[:, 3].max()
-    L = math.ceil(2.0 * (ra + rb) * 8.0) / 8.0
+    L = math.ceil(2.0 * (ra + rb + pad) * 8.0) / 8.0
     return Grid(n=n, box=L, origin=(-L / 2,) * 3, sigma=sigma, kb_width=kb_width, tol=tol)
 
 

@@ -77,6 +77,10 @@ GOOD = np.array([[0.0, 0.0, 0.0, 0.05, 1.0], [0.1, 0.0, 0.0, 0.04, 1.0]])
     (dict(flags=8), pkg.CORR_EINVAL),
     (dict(batch=-1), pkg.CORR_EINVAL),
     (dict(batch=1000), pkg.CORR_EINVAL),
+    (dict(sc=(-0.01, 2.0)), pkg.CORR_EINVAL),
+    (dict(sc=(0.01, -2.0)), pkg.CORR_EINVAL),
+    (dict(sc=(float("nan"), 2.0)), pkg.CORR_EINVAL),
+    (dict(sc=(0.01, float("inf"))), pkg.CORR_EINVAL),
 ])
 def test_create_rejects_bad_grids(lib, bad, code):
     rc, out = _create(GOOD, GOOD, _grid(**bad))
@@ -152,3 +156,14 @@ def test_batch_rejects_bad_arguments(lib):
     assert "pair 0" in pkg._batch_lib().corr_batch_last_error(None).decode()
     assert blib.corr_batch_eval(None, None, None, None, None, None, None) == pkg.CORR_EINVAL
     assert blib.corr_batch_destroy(None) == pkg.CORR_OK
+
+
+def test_complementarity_parameters_need_their_flag(lib):
+    g = _grid()
+    g.sc_offset = 0.01
+    rc, out = _create(GOOD, GOOD, g)
+    assert rc == pkg.CORR_EINVAL and not out.value
+    g = _grid()
+    g.sc_lambda = 1.0
+    rc, out = _create(GOOD, GOOD, g)
+    assert rc == pkg.CORR_EINVAL and not out.value
