@@ -449,16 +449,14 @@ void upload_shape(corr_ctx* c, Shape& s, const corr_ball* balls, double dk) {
         }
         upload(s.pos, pos.data(), sizeof(double) * pos.size(), c->stream);
         upload(s.wts, w.data(), sizeof(float) * w.size(), c->stream);
-        // fixed-point scale: any spreading sum is bounded by sum_i max_c |w_ic|
-        // (window values are <= 1), so 2^61 / that bound cannot overflow int64
+        // fixed-point scale: one knot adds w_ic times window values <= 1 to a
+        // sum, so with 2^30 / max |w_ic| every addend fits an int32 (converted
+        // in one instruction) and a sum of at most 2^31 knots fits int64
         double bound = 0;
-        for (int64_t i = 0; i < n; ++i) {
-            double mx = 0;
-            for (int q = 0; q < e.q; ++q) mx = std::max(mx, (double)std::fabs(w[(size_t)q * n + i]));
-            bound += mx;
-        }
-        int ex2 = 61;
-        if (bound > 0) ex2 = (int)std::floor(std::log2(std::ldexp(1.0, 61) / bound));
+        for (int64_t i = 0; i < n; ++i)
+            for (int q = 0; q < e.q; ++q) bound = std::max(bound, (double)std::fabs(w[(size_t)q * n + i]));
+        int ex2 = 30;
+        if (bound > 0) ex2 = (int)std::floor(std::log2(std::ldexp(1.0, 30) / bound));
         ex2 = std::min(ex2, 100);
         if (ex2 < -100) fail(CORR_EUNSUPPORTED, "ball weights too large for the spreading sums");
         s.fix_scale = (float)std::ldexp(1.0, ex2);

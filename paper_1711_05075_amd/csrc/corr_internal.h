@@ -71,8 +71,8 @@ hipError_t launch_scatter_plan(const Geom& g, int S, int q, const Occupancy& occ
                                float* d_swts, int* d_plan, int* d_list, hipStream_t st);
 // a1 + a2 (x): gather-spreading of the sorted knots fused with the x transform;
 // writes [S][q][z][y][mx] without a spreading grid in HBM.
-// Sums are exact 64-bit fixed point; fix_scale is a power of two with
-// fix_scale * sum_i max_c |wts[c][i]| <= 2^61.
+// Sums are exact 64-bit fixed point of 32-bit addends; fix_scale is a power of
+// two with fix_scale * max_{i,c} |wts[c][i]| <= 2^30.
 // Runs g.spread_wgs persistent workgroups over the plan's tiles; a listed tile
 // that no knot reaches only records that in occ.tile_live.
 hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, int* d_plan, const int* d_list,

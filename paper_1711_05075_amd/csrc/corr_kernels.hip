@@ -394,8 +394,9 @@ __device__ __forceinline__ void bin_scatter(int64_t j, int s, const int* __restr
 // lane per window point, adding into 64-bit fixed-point sums with LDS integer
 // atomics: integer addition is exact and associative, so the result does not
 // depend on scheduling.  The fixed-point scale is a power of two chosen per
-// shape so that no sum can overflow.  A tile that no knot reaches only records
-// that in tile_live.
+// shape so that every addend fits 32 bits (one conversion instruction) and no
+// sum can overflow.  A tile that no knot reaches only records that in
+// tile_live.
 // ---------------------------------------------------------------------------
 template <int M>
 struct SpreadShape {
@@ -712,8 +713,10 @@ __device__ void spread_tile(int s, int z0, int y0, int yt, const int* __restrict
                         const int l = (cy - lo - y0 + ddy + 2 * M) & (M - 1);
                         if (i0 + u * NW < nst && t < w * w && l < TY) {
                             const int off = l * LS + ((cx - lo + ddx + M) & (M - 1));
-                            atomicAdd(acc + off, (unsigned long long)__float2ll_rn(c2[u].x * wyx[u]));
-                            atomicAdd(acc + TY * LS + off, (unsigned long long)__float2ll_rn(c2[u].y * wyx[u]));
+                            // |addend| <= 2^30: a 32-bit conversion, sign-extended
+                            atomicAdd(acc + off, (unsigned long long)(long long)__float2int_rn(c2[u].x * wyx[u]));
+                            atomicAdd(acc + TY * LS + off,
+                                      (unsigned long long)(long long)__float2int_rn(c2[u].y * wyx[u]));
                         }
                     }
                 }
