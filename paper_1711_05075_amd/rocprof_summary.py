@@ -51,8 +51,8 @@ def traffic(regex, fetch, write, cfetch, cwrite, copy_bytes, dst, cmds):
     copy_bytes = float(copy_bytes)
     f_kib, nf = _counter(fetch, regex, "FETCH_SIZE")
     w_kib, nw = _counter(write, regex, "WRITE_SIZE")
-    cf_kib, _ = _counter(cfetch, "copyBuffer|elementwise|copy", "FETCH_SIZE")
-    cw_kib, _ = _counter(cwrite, "copyBuffer|elementwise|copy", "WRITE_SIZE")
+    cf_kib, _ = _counter(cfetch, "copyBuffer", "FETCH_SIZE")
+    cw_kib, _ = _counter(cwrite, "copyBuffer", "WRITE_SIZE")
     kf, kw = copy_bytes / (cf_kib * 1024), copy_bytes / (cw_kib * 1024)
     total = kf * f_kib * 1024 + kw * w_kib * 1024
     sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
