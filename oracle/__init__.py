@@ -168,6 +168,35 @@ def o2_eval_at(FA, FB, L, t) -> np.ndarray:
     return np.array(out)
 
 
+# ---- single-configuration query (Sec. 4.1, eq. eq_single) ---------------------
+
+def o2_query(FA, FB, L, t, mode_radius2) -> np.ndarray:
+    """The Parseval form of the score at arbitrary translations, summed only over
+    the modes with |m|^2 <= mode_radius2 (and |m_d| < N/2):
+    s(t) = (1/L^3) sum_m F_A(k_m) conj(F_RB(k_m)) exp(i k_m . t)."""
+    n = FA.shape[0]
+    m = mode_numbers(n)
+    m2 = m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2
+    keep = (m2 <= mode_radius2) & (np.abs(m)[:, None, None] < n // 2) & (np.abs(m)[None, :, None] < n // 2) \
+        & (np.abs(m)[None, None, :] < n // 2)
+    k = 2.0 * np.pi * m / L
+    S = np.where(keep, FA * np.conj(FB), 0.0) / L ** 3
+    out = []
+    for p in np.atleast_2d(t):
+        ph = (np.exp(1j * k * p[2])[:, None, None] * np.exp(1j * k * p[1])[None, :, None]
+              * np.exp(1j * k * p[0])[None, None, :])
+        out.append(np.real(np.sum(S * ph)))
+    return np.array(out)
+
+
+def query_mode_count(n, mode_radius2) -> int:
+    """Number of modes |m|^2 <= mode_radius2, |m_d| < n/2 (the full sphere)."""
+    m = mode_numbers(n)
+    ok = np.abs(m) < n // 2
+    m2 = m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2
+    return int(np.sum((m2 <= mode_radius2) & ok[:, None, None] & ok[None, :, None] & ok[None, None, :]))
+
+
 # ---- shape-complementarity score (Sec. 4.2, eq. eq_score) ---------------------
 #
 # The affinity of a shape is F_S = i (f_{S (+) B0} - lam f_S).  For a union of

@@ -481,3 +481,52 @@ def test_sc_o2_is_band_limited_projection_of_o1():
         errs.append(np.abs(sp - s2).max() / np.abs(s2).max())
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 1e-4
+
+
+# --------------------------------------------------------------------------
+# Single-configuration query (Sec. 4.1, eq. eq_single)
+# --------------------------------------------------------------------------
+
+def test_query_with_every_mode_is_the_band_limited_score_on_the_grid():
+    A, B, q, g, _ = synth.tiny_case()
+    qr = synth.random_quaternions(1, 61)[0]
+    FA = oracle.o2_spectrum(A, np.eye(3), g.n, g.box)
+    FB = oracle.o2_spectrum(B, oracle.quat_to_rot(qr), g.n, g.box)
+    s2 = oracle.o2_scores_from_spectra(FA, FB, g.box, g.origin)
+    idx = np.random.default_rng(7).integers(0, g.n, (20, 3))
+    t = np.asarray(g.origin)[None, :] + g.h * idx[:, ::-1]
+    full = 3 * (g.n // 2) ** 2
+    np.testing.assert_allclose(oracle.o2_query(FA, FB, g.box, t, full), s2[tuple(idx.T)], rtol=1e-9,
+                               atol=1e-12 * np.abs(s2).max())
+
+
+def test_query_with_only_the_dc_mode_is_the_mean_score():
+    # |m|^2 <= 0 keeps the DC mode: V_A V_B / L^3 at every translation
+    A, B, q, g, _ = synth.tiny_case()
+    FA = oracle.o2_spectrum(A, np.eye(3), g.n, g.box)
+    FB = oracle.o2_spectrum(B, np.eye(3), g.n, g.box)
+    va = np.sum(A[:, 4] * 4 * np.pi * A[:, 3] ** 3 / 3)
+    vb = np.sum(B[:, 4] * 4 * np.pi * B[:, 3] ** 3 / 3)
+    t = np.random.default_rng(3).uniform(-1, 1, (5, 3))
+    np.testing.assert_allclose(oracle.o2_query(FA, FB, g.box, t, 0), va * vb / g.box ** 3, rtol=1e-12)
+    assert oracle.query_mode_count(g.n, 0) == 1
+    assert oracle.query_mode_count(g.n, 1) == 7
+    assert oracle.query_mode_count(g.n, 3 * (g.n // 2) ** 2) == (g.n - 1) ** 3
+
+
+def test_query_approaches_the_plain_score_as_modes_are_added():
+    # away from the grid, the truncated Parseval sum tends to the band-limited
+    # score, whose gap to the plain lens sum (O1) is the band limit's
+    A, B, q, g, _ = synth.tiny_case()
+    qr = synth.random_quaternions(1, 62)[0]
+    R = oracle.quat_to_rot(qr)
+    FA = oracle.o2_spectrum(A, np.eye(3), g.n, g.box)
+    FB = oracle.o2_spectrum(B, R, g.n, g.box)
+    t = np.random.default_rng(11).uniform(-0.3, 0.3, (40, 3))
+    s1 = oracle.o1_points(A, B, R, t)
+    # (the tiny case's balls are smaller than a grid step, so the full band
+    # still differs from O1 by ~27 %; the decrease is not monotone shell by shell)
+    errs = [np.abs(oracle.o2_query(FA, FB, g.box, t, r2) - s1).max() / np.abs(s1).max()
+            for r2 in (1, 9, 100, 3 * (g.n // 2) ** 2)]
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[3] < 0.3
