@@ -147,7 +147,8 @@ int corr_info(const corr_ctx* ctx, corr_info_t* out);
 #define CORR_STAGE_IFFT_Y         6  /* a5: inverse y pass                            */
 #define CORR_STAGE_IFFT_X         7  /* a5: inverse x pass (to real) + block peaks    */
 #define CORR_STAGE_PEAK           8  /* a5: per-rotation peak                         */
-#define CORR_N_STAGES             9
+#define CORR_STAGE_QUERY          9  /* single-configuration query (corr_query)       */
+#define CORR_N_STAGES            10
 
 /* Turn per-stage timing on (enable != 0) or off.  While on, every stage launch
  * on the context's stream is bracketed by a pair of HIP events. */
@@ -157,6 +158,24 @@ int corr_profile(corr_ctx* ctx, int32_t enable);
  * summed device time in milliseconds (ms) and the number of launches timed
  * since the last read; clears the record. */
 int corr_profile_read(corr_ctx* ctx, double* ms, int64_t* launches, int32_t n_stages);
+
+/*
+ * Time-critical score of single configurations (Sec. 4.1, eq. eq_single): for
+ * B turned by quat_wxyz (host, 4 doubles), the band-limited score at n_t
+ * arbitrary translations t_host (host double [n_t][3], any position, not only
+ * grid points), as the Parseval sum
+ *   s(t) = (1/L^3) sum_m F_A(k_m) conj(F_RB(k_m)) exp(i k_m . t)
+ * over the modes with |m|^2 <= mode_radius2 and |m_d| < n/2: a ball of modes
+ * grown from the dominant low modes, trading accuracy for time.  A radius of
+ * 3 (n/2 - 1)^2 or more keeps every mode, which at grid points is the score of
+ * corr_eval.  F_A is the fixed shape's prepared spectrum; F_RB is evaluated at
+ * the kept modes directly from B's knots (no spreading grid).  Writes out_dev
+ * (device float [n_t]) asynchronously on the context's stream; if n_modes is
+ * not NULL it receives the number of modes summed (counting m and -m).  A
+ * score kind set at create (CORR_SC_SCORE) applies here too.
+ */
+int corr_query(corr_ctx* ctx, const double* quat_wxyz, const double* t_host, int64_t n_t, int32_t mode_radius2,
+               float* out_dev, int64_t* n_modes);
 
 /* Occupancy of the last spreading pass run by ctx (the rotations of the last
  * batch of corr_eval, or one shape for corr_prepare_a / corr_spectrum).  The

@@ -30,10 +30,12 @@ CORR_DETERMINISTIC = 1
 CORR_SC_SCORE = 2
 
 EXPORTS = ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
-           "corr_profile_read", "corr_pass_info", "corr_destroy", "corr_last_error", "corr_batch_create",
+           "corr_profile_read", "corr_pass_info", "corr_query", "corr_destroy", "corr_last_error",
+           "corr_batch_create",
            "corr_batch_eval",
            "corr_batch_info", "corr_batch_destroy", "corr_batch_last_error")
-STAGES = ("rotate", "bin", "spread_fft_x", "fft_y", "fft_z_spectrum", "fft_z_product", "ifft_y", "ifft_x", "peak")
+STAGES = ("rotate", "bin", "spread_fft_x", "fft_y", "fft_z_spectrum", "fft_z_product", "ifft_y", "ifft_x", "peak",
+          "query")
 
 
 class corr_grid(ctypes.Structure):
@@ -82,11 +84,12 @@ def load_library(path: str = LIB_PATH):
     lib.corr_profile.argtypes = [vp, i32]
     lib.corr_profile_read.argtypes = [vp, vp, vp, i32]
     lib.corr_pass_info.argtypes = [vp, ctypes.POINTER(corr_pass_t)]
+    lib.corr_query.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(ctypes.c_int64)]
     lib.corr_destroy.argtypes = [vp]
     lib.corr_last_error.argtypes = [vp]
     lib.corr_last_error.restype = ctypes.c_char_p
     for name in ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
-                 "corr_profile_read", "corr_pass_info", "corr_destroy"):
+                 "corr_profile_read", "corr_pass_info", "corr_query", "corr_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -153,6 +156,16 @@ def corr_pass_info(ctx) -> dict:
     return {k: getattr(r, k) for k, _ in corr_pass_t._fields_}
 
 
+def corr_query(ctx, quat, t, mode_radius2, out_ptr) -> int:
+    """Score of single configurations (t: [n][3] host); returns the number of modes summed."""
+    q = np.ascontiguousarray(np.asarray(quat, dtype=np.float64).reshape(4))
+    t = np.ascontiguousarray(np.asarray(t, dtype=np.float64).reshape(-1, 3))
+    nm = ctypes.c_int64()
+    _check(load_library().corr_query(ctx, q.ctypes.data, t.ctypes.data if len(t) else None, len(t), int(mode_radius2),
+                                     out_ptr or None, ctypes.byref(nm)), ctx)
+    return nm.value
+
+
 def corr_destroy(ctx):
     load_library().corr_destroy(ctx)
 
@@ -211,6 +224,16 @@ class Correlator:
 
     def pass_info(self):
         return corr_pass_info(self.ctx)
+
+    def query(self, quat, t, mode_radius2):
+        """Score at translations t ([n][3]) over the modes |m|^2 <= mode_radius2;
+        returns (scores tensor [n], modes summed)."""
+        torch = self.torch
+        t = np.asarray(t, dtype=np.float64).reshape(-1, 3)
+        out = torch.empty(len(t), dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            nm = corr_query(self.ctx, quat, t, mode_radius2, out.data_ptr() if len(t) else None)
+        return out, nm
 
     def spectrum(self, which, quat=None):
         torch = self.torch

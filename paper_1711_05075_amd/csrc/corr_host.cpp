@@ -382,6 +382,19 @@ struct corr_ctx {
     // the last spreading pass: rotations, components, knots
     int last_S = 0, last_q = 0;
     int64_t last_nk = 0;
+    // single-configuration query: half-space mode list of the last radius, and
+    // buffers grown on demand (freed at destroy or when they grow)
+    struct Grown {
+        void* p = nullptr;
+        size_t cap = 0;
+    };
+    Grown q_modes, q_part, q_P, q_t, q_quat, q_tpart;
+    double* q_host = nullptr;  // pinned staging of the rotation and translations
+    size_t q_host_cap = 0;
+    hipEvent_t q_done = nullptr;  // the last copy out of q_host
+    int32_t q_r2 = -1;
+    int q_nm = 0;
+    int64_t q_full = 0;
     // stage timing (corr_profile): event pairs recorded around each launch
     bool profiling = false;
     struct Mark { int stage; hipEvent_t a, b; };
@@ -729,6 +742,10 @@ int guarded(corr_ctx* c, F&& body) {
 void destroy_ctx(corr_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    for (auto* g : {&c->q_modes, &c->q_part, &c->q_P, &c->q_t, &c->q_quat, &c->q_tpart})
+        if (g->p) (void)hipFree(g->p);
+    if (c->q_host) (void)hipHostFree(c->q_host);
+    if (c->q_done) (void)hipEventDestroy(c->q_done);
     c->mem.release();
     if (c->own_ws && c->ws) {
         c->ws->release();
@@ -888,6 +905,112 @@ int corr_pass_info(corr_ctx* c, corr_pass_t* out) {
             }
         }
         *out = r;
+    });
+}
+
+namespace {
+
+// Grow g to at least `bytes` (after the stream has drained its last users).
+void* grow(corr_ctx* c, corr_ctx::Grown& g, size_t bytes) {
+    if (bytes <= g.cap) return g.p;
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (g.p) (void)hipFree(g.p);
+    g.p = nullptr;
+    g.cap = 0;
+    if (hipMalloc(&g.p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        g.p = nullptr;
+        fail(CORR_ENOMEM, "hipMalloc(%zu) for a query", bytes);
+    }
+    g.cap = bytes;
+    return g.p;
+}
+
+// Half-space modes with |m|^2 <= r2 and |m_d| < n/2, in shell order (|m|^2, then
+// mz, my, mx); returns the full-sphere count (m and -m).
+int64_t query_modes(int n, int32_t r2, std::vector<int>& out) {
+    const int h = n / 2 - 1;
+    struct Md { int m2, mz, my, mx; };
+    std::vector<Md> v;
+    for (int mz = -h; mz <= h; ++mz)
+        for (int my = -h; my <= h; ++my)
+            for (int mx = 0; mx <= h; ++mx) {
+                const int m2 = mx * mx + my * my + mz * mz;
+                if (m2 > r2) continue;
+                const bool half = mx > 0 || (mx == 0 && (my > 0 || (my == 0 && mz >= 0)));
+                if (half) v.push_back({m2, mz, my, mx});
+            }
+    std::sort(v.begin(), v.end(), [](const Md& a, const Md& b) {
+        if (a.m2 != b.m2) return a.m2 < b.m2;
+        if (a.mz != b.mz) return a.mz < b.mz;
+        if (a.my != b.my) return a.my < b.my;
+        return a.mx < b.mx;
+    });
+    out.resize(v.size());
+    for (size_t i = 0; i < v.size(); ++i)
+        out[i] = (v[i].mx + 512) | ((v[i].my + 512) << 10) | ((v[i].mz + 512) << 20);
+    return 2 * (int64_t)v.size() - 1;
+}
+
+}  // namespace
+
+int corr_query(corr_ctx* c, const double* quat_wxyz, const double* t_host, int64_t n_t, int32_t mode_radius2,
+               float* out_dev, int64_t* n_modes) {
+    if (!c) {
+        g_thread_error = "corr_query: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] {
+        if (n_t < 0 || n_t > INT32_MAX) fail(CORR_EINVAL, "n_t = %lld; allowed 0..2^31-1", (long long)n_t);
+        if (mode_radius2 < 0) fail(CORR_EINVAL, "mode_radius2 must be >= 0");
+        if (n_t > 0 && (!t_host || !out_dev)) fail(CORR_EINVAL, "NULL translations or output");
+        validate_quats(quat_wxyz, 1);
+        for (int64_t i = 0; i < 3 * n_t; ++i)
+            if (!std::isfinite(t_host[i])) fail(CORR_EINVAL, "translation %lld is not finite", (long long)(i / 3));
+        const Geom& g = c->g;
+        const int32_t full = 3 * (g.n / 2 - 1) * (g.n / 2 - 1);
+        const int32_t r2 = std::min(mode_radius2, full);
+        if (r2 != c->q_r2) {
+            std::vector<int> modes;
+            c->q_full = query_modes(g.n, r2, modes);
+            void* d = grow(c, c->q_modes, sizeof(int) * modes.size());
+            hip_check(hipMemcpyAsync(d, modes.data(), sizeof(int) * modes.size(), hipMemcpyHostToDevice, c->stream),
+                      "mode list H2D");
+            hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+            c->q_nm = (int)modes.size();
+            c->q_r2 = r2;
+        }
+        if (n_modes) *n_modes = c->q_full;
+        if (n_t == 0) return;
+        const Shape& B = c->B;
+        const int nm = c->q_nm;
+        const corr::QueryPlan qp = corr::query_plan(nm, B.n, n_t);
+        auto* part = static_cast<float2*>(grow(c, c->q_part, sizeof(float2) * nm * (size_t)qp.chunks));
+        auto* tpart = static_cast<float*>(grow(c, c->q_tpart, sizeof(float) * (size_t)n_t * qp.mblocks));
+        auto* P = static_cast<float2*>(grow(c, c->q_P, sizeof(float2) * nm));
+        auto* dq = static_cast<double*>(grow(c, c->q_quat, sizeof(double) * 4));
+        auto* dt = static_cast<double*>(grow(c, c->q_t, sizeof(double) * 3 * (size_t)n_t));
+        // the caller's arrays are copied into pinned staging before returning
+        const size_t need = 4 + 3 * (size_t)n_t;
+        if (c->q_done) hip_check(hipEventSynchronize(c->q_done), "event sync");
+        else hip_check(hipEventCreateWithFlags(&c->q_done, hipEventDisableTiming), "hipEventCreate");
+        if (need > c->q_host_cap) {
+            if (c->q_host) (void)hipHostFree(c->q_host);
+            c->q_host = nullptr;
+            c->q_host_cap = 0;
+            hip_check(hipHostMalloc((void**)&c->q_host, sizeof(double) * need, hipHostMallocDefault), "hipHostMalloc");
+            c->q_host_cap = need;
+        }
+        std::memcpy(c->q_host, quat_wxyz, sizeof(double) * 4);
+        std::memcpy(c->q_host + 4, t_host, sizeof(double) * 3 * n_t);
+        hip_check(hipMemcpyAsync(dq, c->q_host, sizeof(double) * 4, hipMemcpyHostToDevice, c->stream), "quat H2D");
+        hip_check(hipMemcpyAsync(dt, c->q_host + 4, sizeof(double) * 3 * n_t, hipMemcpyHostToDevice, c->stream),
+                  "translations H2D");
+        hip_check(hipEventRecord(c->q_done, c->stream), "hipEventRecord");
+        stage(c, CORR_STAGE_QUERY, "query", [&] {
+            return corr::launch_query(g, qp, static_cast<const int*>(c->q_modes.p), nm, dq, B.pos, B.wts, B.n,
+                                      B.ex.q, B.vtab, c->box, part, c->fa, P, dt, n_t, tpart, out_dev, c->stream);
+        });
     });
 }
 

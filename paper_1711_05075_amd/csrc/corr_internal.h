@@ -104,4 +104,18 @@ hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scor
 hipError_t launch_peak_final(const float* d_pval, const int* d_pidx, int S, int nblocks,
                              float* d_peak_val, int64_t* d_peak_idx, hipStream_t st);
 
+// ---- single-configuration query -------------------------------------------
+// d_modes: nm packed modes (mx + 512) | (my + 512) << 10 | (mz + 512) << 20 of the
+// half space.  Scratch: d_part float2 [chunks][nm], d_P float2 [nm], d_tpart
+// float [n_t][mblocks].
+struct QueryPlan {
+    int kch = 256, chunks = 1;  // knots per NDFT chunk, chunks
+    int mblocks = 1, mper = 1;  // mode blocks per translation sum, modes per block
+};
+QueryPlan query_plan(int nm, int64_t nk, int64_t n_t);
+hipError_t launch_query(const Geom& g, const QueryPlan& qp, const int* d_modes, int nm, const double* d_quat,
+                        const double* d_pos, const float* d_wts, int64_t nk, int q, const float* d_vtab, double box,
+                        float2* d_part, const float2* d_fa, float2* d_P, const double* d_t, int64_t n_t,
+                        float* d_tpart, float* d_out, hipStream_t st);
+
 }  // namespace corr

@@ -1154,6 +1154,150 @@ __global__ __launch_bounds__(kThreads) void k_peak_final(const float* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single-configuration query (Sec. 4.1, eq. eq_single): the score at arbitrary
+// translations as the Parseval sum (1/L^3) sum_m F_A(k_m) conj(F_RB(k_m))
+// exp(i k_m . t) over a truncated set of modes.  F_RB is evaluated directly at
+// the kept modes (an NDFT of the rotated knots on the radius expansion), so no
+// spreading grid is involved.  Modes are listed once per pair of +-m (half
+// space: mx > 0, or mx = 0 and my > 0, or mx = my = 0 and mz >= 0); the
+// summand of a pair is twice the real part of one of them, the DC once.
+// ---------------------------------------------------------------------------
+constexpr int kQBlock = 256;   // threads per workgroup
+constexpr int kQModes = 64;    // modes per NDFT workgroup (a wave each), 4 knot groups
+constexpr int kQMaxChunk = 256;
+
+__device__ __forceinline__ void unpack_mode(int p, int& mx, int& my, int& mz) {
+    mx = (p & 1023) - 512;
+    my = ((p >> 10) & 1023) - 512;
+    mz = ((p >> 20) & 1023) - 512;
+}
+
+// part[chunk][mode] = sum over the chunk's knots j of
+//   (sum_c vtab[c][|m|^2] wts[c][j]) exp(-2 pi i m . (R y_j) / L);
+// a workgroup takes kQModes modes, its four waves a quarter of the chunk each.
+__global__ __launch_bounds__(kQBlock) void k_query_ndft(const int* __restrict__ modes, int nm,
+                                                        const double* __restrict__ quat,
+                                                        const double* __restrict__ pos,
+                                                        const float* __restrict__ wts, int64_t nk, int q, int kch,
+                                                        const float* __restrict__ vtab, int m2n, double inv_l,
+                                                        float2* __restrict__ part) {
+    __shared__ double su[kQMaxChunk][3];
+    __shared__ float sw[32][kQMaxChunk];
+    __shared__ float2 red[4][kQModes];
+    const int chunk = blockIdx.y;
+    const int64_t j0 = (int64_t)chunk * kch;
+    const int nj = (int)min<int64_t>(kch, nk - j0);
+    {
+        const double nn = sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3]);
+        const double w = quat[0] / nn, x = quat[1] / nn, y = quat[2] / nn, z = quat[3] / nn;
+        const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z),    2 * (x * z + w * y),
+                             2 * (x * y + w * z),    1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                             2 * (x * z - w * y),    2 * (y * z + w * x),    1 - 2 * (x * x + y * y)};
+        for (int t = threadIdx.x; t < nj; t += kQBlock) {
+            const double px = pos[3 * (j0 + t)], py = pos[3 * (j0 + t) + 1], pz = pos[3 * (j0 + t) + 2];
+            su[t][0] = (R[0] * px + R[1] * py + R[2] * pz) * inv_l;
+            su[t][1] = (R[3] * px + R[4] * py + R[5] * pz) * inv_l;
+            su[t][2] = (R[6] * px + R[7] * py + R[8] * pz) * inv_l;
+            for (int c = 0; c < q; ++c) sw[c][t] = wts[(size_t)c * nk + j0 + t];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int mi = blockIdx.x * kQModes + lane;
+    float ar = 0.f, ai = 0.f;
+    if (mi < nm) {
+        int mx, my, mz;
+        unpack_mode(modes[mi], mx, my, mz);
+        const int m2 = mx * mx + my * my + mz * mz;
+        float v[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) v[c] = c < q ? vtab[(size_t)c * m2n + m2] : 0.f;
+        for (int j = grp; j < nj; j += 4) {
+            float kj = 0.f;
+#pragma unroll
+            for (int c = 0; c < 32; ++c) {
+                if (c >= q) break;
+                kj += v[c] * sw[c][j];
+            }
+            // phase in cycles, reduced in FP64 before the FP32 sine and cosine
+            const double ph = (double)mx * su[j][0] + (double)my * su[j][1] + (double)mz * su[j][2];
+            const float f = (float)(ph - rint(ph));
+            float sn, cs;
+            sincospif(2.0f * f, &sn, &cs);
+            ar += kj * cs;
+            ai -= kj * sn;
+        }
+    }
+    red[grp][lane] = make_float2(ar, ai);
+    __syncthreads();
+    if (grp == 0 && mi < nm) {
+        const float2 a0 = red[0][lane], a1 = red[1][lane], a2 = red[2][lane], a3 = red[3][lane];
+        part[(size_t)chunk * nm + mi] = make_float2((a0.x + a1.x) + (a2.x + a3.x), (a0.y + a1.y) + (a2.y + a3.y));
+    }
+}
+
+// P[mode] = weight * F_A(k_m) conj(F_RB(k_m)) / L^3, F_RB = sum of the chunks in
+// order; F_A from the prepared half spectrum [mz][my][mx], mx >= 0.
+__global__ __launch_bounds__(kQBlock) void k_query_reduce(const int* __restrict__ modes, int nm, int chunks,
+                                                          const float2* __restrict__ part,
+                                                          const float2* __restrict__ fa, int n, double inv_l3,
+                                                          float2* __restrict__ P) {
+    const int mi = blockIdx.x * kQBlock + threadIdx.x;
+    if (mi >= nm) return;
+    float br = 0.f, bi = 0.f;
+    for (int c = 0; c < chunks; ++c) {
+        const float2 v = part[(size_t)c * nm + mi];
+        br += v.x;
+        bi += v.y;
+    }
+    int mx, my, mz;
+    unpack_mode(modes[mi], mx, my, mz);
+    const float2 A = fa[((size_t)((mz + n) % n) * n + (my + n) % n) * (n / 2) + mx];
+    const float wgt = (float)(((mx | my | mz) == 0 ? 1.0 : 2.0) * inv_l3);
+    // A * conj(B)
+    P[mi] = make_float2((A.x * br + A.y * bi) * wgt, (A.y * br - A.x * bi) * wgt);
+}
+
+// tpart[t][b] = sum over mode block b of Re(P_m exp(2 pi i m . t / L)); the mode
+// list is cut into gridDim.y blocks of mper modes.
+__global__ __launch_bounds__(kQBlock) void k_query_sum(const int* __restrict__ modes, int nm, int mper,
+                                                       const float2* __restrict__ P,
+                                                       const double* __restrict__ t, double inv_l,
+                                                       float* __restrict__ tpart) {
+    __shared__ float red[kQBlock];
+    const double tx = t[3 * blockIdx.x] * inv_l, ty = t[3 * blockIdx.x + 1] * inv_l, tz = t[3 * blockIdx.x + 2] * inv_l;
+    const int m0 = blockIdx.y * mper, m1 = min(nm, m0 + mper);
+    float acc = 0.f;
+    for (int mi = m0 + threadIdx.x; mi < m1; mi += kQBlock) {
+        int mx, my, mz;
+        unpack_mode(modes[mi], mx, my, mz);
+        const double ph = (double)mx * tx + (double)my * ty + (double)mz * tz;
+        const float f = (float)(ph - rint(ph));
+        float sn, cs;
+        sincospif(2.0f * f, &sn, &cs);
+        const float2 p = P[mi];
+        acc += p.x * cs - p.y * sn;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = kQBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tpart[(size_t)blockIdx.x * gridDim.y + blockIdx.y] = red[0];
+}
+
+// out[t] = sum of its mode blocks, in order.
+__global__ __launch_bounds__(kQBlock) void k_query_final(const float* __restrict__ tpart, int nb, int64_t n_t,
+                                                         float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kQBlock + threadIdx.x;
+    if (i >= n_t) return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += tpart[(size_t)i * nb + b];
+    out[i] = s;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1363,4 +1507,44 @@ hipError_t launch_peak_final(const float* d_pval, const int* d_pidx, int S, int 
     return hipGetLastError();
 }
 
+QueryPlan query_plan(int nm, int64_t nk, int64_t n_t) {
+    QueryPlan p;
+    const int mb = (nm + kQModes - 1) / kQModes;
+    // knots per chunk: a power of two in 16..256, small enough for ~1024
+    // workgroups, but at most 32 chunks (the reduction walks them in order)
+    p.kch = kQMaxChunk;
+    while (p.kch > 16 && (int64_t)mb * ((nk + p.kch - 1) / p.kch) < 1024 && (nk + p.kch / 2 - 1) / (p.kch / 2) <= 32)
+        p.kch >>= 1;
+    p.chunks = (int)std::max<int64_t>(1, (nk + p.kch - 1) / p.kch);
+    // translation sums: enough mode blocks for ~1024 workgroups, at least 1024 modes each
+    p.mblocks = 1;
+    while (p.mblocks < 1024 && n_t * p.mblocks < 1024 && (int64_t)nm > 1024 * p.mblocks) p.mblocks <<= 1;
+    p.mper = (nm + p.mblocks - 1) / p.mblocks;
+    return p;
+}
+
+hipError_t launch_query(const Geom& g, const QueryPlan& qp, const int* d_modes, int nm, const double* d_quat,
+                        const double* d_pos, const float* d_wts, int64_t nk, int q, const float* d_vtab, double box,
+                        float2* d_part, const float2* d_fa, float2* d_P, const double* d_t, int64_t n_t,
+                        float* d_tpart, float* d_out, hipStream_t st) {
+    if (n_t == 0) return hipSuccess;
+    if (nk > 0)  // an empty shape has F_RB = 0: the reduction below then sums no chunk
+        hipLaunchKernelGGL(k_query_ndft, dim3((nm + kQModes - 1) / kQModes, qp.chunks), dim3(kQBlock), 0, st,
+                           d_modes, nm, d_quat, d_pos, d_wts, nk, q, qp.kch, d_vtab, g.m2n, 1.0 / box, d_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_query_reduce, dim3((nm + kQBlock - 1) / kQBlock), dim3(kQBlock), 0, st, d_modes, nm,
+                       nk > 0 ? qp.chunks : 0, d_part, d_fa, g.n, 1.0 / (box * box * box), d_P);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_query_sum, dim3((unsigned)n_t, qp.mblocks), dim3(kQBlock), 0, st, d_modes, nm, qp.mper,
+                       d_P, d_t, 1.0 / box, d_tpart);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_query_final, dim3((unsigned)((n_t + kQBlock - 1) / kQBlock)), dim3(kQBlock), 0, st,
+                       d_tpart, qp.mblocks, n_t, d_out);
+    return hipGetLastError();
+}
+
 }  // namespace corr
+

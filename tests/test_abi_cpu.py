@@ -110,6 +110,7 @@ def test_create_rejects_null_arguments(lib):
 
 def test_null_context_calls_fail_cleanly(lib):
     assert lib.corr_eval(None, None, 0, None, None, None) == pkg.CORR_EINVAL
+    assert lib.corr_query(None, None, None, 0, 0, None, None) == pkg.CORR_EINVAL
     assert lib.corr_prepare_a(None) == pkg.CORR_EINVAL
     assert lib.corr_spectrum(None, 0, None, None) == pkg.CORR_EINVAL
     assert lib.corr_info(None, None) == pkg.CORR_EINVAL
