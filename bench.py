@@ -26,7 +26,6 @@ import synth  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1711_05075_amd", "csrc", "corr_kernels.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_spread_fftx_single_rotation_4096_n128.txt")
 
 
@@ -64,7 +63,7 @@ def stage_bytes(info, pa, pb):
 def measured_traffic():
     """HBM bytes per launch of the spreading kernel from the committed counter
     summary, if it was taken on the current kernel source; else None."""
-    import hashlib
+    from paper_1711_05075_amd.rocprof_summary import kernel_source_digest
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     fields = {}
@@ -72,8 +71,7 @@ def measured_traffic():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != src:
+    if fields.get("kernel_source_sha256") != kernel_source_digest():
         return None
     return float(fields["hbm_bytes_per_launch"])
 

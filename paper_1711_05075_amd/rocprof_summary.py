@@ -20,6 +20,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1711_05075_amd", "csrc", "corr_kernels.hip")
 
 
+def kernel_source_digest(text=None):
+    """SHA-256 of the source the spreading kernel is compiled from: the kernel
+    file up to the end of k_spread_fftx (the column FFT engine, the sort and
+    spreading code), so that later kernels in the file do not void counters
+    taken on it."""
+    if text is None:
+        text = open(KERNEL_SOURCE).read()
+    end = text.index("// Index of kept output mode")
+    return hashlib.sha256(text[:end].encode()).hexdigest()
+
+
 def _short(name):
     name = re.sub(r"\(anonymous namespace\)::", "", name)
     return re.sub(r"^void ", "", name).split("(")[0].split("::")[-1]
@@ -55,11 +66,12 @@ def traffic(regex, fetch, write, cfetch, cwrite, copy_bytes, dst, cmds):
     cw_kib, _ = _counter(cwrite, "copyBuffer", "WRITE_SIZE")
     kf, kw = copy_bytes / (cf_kib * 1024), copy_bytes / (cw_kib * 1024)
     total = kf * f_kib * 1024 + kw * w_kib * 1024
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    sha = kernel_source_digest()
     lines = ["# HBM traffic per launch of kernels matching /%s/" % regex, "#",
              "# commands (one MI355X, repository root; one counter per run):"]
     lines += ["#   " + c for c in cmds.split(";;")]
     lines += ["#",
+              "# kernel_source_sha256 covers corr_kernels.hip up to the end of k_spread_fftx.",
               "# FETCH_SIZE and WRITE_SIZE are KiB per dispatch; each is scaled by what it",
               "# reads for a plain copy of %d bytes per launch." % copy_bytes, "",
               "dispatches_fetch: %d" % nf, "dispatches_write: %d" % nw,
