@@ -17,6 +17,9 @@ Two oracles, both written from Behandish & Ilies (CAD 2016):
   inverse FFT onto an L-periodic translation grid, keeping |m_d| < N/2.
 * ``*_sc_*`` -- the shape-complementarity score (Sec. 4.2 eq. eq_score), built
   from the two above by its definition.
+* ``obstacle``, ``o1_obstacle_points``, ``offset_balls`` -- the configuration
+  obstacle as the positive set of the score (Sec. 3.1 eq. eq_obs), its
+  pairwise Minkowski-sum form, and the offset slices (Sec. 3.1).
 
 The heavy loops live in ``oracle.c`` (plain C, OpenMP), built on first use with
 gcc into ``liboracle.so`` next to this file.
@@ -245,3 +248,48 @@ def peak(scores) -> tuple:
     s = np.asarray(scores).reshape(scores.shape[0], -1) if np.ndim(scores) == 4 else np.asarray(scores).reshape(1, -1)
     idx = np.argmax(s, axis=1)
     return s[np.arange(len(s)), idx], idx
+
+
+# ---- configuration obstacle and offset obstacles ------------------------------
+#
+# For a fixed rotation the translational obstacle is the set of translations
+# where the score is positive (Sec. 3.1 eq. eq_obs); for unions of balls it is
+# the union, over every pair of primitives, of the ball of radius r_i + rho_j
+# about x_i - R y_j (the Minkowski-sum form of Sec. 3.1, eqs. eq_ORP and
+# eq_ORA, taken pair by pair).  Slices of the lifted obstacle away from r = 0
+# are the obstacles of the primitives offset by a total of delta (Sec. 3.1,
+# offset obstacles); here the whole offset is put on A's balls.
+
+def obstacle(scores, threshold=0.0) -> np.ndarray:
+    """The translations whose score exceeds threshold (threshold 0: eq. eq_obs)."""
+    return np.asarray(scores) > threshold
+
+
+def o1_obstacle_points(A, B, R, t) -> np.ndarray:
+    """Obstacle membership from the Minkowski-sum form, by brute force over all
+    pairs: t is inside iff |x_i - R y_j - t| < r_i + rho_j for some pair (for
+    positive weights, where this is exactly where the plain score is > 0)."""
+    A, B, R = _f64(A), _f64(B), _f64(R)
+    t = _f64(np.atleast_2d(t))
+    RB = B[:, :3] @ R.T
+    inside = np.zeros(len(t), dtype=bool)
+    for i in range(len(A)):
+        d = A[i, None, None, :3] - RB[None, :, :] - t[:, None, :]     # [t][j][3]
+        dist = np.sqrt(np.sum(d * d, axis=2))
+        inside |= np.any(dist < A[i, 3] + B[None, :, 3], axis=1)
+    return inside
+
+
+def offset_balls(balls, delta) -> np.ndarray:
+    """Every primitive ball's radius changed by delta (grown for delta > 0,
+    shrunk for delta < 0; every radius must stay positive)."""
+    b = _f64(balls).copy()
+    b[:, 3] += delta
+    if len(b) and not np.all(b[:, 3] > 0):
+        raise ValueError("offset %g leaves a radius <= 0" % delta)
+    return b
+
+
+def o2_offset_scores(A, B, q, n, L, origin, delta) -> np.ndarray:
+    """Band-limited score of the offset slice delta: A's balls offset by delta."""
+    return o2_scores(offset_balls(A, delta), B, q, n, L, origin)

@@ -530,3 +530,77 @@ def test_query_approaches_the_plain_score_as_modes_are_added():
             for r2 in (1, 9, 100, 3 * (g.n // 2) ** 2)]
     assert errs[0] > errs[1] > errs[2] > errs[3]
     assert errs[3] < 0.3
+
+
+# --------------------------------------------------------------------------
+# Configuration obstacle and offset obstacles (Sec. 3.1 eq. eq_obs, offset slices)
+# --------------------------------------------------------------------------
+
+def _gap(A, B, R, t):
+    """min over pairs of |x_i - R y_j - t| - r_i - rho_j, written out directly."""
+    c = A[:, None, :3] - (B[:, :3] @ R.T)[None, :, :]                       # [i][j][3]
+    rs = A[:, None, 3] + B[None, :, 3]
+    d = np.linalg.norm(t[:, None, None, :] - c[None], axis=-1) - rs[None]
+    return d.reshape(len(t), -1).min(axis=1)
+
+
+def _obstacle_probe_points(A, B, R, g, n_uniform=800, n_near=1600, spread=0.1):
+    c = (A[:, None, :3] - (B[:, :3] @ R.T)[None, :, :]).reshape(-1, 3)
+    near = c[g.integers(0, len(c), n_near)] + g.uniform(-spread, spread, (n_near, 3))
+    return np.concatenate([g.uniform(-0.8, 0.8, (n_uniform, 3)), near])
+
+
+def test_obstacle_of_the_plain_score_is_the_pairwise_minkowski_union():
+    # unequal radii: the plain score is > 0 exactly on the union of the balls of
+    # radius r_i + rho_j about x_i - R y_j (eq. eq_obs, eq. eq_ORA pair by pair)
+    g = np.random.default_rng(71)
+    A = np.column_stack([g.random((7, 3)) * 0.4, g.uniform(0.02, 0.07, 7), np.ones(7)])
+    B = np.column_stack([g.random((6, 3)) * 0.4, g.uniform(0.01, 0.05, 6), np.ones(6)])
+    R = oracle.quat_to_rot(synth.random_quaternions(1, 72)[0])
+    t = _obstacle_probe_points(A, B, R, g)
+    inside = _gap(A, B, R, t) < 0
+    assert inside.sum() > 300 and (~inside).sum() > 300
+    assert np.array_equal(oracle.o1_obstacle_points(A, B, R, t), inside)
+    assert np.array_equal(oracle.obstacle(oracle.o1_points(A, B, R, t)), inside)
+
+
+@pytest.mark.parametrize("delta", [0.015, -0.008])
+def test_offset_obstacle_depends_only_on_the_total_offset(delta):
+    # the slice at offset delta is the obstacle of the primitives offset by a
+    # total of delta, however the offset is split between the two shapes
+    g = np.random.default_rng(73)
+    A = np.column_stack([g.random((6, 3)) * 0.4, g.uniform(0.02, 0.06, 6), np.ones(6)])
+    B = np.column_stack([g.random((5, 3)) * 0.4, g.uniform(0.015, 0.04, 5), np.ones(5)])
+    R = oracle.quat_to_rot(synth.random_quaternions(1, 74)[0])
+    t = _obstacle_probe_points(A, B, R, g)
+    want = _gap(A, B, R, t) < delta
+    assert want.sum() > 300 and (~want).sum() > 300
+    on_a = oracle.obstacle(oracle.o1_points(oracle.offset_balls(A, delta), B, R, t))
+    split = oracle.obstacle(oracle.o1_points(oracle.offset_balls(A, delta / 2),
+                                             oracle.offset_balls(B, delta / 2), R, t))
+    assert np.array_equal(on_a, want)
+    assert np.array_equal(split, want)
+    # the score values of the two splits differ: only the obstacle is shared
+    assert not np.allclose(oracle.o1_points(oracle.offset_balls(A, delta), B, R, t),
+                           oracle.o1_points(oracle.offset_balls(A, delta / 2),
+                                            oracle.offset_balls(B, delta / 2), R, t))
+
+
+def test_offset_slice_dc_term_is_the_offset_volumes():
+    # sum_n s h^3 = (sum_i 4 pi (r_i + delta)^3 / 3) (sum_j 4 pi rho_j^3 / 3):
+    # the offset is on A's balls only
+    A, B, q, g, _ = synth.tiny_case()
+    h = g.box / g.n
+    for delta in (0.01, -0.01):
+        s = oracle.o2_offset_scores(A, B, q, g.n, g.box, g.origin, delta)
+        va = np.sum(A[:, 4] * 4 * np.pi * (A[:, 3] + delta) ** 3 / 3)
+        vb = np.sum(B[:, 4] * 4 * np.pi * B[:, 3] ** 3 / 3)
+        assert abs(s.sum() * h ** 3 - va * vb) <= 1e-12 * va * vb
+
+
+def test_offset_balls_keeps_radii_positive():
+    A = np.array([[0, 0, 0, 0.25, 1.0], [0.1, 0, 0, 0.5, 2.0]])
+    assert np.array_equal(oracle.offset_balls(A, 0.125)[:, 3], [0.375, 0.625])
+    assert np.array_equal(oracle.offset_balls(A, 0.125)[:, [0, 1, 2, 4]], A[:, [0, 1, 2, 4]])
+    with pytest.raises(ValueError):
+        oracle.offset_balls(A, -0.25)
