@@ -235,6 +235,64 @@ def run_query(args, torch, pkg):
                       "rows": rows}), flush=True)
 
 
+def run_slices(args, torch, pkg):
+    """Offset slices and obstacle masks: time per pass for 1, 4 and 8 slices of
+    A's balls offset by delta in [0, 0.02], writing every slice's scores and
+    peaks, or only its obstacle bits and count; B is spread once per rotation."""
+    dev = torch.device("cuda:0")
+    rows = []
+    for name, case in (("single rotation, 4096+4096 mixture balls, n = 128", synth.single_rotation_case),
+                       ("512 rotations, 20000+2000 mixture balls, n = 64", synth.batched_rotations_case)):
+        A, B, q, g = case()
+        g = synth.grid_for(A, B, g.n, pad=0.04)
+        c = pkg.Correlator(A, B, g.n, g.box, g.origin, device=dev)
+        n, R = g.n, len(q)
+
+        def timed(f):
+            for _ in range(args.warmup):
+                f()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                f()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3 / args.steps
+
+        s = torch.empty((R, n, n, n), dtype=torch.float32, device=dev)
+        pv = torch.empty(R, dtype=torch.float32, device=dev)
+        pi = torch.empty(R, dtype=torch.int64, device=dev)
+        t_plain = timed(lambda: pkg.corr_eval(c.ctx, q, s.data_ptr(), pv.data_ptr(), pi.data_ptr()))
+        thr = 0.01 * float(pv.max().item())
+        del s
+        row = {"workload": name, "rotations": R, "ms_corr_eval": t_plain, "threshold": thr, "slices": []}
+        for K in (1, 4, 8):
+            c.set_offsets(np.linspace(0.0, 0.02, K))
+            sc = torch.empty((K, R, n, n, n), dtype=torch.float32, device=dev)
+            pvk = torch.empty((K, R), dtype=torch.float32, device=dev)
+            pik = torch.empty((K, R), dtype=torch.int64, device=dev)
+            mk = torch.empty((K, R, n ** 3 // 32), dtype=torch.int32, device=dev)
+            ck = torch.empty((K, R), dtype=torch.int64, device=dev)
+            t_sc = timed(lambda: pkg.corr_eval_slices(c.ctx, q, sc.data_ptr(), pvk.data_ptr(), pik.data_ptr()))
+            del sc
+            t_ob = timed(lambda: pkg.corr_eval_slices(c.ctx, q, None, None, None, mk.data_ptr(), ck.data_ptr(), thr))
+            row["slices"].append({"slices": K, "ms_scores_and_peaks": t_sc, "ms_obstacle_bits_only": t_ob,
+                                  "slice_rot_trans_per_s_obstacle": K * R * n ** 3 / (t_ob * 1e-3),
+                                  "obstacle_fraction": float(ck.sum().item()) / (K * R * n ** 3)})
+            print("%s: %d slices: %.3f ms with scores, %.3f ms obstacle only" % (name, K, t_sc, t_ob),
+                  file=sys.stderr, flush=True)
+        s1, s8 = row["slices"][0], row["slices"][-1]
+        row["ms_per_extra_slice_scores"] = (s8["ms_scores_and_peaks"] - s1["ms_scores_and_peaks"]) / 7
+        row["ms_per_extra_slice_obstacle"] = (s8["ms_obstacle_bits_only"] - s1["ms_obstacle_bits_only"]) / 7
+        rows.append(row)
+        c.close()
+    print(json.dumps({"metric": "offset slices: time per pass (B spread once, product and inverse per slice)",
+                      "unit": "ms", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "steps": args.steps, "warmup": args.warmup, "dtype": "f32",
+                      "config": {"workload": "offsets linspace(0, 0.02, K) on A's balls; box padded by 0.04; "
+                                             "obstacle threshold 1 % of the unoffset peak"},
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +307,8 @@ def main():
     ap.add_argument("--proposal-epochs", type=int, default=40)
     ap.add_argument("--query", action="store_true",
                     help="time single-configuration queries (Sec. 4.1) instead, by number of modes")
+    ap.add_argument("--slices", action="store_true",
+                    help="time offset slices and obstacle masks (corr_eval_slices) instead")
     ap.add_argument("--sc", type=str, default=None, metavar="R0,LAMBDA",
                     help="score shape complementarity (skin offset R0, penalty LAMBDA) instead of the overlap")
     args = ap.parse_args()
@@ -277,6 +337,9 @@ def main():
         return
     if args.query:
         run_query(args, torch, pkg)
+        return
+    if args.slices:
+        run_slices(args, torch, pkg)
         return
     A, B, q, g = synth.single_rotation_case()
     sc = tuple(float(v) for v in args.sc.split(",")) if args.sc else None

@@ -142,8 +142,10 @@ int corr_info(const corr_ctx* ctx, corr_info_t* out);
 #define CORR_STAGE_BIN            1  /* a0: sorted knot records + live-tile plan      */
 #define CORR_STAGE_SPREAD_FFT_X   2  /* a1 + a2: spreading fused with the x pass      */
 #define CORR_STAGE_FFT_Y          3  /* a2: forward y pass                            */
-#define CORR_STAGE_FFT_Z_SPECTRUM 4  /* a2 z pass + a3, for A or corr_spectrum        */
-#define CORR_STAGE_FFT_Z_PRODUCT  5  /* a2 z pass + a3 + a4 + inverse z, for B        */
+#define CORR_STAGE_FFT_Z_SPECTRUM 4  /* a2 z pass + a3, for A or corr_spectrum; with
+                                        several slices also B's z sums, once           */
+#define CORR_STAGE_FFT_Z_PRODUCT  5  /* a2 z pass + a3 + a4 + inverse z, for B; with
+                                        several slices a4 + inverse z per slice        */
 #define CORR_STAGE_IFFT_Y         6  /* a5: inverse y pass                            */
 #define CORR_STAGE_IFFT_X         7  /* a5: inverse x pass (to real) + block peaks    */
 #define CORR_STAGE_PEAK           8  /* a5: per-rotation peak                         */
@@ -176,6 +178,57 @@ int corr_profile_read(corr_ctx* ctx, double* ms, int64_t* launches, int32_t n_st
  */
 int corr_query(corr_ctx* ctx, const double* quat_wxyz, const double* t_host, int64_t n_t, int32_t mode_radius2,
                float* out_dev, int64_t* n_modes);
+
+/* ---- configuration obstacles and offset slices --------------------------- */
+
+#define CORR_MAX_SLICES 16
+
+/*
+ * Offset obstacles (Sec. 3.1: the slices of the lifted obstacle away from
+ * r = 0 are the obstacles of the primitives offset by a total r).  Sets the
+ * radius offsets delta_k used by corr_eval_slices: slice k scores
+ *     s_k(R, t) = < f_{A_k}, f_{(R,t)B} >,  A_k = A with every radius r_i + delta_k,
+ * whose positive set is the translational configuration obstacle grown by
+ * delta_k (shrunk for delta_k < 0): the translations where some pair of balls
+ * comes closer than r_i + rho_j + delta_k.
+ *   offsets    host double [n_offsets], copied; each finite with
+ *              r_i + delta_k > 0 for every ball of A.
+ *   n_offsets  0 .. CORR_MAX_SLICES; 0 clears the list (then corr_eval_slices
+ *              has one slice, the context's own score).
+ * Plans each offset shape and computes its spectrum on the context's stream;
+ * returns after that work is done.  The B side is shared: per rotation, B is
+ * spread and transformed once for all slices.
+ * Errors: CORR_EINVAL (bad value or count), CORR_EUNSUPPORTED (with
+ * CORR_SC_SCORE, whose kernel already offsets the balls), CORR_ENOMEM, CORR_EHIP.
+ * After an error the previous offsets stay in force.
+ */
+int corr_set_offsets(corr_ctx* ctx, const double* offsets, int32_t n_offsets);
+
+/* Outputs of corr_eval_slices; every pointer is device memory or NULL (not
+ * produced).  S = number of slices (offsets set, or 1), R = n_rot. */
+typedef struct {
+    float* scores;            /* float [S][R][n][n][n]                                  */
+    float* peak_val;          /* float [S][R]: largest score of each rotation            */
+    int64_t* peak_idx;        /* int64 [S][R]: its linear index (lowest wins ties);
+                                 set iff peak_val is                                      */
+    uint32_t* obstacle;       /* uint32 [S][R][n^3 / 32]: bit b of word w is set iff the
+                                 score at linear index 32 w + b exceeds threshold: the
+                                 translational configuration obstacle of Sec. 3.1
+                                 eq. eq_obs (threshold 0) as a bit mask                   */
+    int64_t* obstacle_count;  /* int64 [S][R]: translations in the obstacle               */
+    float threshold;          /* finite, in score (volume) units; the comparison is
+                                 made on the float score, exactly as stored in scores     */
+} corr_slices_out;
+
+/*
+ * Score n_rot rotations of B (host quat_wxyz [n_rot][4]) against every slice
+ * of corr_set_offsets (or against A alone if none are set) and write the
+ * requested outputs.  The obstacle bits are the configuration-obstacle
+ * predicate of the band-limited score; with a threshold of 0 the band limit's
+ * ringing also marks points near the obstacle, so a small positive threshold
+ * is the usual choice.  Asynchronous.
+ */
+int corr_eval_slices(corr_ctx* ctx, const double* quat_wxyz, int64_t n_rot, const corr_slices_out* out);
 
 /* Occupancy of the last spreading pass run by ctx (the rotations of the last
  * batch of corr_eval, or one shape for corr_prepare_a / corr_spectrum).  The

@@ -28,9 +28,11 @@ CORR_EHIP = -3
 CORR_EUNSUPPORTED = -4
 CORR_DETERMINISTIC = 1
 CORR_SC_SCORE = 2
+CORR_MAX_SLICES = 16
 
 EXPORTS = ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
-           "corr_profile_read", "corr_pass_info", "corr_query", "corr_destroy", "corr_last_error",
+           "corr_profile_read", "corr_pass_info", "corr_query", "corr_set_offsets", "corr_eval_slices",
+           "corr_destroy", "corr_last_error",
            "corr_batch_create",
            "corr_batch_eval",
            "corr_batch_info", "corr_batch_destroy", "corr_batch_last_error")
@@ -56,6 +58,11 @@ class corr_pass_t(ctypes.Structure):
     _fields_ = [("rotations", ctypes.c_int32), ("q", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("knots", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("live_tiles", ctypes.c_int64), ("live_rows", ctypes.c_int64)]
+
+
+class corr_slices_out(ctypes.Structure):
+    _fields_ = [("scores", ctypes.c_void_p), ("peak_val", ctypes.c_void_p), ("peak_idx", ctypes.c_void_p),
+                ("obstacle", ctypes.c_void_p), ("obstacle_count", ctypes.c_void_p), ("threshold", ctypes.c_float)]
 
 
 class CorrError(RuntimeError):
@@ -85,11 +92,14 @@ def load_library(path: str = LIB_PATH):
     lib.corr_profile_read.argtypes = [vp, vp, vp, i32]
     lib.corr_pass_info.argtypes = [vp, ctypes.POINTER(corr_pass_t)]
     lib.corr_query.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.corr_set_offsets.argtypes = [vp, vp, i32]
+    lib.corr_eval_slices.argtypes = [vp, vp, i64, ctypes.POINTER(corr_slices_out)]
     lib.corr_destroy.argtypes = [vp]
     lib.corr_last_error.argtypes = [vp]
     lib.corr_last_error.restype = ctypes.c_char_p
     for name in ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
-                 "corr_profile_read", "corr_pass_info", "corr_query", "corr_destroy"):
+                 "corr_profile_read", "corr_pass_info", "corr_query", "corr_set_offsets", "corr_eval_slices",
+                 "corr_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -166,6 +176,19 @@ def corr_query(ctx, quat, t, mode_radius2, out_ptr) -> int:
     return nm.value
 
 
+def corr_set_offsets(ctx, offsets):
+    d = np.ascontiguousarray(np.asarray(offsets, dtype=np.float64).reshape(-1))
+    _check(load_library().corr_set_offsets(ctx, d.ctypes.data if len(d) else None, len(d)), ctx)
+
+
+def corr_eval_slices(ctx, quats, scores_ptr=None, peak_val_ptr=None, peak_idx_ptr=None, obstacle_ptr=None,
+                     count_ptr=None, threshold=0.0):
+    q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
+    o = corr_slices_out(scores_ptr or None, peak_val_ptr or None, peak_idx_ptr or None, obstacle_ptr or None,
+                        count_ptr or None, float(threshold))
+    _check(load_library().corr_eval_slices(ctx, q.ctypes.data if len(q) else None, len(q), ctypes.byref(o)), ctx)
+
+
 def corr_destroy(ctx):
     load_library().corr_destroy(ctx)
 
@@ -221,6 +244,35 @@ class Correlator:
             corr_eval(self.ctx, q, s.data_ptr() if s is not None else None,
                       pv.data_ptr() if pv is not None else None, pi.data_ptr() if pi is not None else None)
         return s, pv, pi
+
+    def set_offsets(self, offsets):
+        """Radius offsets of A's balls for eval_slices (empty: no slices)."""
+        with self.torch.cuda.device(self.device):
+            corr_set_offsets(self.ctx, offsets)
+        self.n_slices = max(1, len(np.atleast_1d(offsets)))
+
+    def eval_slices(self, quats, scores=True, peaks=True, obstacle=False, count=False, threshold=0.0):
+        """Outputs of corr_eval_slices as a dict of tensors shaped [slices][rotations]...;
+        the obstacle masks are int32 [slices][rotations][n^3 / 32] (the uint32 bits)."""
+        torch = self.torch
+        q = np.asarray(quats, dtype=np.float64).reshape(-1, 4)
+        S, r, n = getattr(self, "n_slices", 1), len(q), self.n
+        dev = self.device
+        out = {}
+        if scores:
+            out["scores"] = torch.empty((S, r, n, n, n), dtype=torch.float32, device=dev)
+        if peaks:
+            out["peak_val"] = torch.empty((S, r), dtype=torch.float32, device=dev)
+            out["peak_idx"] = torch.empty((S, r), dtype=torch.int64, device=dev)
+        if obstacle:
+            out["obstacle"] = torch.empty((S, r, n ** 3 // 32), dtype=torch.int32, device=dev)
+        if count:
+            out["obstacle_count"] = torch.empty((S, r), dtype=torch.int64, device=dev)
+        ptr = {k: v.data_ptr() for k, v in out.items()}
+        with torch.cuda.device(dev):
+            corr_eval_slices(self.ctx, q, ptr.get("scores"), ptr.get("peak_val"), ptr.get("peak_idx"),
+                             ptr.get("obstacle"), ptr.get("obstacle_count"), threshold)
+        return out
 
     def pass_info(self):
         return corr_pass_info(self.ctx)

@@ -275,6 +275,13 @@ struct Shape {
     float* vtab = nullptr;  // [q][m2n]
 };
 
+// One offset slice: A's balls with every radius changed by delta, and its spectrum.
+struct Slice {
+    double delta = 0;
+    Shape A;
+    float2* fa = nullptr;  // [n][n][half]
+};
+
 }  // namespace
 
 namespace corr {
@@ -296,7 +303,7 @@ struct WsReq {
         list = std::max(list, o.list);
     }
     size_t slot_bytes() const {
-        return 4 * buf0 + 8 * buf1 + 4 * (3 * nk + nkw + nkq) + 12 * nkw + 4 * (counts + bins) + 8 * blocks + tiles +
+        return 4 * buf0 + 8 * buf1 + 4 * (3 * nk + nkw + nkq) + 12 * nkw + 4 * (counts + bins) + 12 * blocks + tiles +
                4 * list + 32;
     }
 };
@@ -319,8 +326,9 @@ struct Workspace {
     float* skbw = nullptr;         // [slots][nk][3][w]              window weights
     float* swts = nullptr;         // [slots][nk][q]                 component weights
     double* quats = nullptr;       // [slots][4]
-    float* pval = nullptr;         // [slots][blocks]
+    float* pval = nullptr;         // [slots][blocks] inverse-x block peaks
     int* pidx = nullptr;
+    int* pcnt = nullptr;           // [slots][blocks] inverse-x block obstacle counts
     double* host_quats = nullptr;  // pinned [slots][4]
     hipEvent_t quat_done = nullptr;
 
@@ -346,6 +354,7 @@ struct Workspace {
         quats = mem.alloc<double>(S * 4);
         pval = mem.alloc<float>(S * r.blocks);
         pidx = mem.alloc<int>(S * r.blocks);
+        pcnt = mem.alloc<int>(S * r.blocks);
         hip_check(hipHostMalloc((void**)&host_quats, sizeof(double) * 4 * S, hipHostMallocDefault), "hipHostMalloc");
         hip_check(hipEventCreateWithFlags(&quat_done, hipEventDisableTiming), "hipEventCreate");
         hip_check(hipEventRecord(quat_done, st), "event");
@@ -371,6 +380,9 @@ struct corr_ctx {
     int qmax = 1;
     int64_t nkmax = 1;  // max(nA, nB, 1)
     Shape A, B;
+    std::vector<corr_ball> host_a;  // A as given (offset slices are planned from it)
+    std::vector<Slice> slices;      // corr_set_offsets
+    DevMem slice_mem;
     DevMem mem;
     float2 *twm = nullptr, *twn = nullptr;
     double* deconv = nullptr;
@@ -437,12 +449,12 @@ void setup_shape(corr_ctx* c, Shape& s, const corr_ball* balls, int64_t n, doubl
     s.ex = build_expansion(rlo, rhi, dk, c->g.m2n, c->tol, c->sc_r0, c->sc_lam);
 }
 
-void upload_shape(corr_ctx* c, Shape& s, const corr_ball* balls, double dk) {
+void upload_shape(corr_ctx* c, DevMem& mem, Shape& s, const corr_ball* balls, double dk) {
     const Expansion& e = s.ex;
     const int64_t n = s.n;
-    s.pos = c->mem.alloc<double>((size_t)3 * std::max<int64_t>(n, 1));
-    s.wts = c->mem.alloc<float>((size_t)e.q * std::max<int64_t>(n, 1));
-    s.vtab = c->mem.alloc<float>((size_t)e.q * c->g.m2n);
+    s.pos = mem.alloc<double>((size_t)3 * std::max<int64_t>(n, 1));
+    s.wts = mem.alloc<float>((size_t)e.q * std::max<int64_t>(n, 1));
+    s.vtab = mem.alloc<float>((size_t)e.q * c->g.m2n);
     if (n > 0) {
         std::vector<double> pos((size_t)3 * n);
         std::vector<float> w((size_t)e.q * n);
@@ -474,8 +486,8 @@ void upload_shape(corr_ctx* c, Shape& s, const corr_ball* balls, double dk) {
         if (ex2 < -100) fail(CORR_EUNSUPPORTED, "ball weights too large for the spreading sums");
         s.fix_scale = (float)std::ldexp(1.0, ex2);
     }
-    double* d_nodes = c->mem.alloc<double>(e.p);
-    double* d_basis = c->mem.alloc<double>((size_t)e.p * e.q);
+    double* d_nodes = mem.alloc<double>(e.p);
+    double* d_basis = mem.alloc<double>((size_t)e.p * e.q);
     upload(d_nodes, e.nodes.data(), sizeof(double) * e.p, c->stream);
     upload(d_basis, e.basis.data(), sizeof(double) * e.p * e.q, c->stream);
     hip_check(corr::launch_ball_table(c->g, dk, d_nodes, d_basis, e.p, e.q, e.rref, e.r0, e.lam, s.vtab, c->stream),
@@ -544,14 +556,16 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
 
 void stage_quats(corr_ctx* c, const double* q, int S);
 
-void prepare_a(corr_ctx* c) {
-    run_spectrum_stages(c, c->A, c->ident_q, 1);
+// The fixed shape's spectrum (unturned) into fa.
+void fixed_spectrum(corr_ctx* c, const Shape& a, float2* fa) {
+    run_spectrum_stages(c, a, c->ident_q, 1);
     stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z (A)", [&] {
-        return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->ws->buf0), 1, c->A.ex.q,
-                                           occupancy(c, c->A), c->A.vtab, c->deconv,
-                                           c->fa, c->twm, c->stream);
+        return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->ws->buf0), 1, a.ex.q,
+                                           occupancy(c, a), a.vtab, c->deconv, fa, c->twm, c->stream);
     });
 }
+
+void prepare_a(corr_ctx* c) { fixed_spectrum(c, c->A, c->fa); }
 
 // host quaternions -> pinned staging -> device, S at a time
 void stage_quats(corr_ctx* c, const double* q, int S) {
@@ -655,8 +669,9 @@ corr_ctx* plan_pair(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t 
         c->deconv = c->mem.alloc<double>(g.n);
         c->phase = c->mem.alloc<double2>((size_t)3 * g.n);
         hip_check(corr::launch_deconv_tables(g, c->box, c->origin, c->deconv, c->phase, c->stream), "deconv tables");
-        upload_shape(c, c->A, A, dk);
-        upload_shape(c, c->B, B, dk);
+        upload_shape(c, c->mem, c->A, A, dk);
+        upload_shape(c, c->mem, c->B, B, dk);
+        c->host_a.assign(A, A + nA);
         c->fa = c->mem.alloc<float2>((size_t)g.n * g.n * g.half);
         static const double ident[4] = {1, 0, 0, 0};
         c->ident_q = c->mem.alloc<double>(4);
@@ -684,12 +699,26 @@ corr::WsReq ws_req(const corr_ctx* c) {
     return r;
 }
 
-// Score n_rot rotations of B against A (validated here), batch by batch.
-void eval_impl(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* scores_dev, float* peak_val_dev,
-               int64_t* peak_idx_dev) {
+// Outputs of one evaluation; slice k's arrays follow slice k-1's (n_rot rotations each).
+struct EvalOut {
+    float* scores = nullptr;
+    float* peak_val = nullptr;
+    int64_t* peak_idx = nullptr;
+    unsigned* mask = nullptr;
+    int64_t* count = nullptr;
+    float thr = 0.f;
+};
+
+// Score n_rot rotations of B (validated here) against each fixed spectrum in
+// fas, batch by batch: B is spread and transformed once per batch, then each
+// slice takes the product and inverse passes (the inverse y pass works in
+// place, so B's transformed components stay for the next slice).
+void eval_impl(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, const std::vector<const float2*>& fas,
+               const EvalOut& o) {
     if (n_rot < 0) fail(CORR_EINVAL, "n_rot < 0");
-    if ((peak_val_dev == nullptr) != (peak_idx_dev == nullptr))
-        fail(CORR_EINVAL, "peak_val_dev and peak_idx_dev must both be set or both be NULL");
+    if ((o.peak_val == nullptr) != (o.peak_idx == nullptr))
+        fail(CORR_EINVAL, "peak_val and peak_idx must both be set or both be NULL");
+    if (!std::isfinite(o.thr)) fail(CORR_EINVAL, "threshold must be finite");
     validate_quats(quat_wxyz, n_rot);
     const Geom& g = c->g;
     const size_t n3 = (size_t)g.n * g.n * g.n;
@@ -698,25 +727,103 @@ void eval_impl(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* score
         const int S = (int)std::min<int64_t>(c->ws->slots, n_rot - r0);
         stage_quats(c, quat_wxyz + 4 * r0, S);
         run_spectrum_stages(c, c->B, c->ws->quats, S);
-        stage(c, CORR_STAGE_FFT_Z_PRODUCT, "fft z product", [&] {
-            return corr::launch_fft_z_product(g, reinterpret_cast<float2*>(c->ws->buf0), S, c->B.ex.q,
-                                              occupancy(c, c->B), c->B.vtab,
-                                              c->phase, c->fa, c->ws->buf1, c->twm, c->twn, c->stream);
-        });
-        stage(c, CORR_STAGE_IFFT_Y, "ifft y", [&] {
-            return corr::launch_ifft_y(g, c->ws->buf1, S, reinterpret_cast<float2*>(c->ws->buf0), c->twn, c->stream);
-        });
-        stage(c, CORR_STAGE_IFFT_X, "ifft x", [&] {
-            return corr::launch_ifft_x(g, reinterpret_cast<float2*>(c->ws->buf0), S,
-                                       scores_dev ? scores_dev + (size_t)r0 * n3 : nullptr, c->ws->pval, c->ws->pidx,
-                                       c->twn, c->stream);
-        });
-        if (peak_val_dev)
-            stage(c, CORR_STAGE_PEAK, "peak", [&] {
-                return corr::launch_peak_final(c->ws->pval, c->ws->pidx, S, nb, peak_val_dev + r0, peak_idx_dev + r0,
-                                               c->stream);
+        // several slices: B's z sums once, into the second half of buf1
+        // (buf1 holds q m^2 n/2 >= 2 n^2 n/2 values per slot)
+        float2* zsums = c->ws->buf1 + (size_t)c->ws->slots * g.n * g.n * g.half;
+        if (fas.size() > 1)
+            stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z sums (B)", [&] {
+                return corr::launch_fft_z_spectrum(g, reinterpret_cast<float2*>(c->ws->buf0), S, c->B.ex.q,
+                                                   occupancy(c, c->B), c->B.vtab, nullptr, zsums, c->twm, c->stream);
             });
+        for (size_t k = 0; k < fas.size(); ++k) {
+            const size_t first = (size_t)k * n_rot + r0;  // this slice's first rotation of the batch
+            stage(c, CORR_STAGE_FFT_Z_PRODUCT, "fft z product", [&] {
+                if (fas.size() > 1)
+                    return corr::launch_product_ifft_z(g, zsums, S, c->phase, fas[k], c->ws->buf1, c->twn, c->stream);
+                return corr::launch_fft_z_product(g, reinterpret_cast<float2*>(c->ws->buf0), S, c->B.ex.q,
+                                                  occupancy(c, c->B), c->B.vtab, c->phase, fas[k], c->ws->buf1,
+                                                  c->twm, c->twn, c->stream);
+            });
+            stage(c, CORR_STAGE_IFFT_Y, "ifft y", [&] {
+                return corr::launch_ifft_y(g, c->ws->buf1, S, c->ws->buf1, c->twn, c->stream);
+            });
+            stage(c, CORR_STAGE_IFFT_X, "ifft x", [&] {
+                return corr::launch_ifft_x(g, c->ws->buf1, S, o.scores ? o.scores + first * n3 : nullptr,
+                                           o.mask ? o.mask + first * (n3 / 32) : nullptr, o.thr, c->ws->pval,
+                                           c->ws->pidx, o.count ? c->ws->pcnt : nullptr, c->twn, c->stream);
+            });
+            if (o.peak_val || o.count)
+                stage(c, CORR_STAGE_PEAK, "peak", [&] {
+                    return corr::launch_peak_final(c->ws->pval, c->ws->pidx, c->ws->pcnt, S, nb,
+                                                   o.peak_val ? o.peak_val + first : nullptr,
+                                                   o.peak_idx ? o.peak_idx + first : nullptr,
+                                                   o.count ? o.count + first : nullptr, c->stream);
+                });
+        }
     }
+}
+
+void eval_plain(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* scores_dev, float* peak_val_dev,
+                int64_t* peak_idx_dev) {
+    EvalOut o;
+    o.scores = scores_dev;
+    o.peak_val = peak_val_dev;
+    o.peak_idx = peak_idx_dev;
+    eval_impl(c, quat_wxyz, n_rot, {c->fa}, o);
+}
+
+// Plan and compute the offset slices of A (corr_set_offsets).
+void set_offsets(corr_ctx* c, const double* offsets, int32_t n) {
+    if (c->flags & CORR_SC_SCORE)
+        fail(CORR_EUNSUPPORTED, "offset slices with CORR_SC_SCORE: its kernel already offsets the balls");
+    if (n < 0 || n > CORR_MAX_SLICES) fail(CORR_EINVAL, "n_offsets = %d; allowed 0..%d", n, CORR_MAX_SLICES);
+    if (n > 0 && !offsets) fail(CORR_EINVAL, "NULL offsets with n_offsets = %d", n);
+    double rmin = HUGE_VAL;
+    for (const corr_ball& b : c->host_a) rmin = std::min(rmin, b.r);
+    for (int k = 0; k < n; ++k) {
+        if (!std::isfinite(offsets[k])) fail(CORR_EINVAL, "offset %d is not finite", k);
+        if (!c->host_a.empty() && !(rmin + offsets[k] > 0))
+            fail(CORR_EINVAL, "offset %d (%g) leaves a ball of A with radius <= 0 (smallest radius %g)", k, offsets[k],
+                 rmin);
+    }
+    const double dk = 2.0 * M_PI / c->box;
+    const int64_t na = (int64_t)c->host_a.size();
+    std::vector<Slice> ns(n);
+    DevMem nm;
+    try {
+        std::vector<corr_ball> grown(c->host_a);
+        int qmax = c->qmax;
+        for (int k = 0; k < n; ++k) {
+            for (int64_t i = 0; i < na; ++i) grown[i].r = c->host_a[i].r + offsets[k];
+            ns[k].delta = offsets[k];
+            setup_shape(c, ns[k].A, grown.data(), na, dk);
+            qmax = std::max(qmax, ns[k].A.ex.q);
+            upload_shape(c, nm, ns[k].A, grown.data(), dk);
+            ns[k].fa = nm.alloc<float2>((size_t)c->g.n * c->g.n * c->g.half);
+        }
+        if (qmax > c->qmax) {  // a slice needs more components than the workspace holds
+            if (!c->own_ws) fail(CORR_EUNSUPPORTED, "offset slices need a larger shared workspace");
+            hipDeviceProp_t prop;
+            hip_check(hipGetDeviceProperties(&prop, c->device), "hipGetDeviceProperties");
+            if (corr::max_lds_bytes(c->g, qmax) > prop.sharedMemPerBlock)
+                fail(CORR_EUNSUPPORTED, "offset slices need %d radius components: too much LDS", qmax);
+            hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+            const int slots = c->ws->slots;
+            c->ws->release();
+            c->qmax = qmax;
+            c->ws->allocate(slots, ws_req(c), c->stream);
+        }
+        for (int k = 0; k < n; ++k) fixed_spectrum(c, ns[k].A, ns[k].fa);
+        hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    } catch (...) {
+        (void)hipStreamSynchronize(c->stream);
+        nm.release();
+        throw;
+    }
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    c->slice_mem.release();
+    c->slices = std::move(ns);
+    c->slice_mem = nm;
 }
 
 template <class F>
@@ -747,6 +854,7 @@ void destroy_ctx(corr_ctx* c) {
     if (c->q_host) (void)hipHostFree(c->q_host);
     if (c->q_done) (void)hipEventDestroy(c->q_done);
     c->mem.release();
+    c->slice_mem.release();
     if (c->own_ws && c->ws) {
         c->ws->release();
         delete c->ws;
@@ -798,7 +906,36 @@ int corr_eval(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* scores
         g_thread_error = "corr_eval: NULL context";
         return CORR_EINVAL;
     }
-    return guarded(c, [&] { eval_impl(c, quat_wxyz, n_rot, scores_dev, peak_val_dev, peak_idx_dev); });
+    return guarded(c, [&] { eval_plain(c, quat_wxyz, n_rot, scores_dev, peak_val_dev, peak_idx_dev); });
+}
+
+int corr_set_offsets(corr_ctx* c, const double* offsets, int32_t n_offsets) {
+    if (!c) {
+        g_thread_error = "corr_set_offsets: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] { set_offsets(c, offsets, n_offsets); });
+}
+
+int corr_eval_slices(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, const corr_slices_out* out) {
+    if (!c) {
+        g_thread_error = "corr_eval_slices: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] {
+        if (!out) fail(CORR_EINVAL, "out is NULL");
+        EvalOut o;
+        o.scores = out->scores;
+        o.peak_val = out->peak_val;
+        o.peak_idx = out->peak_idx;
+        o.mask = out->obstacle;
+        o.count = out->obstacle_count;
+        o.thr = out->threshold;
+        std::vector<const float2*> fas;
+        for (const Slice& sl : c->slices) fas.push_back(sl.fa);
+        if (fas.empty()) fas.push_back(c->fa);
+        eval_impl(c, quat_wxyz, n_rot, fas, o);
+    });
 }
 
 int corr_spectrum(corr_ctx* c, int32_t which, const double* quat_wxyz, float* out_dev) {
@@ -1076,8 +1213,8 @@ int corr_batch_eval(corr_batch* b, const double* quat_wxyz, const int64_t* rot_o
             float* sc = nullptr;
             if (scores_dev) sc = scores_dev + (score_offsets ? score_offsets[p] : packed);
             packed += nr * n3;
-            eval_impl(c, quat_wxyz + 4 * r0, nr, sc, peak_val_dev ? peak_val_dev + r0 : nullptr,
-                      peak_idx_dev ? peak_idx_dev + r0 : nullptr);
+            eval_plain(c, quat_wxyz + 4 * r0, nr, sc, peak_val_dev ? peak_val_dev + r0 : nullptr,
+                       peak_idx_dev ? peak_idx_dev + r0 : nullptr);
         }
     });
     if (rc != CORR_OK) b->err = cur && cur->err != "no error" ? cur->err : g_thread_error;

@@ -84,7 +84,9 @@ size_t max_lds_bytes(const Geom& g, int qmax);
 hipError_t launch_fft_y(const Geom& g, int S, int q, const Occupancy& occ, const float2* d_in, float2* d_out,
                         const float2* d_twm, hipStream_t st);
 // a2 (z) + a3: z transform of every component, the radius-expansion sum with the
-// ball-transform table, and the deconvolution; writes the shape spectrum.
+// ball-transform table, and the deconvolution; writes the shape spectrum.  With
+// d_deconv NULL it writes the sums without the deconvolution (for
+// launch_product_ifft_z).
 hipError_t launch_fft_z_spectrum(const Geom& g, const float2* d_in, int S, int q, const Occupancy& occ,
                                  const float* d_vtab, const double* d_deconv, float2* d_spec,
                                  const float2* d_twm, hipStream_t st);
@@ -95,14 +97,24 @@ hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q,
                                 const float* d_vtab, const double2* d_phase, const float2* d_fa,
                                 float2* d_out, const float2* d_twm, const float2* d_twn,
                                 hipStream_t st);
-// a5: inverse y, then inverse x (half-complex to real) with per-block peaks.
+// a4 + first inverse pass of a5 for one more fixed spectrum d_fa, from the
+// rotated shape's z sums d_acc [S][n][n][half]: the product and inverse z of
+// launch_fft_z_product, bit for bit.
+hipError_t launch_product_ifft_z(const Geom& g, const float2* d_acc, int S, const double2* d_phase,
+                                 const float2* d_fa, float2* d_out, const float2* d_twn, hipStream_t st);
+// a5: inverse y (d_in == d_out allowed), then inverse x (half-complex to real)
+// with per-block peaks and, for the obstacle predicate score > thr, the bit
+// mask d_mask [S][n^3 / 32] (NULL: not written) and per-block counts d_pcnt
+// (NULL: not counted).  d_scores NULL: scores not written.
 hipError_t launch_ifft_y(const Geom& g, const float2* d_in, int S, float2* d_out,
                          const float2* d_twn, hipStream_t st);
 int ifft_x_blocks(const Geom& g);
-hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scores,
-                         float* d_pval, int* d_pidx, const float2* d_twn, hipStream_t st);
-hipError_t launch_peak_final(const float* d_pval, const int* d_pidx, int S, int nblocks,
-                             float* d_peak_val, int64_t* d_peak_idx, hipStream_t st);
+hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scores, unsigned* d_mask, float thr,
+                         float* d_pval, int* d_pidx, int* d_pcnt, const float2* d_twn, hipStream_t st);
+// Per rotation: peak (d_peak_val, d_peak_idx; NULL: skipped) and obstacle count
+// (d_count; NULL: skipped) from the inverse-x blocks.
+hipError_t launch_peak_final(const float* d_pval, const int* d_pidx, const int* d_pcnt, int S, int nblocks,
+                             float* d_peak_val, int64_t* d_peak_idx, int64_t* d_count, hipStream_t st);
 
 // ---- single-configuration query -------------------------------------------
 // d_modes: nm packed modes (mx + 512) | (my + 512) << 10 | (mz + 512) << 20 of the

@@ -938,7 +938,9 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
     }
 }
 
-// a2 (z) + a3 for the fixed shape or a single spectrum: F = D(m) * acc.
+// a2 (z) + a3 for the fixed shape or a single spectrum: F = D(m) * acc; with
+// deconv NULL the plain sums acc (the rotated shape's z pass shared by several
+// products, each finished by k_product_ifft_z).
 template <int M>
 __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __restrict__ in, int q,
                                                              const float* __restrict__ vtab, int m2n,
@@ -967,10 +969,23 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __res
         const int t = threadIdx.x + k * kThreads;
         if (t < N * COLS) {
             const int o = t / COLS, cc = t % COLS;
-            const float d = (float)(deconv[c0 + cc] * deconv[iy] * deconv[o]);
-            dst[(size_t)o * N * H + cc] = make_float2(acc[k].x * d, acc[k].y * d);
+            if (deconv) {
+                const float d = (float)(deconv[c0 + cc] * deconv[iy] * deconv[o]);
+                dst[(size_t)o * N * H + cc] = make_float2(acc[k].x * d, acc[k].y * d);
+            } else {
+                dst[(size_t)o * N * H + cc] = acc[k];
+            }
         }
     }
+}
+
+// The product's factor prod_d D(m_d) exp(i k_d o_d) / L for output mode
+// (x index cx, y index iy, z index o), from the per-axis FP64 table, as float.
+__device__ __forceinline__ float2 shift_factor(const double2* __restrict__ phase, int n, int cx, int iy, int o) {
+    const double2 px = phase[cx], py = phase[n + iy], pz = phase[2 * n + o];
+    const double fr = px.x * py.x - px.y * py.y, fi = px.x * py.y + px.y * py.x;
+    const double gr = fr * pz.x - fi * pz.y, gi = fr * pz.y + fi * pz.x;
+    return make_float2((float)gr, (float)gi);
 }
 
 // a2 (z) + a3 + a4 + inverse z for the rotated shape:
@@ -1003,17 +1018,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
     __syncthreads();
     float2 acc[PER];
     z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, twl, zlive, acc);
-    const double2 py = phase[N + iy];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int t = threadIdx.x + k * kThreads;
         if (t < N * COLS) {
             const int o = t / COLS, cc = t % COLS;
-            const double2 px = phase[c0 + cc], pz = phase[2 * N + o];
-            const double fr = px.x * py.x - px.y * py.y, fi = px.x * py.y + px.y * py.x;
-            const double gr = fr * pz.x - fi * pz.y, gi = fr * pz.y + fi * pz.x;
             const float2 A = fa[((size_t)o * N + iy) * H + c0 + cc];
-            a[o * COLS + cc] = cmul(cmul(A, make_float2(acc[k].x, -acc[k].y)), make_float2((float)gr, (float)gi));
+            a[o * COLS + cc] = cmul(cmul(A, make_float2(acc[k].x, -acc[k].y)), shift_factor(phase, N, c0 + cc, iy, o));
         }
     }
     __syncthreads();
@@ -1021,10 +1032,42 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
     for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * N * H + t % COLS] = a[t];
 }
 
-// a5: inverse y over [s][z][my][mx] -> [s][z][y][mx].
+// a4 + inverse z for one more fixed spectrum, from the rotated shape's z sums
+// acc [s][mz][my][mx] (k_fft_z_spectrum without deconvolution): the same
+// product and transform as k_fft_z_product, in the same order of operations.
 template <int M>
-__global__ __launch_bounds__(kThreads) void k_ifft_y(const float2* __restrict__ in, float2* __restrict__ out,
-                                                     const float2* __restrict__ twn) {
+__global__ __launch_bounds__(kThreads) void k_product_ifft_z(const float2* __restrict__ accs,
+                                                             const double2* __restrict__ phase,
+                                                             const float2* __restrict__ fa, float2* __restrict__ out,
+                                                             const float2* __restrict__ twn) {
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ICOLS;
+    extern __shared__ float2 lds[];
+    float2* a = lds;
+    float2* twnl = a + N * COLS;
+    const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
+    float2* dst = out + (size_t)s * N * N * H + (size_t)iy * H + c0;
+    if (iy == N / 2) {
+        for (int t = threadIdx.x; t < N * COLS; t += kThreads)
+            dst[(size_t)(t / COLS) * N * H + t % COLS] = make_float2(0.f, 0.f);
+        return;
+    }
+    load_table<N>(twnl, twn);
+    const float2* src = accs + (size_t)s * N * N * H + (size_t)iy * H + c0;
+    for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
+        const int o = t / COLS, cc = t % COLS;
+        const float2 acc = src[(size_t)o * N * H + cc];
+        const float2 A = fa[((size_t)o * N + iy) * H + c0 + cc];
+        a[t] = cmul(cmul(A, make_float2(acc.x, -acc.y)), shift_factor(phase, N, c0 + cc, iy, o));
+    }
+    __syncthreads();
+    fft_cols<N, 1, COLS, false>(a, twnl);
+    for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * N * H + t % COLS] = a[t];
+}
+
+// a5: inverse y over [s][z][my][mx] -> [s][z][y][mx].  A workgroup reads all of
+// its columns before it writes them back, so in == out (in place) is allowed.
+template <int M>
+__global__ __launch_bounds__(kThreads) void k_ifft_y(const float2* in, float2* out, const float2* __restrict__ twn) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ICOLS;
     extern __shared__ float2 lds[];
     float2* a = lds;
@@ -1044,15 +1087,22 @@ __global__ __launch_bounds__(kThreads) void k_ifft_y(const float2* __restrict__ 
 // transform of Z = X1 + i X2 with both extended by Hermitian symmetry
 // (X[n-m] = conj X[m], Nyquist 0, imaginary part of X[0] dropped); the real and
 // imaginary parts of the result are the two score lines.  Each block also
-// reduces its scores to (max, lowest index of the max).
+// reduces its scores to (max, lowest index of the max) and, for the obstacle
+// predicate (Sec. 3.1 eq. eq_obs), writes the bits score > thr of its points
+// (bit b of word w: linear index 32 w + b) and counts them.
 template <int M>
 __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ in, float* __restrict__ scores,
+                                                     unsigned* __restrict__ mask, float thr,
                                                      float* __restrict__ pval, int* __restrict__ pidx,
-                                                     const float2* __restrict__ twn) {
+                                                     int* __restrict__ pcnt, const float2* __restrict__ twn) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::XCOLS, SC = N + 1;
+    // whole iterations of the output loop: every lane takes part in each ballot,
+    // and a wave's 64 points are two whole mask words
+    static_assert((2 * COLS * N) % kThreads == 0, "output loop must be whole");
     extern __shared__ float2 lds[];
     __shared__ float red_v[kThreads];
     __shared__ int red_i[kThreads];
+    __shared__ int red_c[kThreads];
     float2* a = lds;
     float2* twl = a + COLS * SC;
     load_table<N>(twl, twn);
@@ -1086,7 +1136,10 @@ __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ 
     const float2* res = a;
     float best = -INFINITY;
     int besti = 0x7fffffff;
+    int cnt = 0;
     float* dst = scores ? scores + (size_t)s * N * N * N + line0 * N : nullptr;
+    unsigned* mdst = mask ? mask + ((size_t)s * N * N * N + line0 * N) / 32 : nullptr;
+    const int lane = threadIdx.x & 63;
     for (int t = threadIdx.x; t < 2 * COLS * N; t += kThreads) {
         const int l = t / N, x = t % N;
         const float2 zz = res[(l >> 1) * SC + x];
@@ -1097,9 +1150,19 @@ __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ 
             best = v;
             besti = gi;
         }
+        const bool hit = v > thr;
+        cnt += hit;
+        if (mdst) {
+            const unsigned long long b = __ballot(hit);
+            if (lane == 0) {
+                mdst[(t >> 5)] = (unsigned)b;
+                mdst[(t >> 5) + 1] = (unsigned)(b >> 32);
+            }
+        }
     }
     red_v[threadIdx.x] = best;
     red_i[threadIdx.x] = besti;
+    red_c[threadIdx.x] = cnt;
     __syncthreads();
     for (int off = kThreads / 2; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) {
@@ -1109,23 +1172,30 @@ __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ 
                 red_v[threadIdx.x] = v2;
                 red_i[threadIdx.x] = i2;
             }
+            red_c[threadIdx.x] += red_c[threadIdx.x + off];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         pval[(size_t)s * gridDim.x + blockIdx.x] = red_v[0];
         pidx[(size_t)s * gridDim.x + blockIdx.x] = red_i[0];
+        if (pcnt) pcnt[(size_t)s * gridDim.x + blockIdx.x] = red_c[0];
     }
 }
 
+// Per rotation: the peak over the inverse-x blocks (out_val, out_idx; NULL: not
+// wanted) and the obstacle count (out_cnt; NULL: not wanted).
 __global__ __launch_bounds__(kThreads) void k_peak_final(const float* __restrict__ pval, const int* __restrict__ pidx,
-                                                         int nblocks, float* __restrict__ out_val,
-                                                         int64_t* __restrict__ out_idx) {
+                                                         const int* __restrict__ pcnt, int nblocks,
+                                                         float* __restrict__ out_val, int64_t* __restrict__ out_idx,
+                                                         int64_t* __restrict__ out_cnt) {
     __shared__ float red_v[kThreads];
     __shared__ int red_i[kThreads];
+    __shared__ long long red_c[kThreads];
     const int s = blockIdx.x;
     float best = -INFINITY;
     int besti = 0x7fffffff;
+    long long cnt = 0;
     for (int t = threadIdx.x; t < nblocks; t += kThreads) {
         const float v = pval[(size_t)s * nblocks + t];
         const int i = pidx[(size_t)s * nblocks + t];
@@ -1133,7 +1203,16 @@ __global__ __launch_bounds__(kThreads) void k_peak_final(const float* __restrict
             best = v;
             besti = i;
         }
+        if (out_cnt) cnt += pcnt[(size_t)s * nblocks + t];
     }
+    red_c[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red_c[threadIdx.x] += red_c[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (out_cnt && threadIdx.x == 0) out_cnt[s] = red_c[0];
+    if (!out_val) return;
     red_v[threadIdx.x] = best;
     red_i[threadIdx.x] = besti;
     __syncthreads();
@@ -1405,7 +1484,7 @@ size_t max_lds_bytes(const Geom& g, int qmax) {
         need = std::max(need, spread_lds_t<M>(g.w));
         need = std::max(need, sizeof(float2) * ((size_t)M * C::COLS + M + N));
         need = std::max(need, sizeof(float2) * ((size_t)N * C::ICOLS + N));
-        need = std::max(need, sizeof(float2) * ((size_t)C::XCOLS * (N + 1) + N) + 8 * kThreads);
+        need = std::max(need, sizeof(float2) * ((size_t)C::XCOLS * (N + 1) + N) + 12 * kThreads);
     });
     return need;
 }
@@ -1469,6 +1548,16 @@ hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q,
     });
 }
 
+hipError_t launch_product_ifft_z(const Geom& g, const float2* d_acc, int S, const double2* d_phase,
+                                 const float2* d_fa, float2* d_out, const float2* d_twn, hipStream_t st) {
+    return with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        using C = ColShape<M>;
+        hipLaunchKernelGGL(k_product_ifft_z<M>, dim3(C::H / C::ICOLS, C::N, S), dim3(kThreads),
+                           sizeof(float2) * ((size_t)C::N * C::ICOLS + C::N), st, d_acc, d_phase, d_fa, d_out, d_twn);
+    });
+}
+
 hipError_t launch_ifft_y(const Geom& g, const float2* d_in, int S, float2* d_out, const float2* d_twn,
                          hipStream_t st) {
     return with_m(g.m, [&](auto mc) {
@@ -1489,21 +1578,21 @@ int ifft_x_blocks(const Geom& g) {
     return nb;
 }
 
-hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scores, float* d_pval, int* d_pidx,
-                         const float2* d_twn, hipStream_t st) {
+hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scores, unsigned* d_mask, float thr,
+                         float* d_pval, int* d_pidx, int* d_pcnt, const float2* d_twn, hipStream_t st) {
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
         hipLaunchKernelGGL(k_ifft_x<M>, dim3(C::N * C::N / (2 * C::XCOLS), S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)C::XCOLS * (C::N + 1) + C::N), st, d_in, d_scores, d_pval,
-                           d_pidx, d_twn);
+                           sizeof(float2) * ((size_t)C::XCOLS * (C::N + 1) + C::N), st, d_in, d_scores, d_mask,
+                           thr, d_pval, d_pidx, d_pcnt, d_twn);
     });
 }
 
-hipError_t launch_peak_final(const float* d_pval, const int* d_pidx, int S, int nblocks, float* d_peak_val,
-                             int64_t* d_peak_idx, hipStream_t st) {
-    hipLaunchKernelGGL(k_peak_final, dim3(S), dim3(kThreads), 0, st, d_pval, d_pidx, nblocks, d_peak_val,
-                       d_peak_idx);
+hipError_t launch_peak_final(const float* d_pval, const int* d_pidx, const int* d_pcnt, int S, int nblocks,
+                             float* d_peak_val, int64_t* d_peak_idx, int64_t* d_count, hipStream_t st) {
+    hipLaunchKernelGGL(k_peak_final, dim3(S), dim3(kThreads), 0, st, d_pval, d_pidx, d_pcnt, nblocks, d_peak_val,
+                       d_peak_idx, d_count);
     return hipGetLastError();
 }
 

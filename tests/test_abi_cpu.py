@@ -111,6 +111,8 @@ def test_create_rejects_null_arguments(lib):
 def test_null_context_calls_fail_cleanly(lib):
     assert lib.corr_eval(None, None, 0, None, None, None) == pkg.CORR_EINVAL
     assert lib.corr_query(None, None, None, 0, 0, None, None) == pkg.CORR_EINVAL
+    assert lib.corr_set_offsets(None, None, 0) == pkg.CORR_EINVAL
+    assert lib.corr_eval_slices(None, None, 0, None) == pkg.CORR_EINVAL
     assert lib.corr_prepare_a(None) == pkg.CORR_EINVAL
     assert lib.corr_spectrum(None, 0, None, None) == pkg.CORR_EINVAL
     assert lib.corr_info(None, None) == pkg.CORR_EINVAL
@@ -168,3 +170,18 @@ def test_complementarity_parameters_need_their_flag(lib):
     g.sc_lambda = 1.0
     rc, out = _create(GOOD, GOOD, g)
     assert rc == pkg.CORR_EINVAL and not out.value
+
+
+def test_slices_output_struct_matches_the_header():
+    # the binding's mirror of corr_slices_out: five pointers, then the float threshold
+    import ctypes as ct
+    assert [f for f, _ in pkg.corr_slices_out._fields_] == ["scores", "peak_val", "peak_idx", "obstacle",
+                                                             "obstacle_count", "threshold"]
+    assert ct.sizeof(pkg.corr_slices_out) == 48
+    assert pkg.corr_slices_out.threshold.offset == 40
+    with open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "corr.h")) as f:
+        h = f.read()
+    body = h[h.index("typedef struct {\n    float* scores;"):h.index("} corr_slices_out;")]
+    fields = re.findall(r"^\s*(?:float|int64_t|uint32_t)\*?\s+(\w+);", body, flags=re.M)
+    assert fields == [f for f, _ in pkg.corr_slices_out._fields_]
+    assert "#define CORR_MAX_SLICES 16" in h and pkg.CORR_MAX_SLICES == 16
