@@ -813,10 +813,13 @@ __device__ __forceinline__ int kept_source(int o) {
 template <int M>
 struct ColShape {
     static constexpr int N = M / 2, H = N / 2;
-    static constexpr int COLS = cmin<H, 4096 / M>();          // forward y pass
+    // column batches: a forward y workgroup of 8 columns at m = 256 (16 at 128)
+    // keeps more workgroups per CU in flight than 16 (32) and was measured faster,
+    // as were 16-column inverse y workgroups at n = 128; the z passes keep 8
+    static constexpr int COLS = cmin<H, 2048 / M>();          // forward y pass
     static constexpr int ZCOLS = cmin<H, 2048 / M>();         // z passes
     static constexpr int YZB = 1;                              // z rows per y-pass workgroup
-    static constexpr int ICOLS = cmin<H, 4096 / N>();         // inverse y pass
+    static constexpr int ICOLS = cmin<H, 2048 / N>();         // inverse y pass
     static constexpr int XCOLS = cmin<N * N / 2, 4096 / N>(); // inverse x pass (line pairs)
 };
 
