@@ -815,12 +815,13 @@ struct ColShape {
     static constexpr int N = M / 2, H = N / 2;
     // column batches: a forward y workgroup of 8 columns at m = 256 (16 at 128)
     // keeps more workgroups per CU in flight than 16 (32) and was measured faster,
-    // as were 16-column inverse y workgroups at n = 128; the z passes keep 8
+    // as were 16-column inverse y and 16-line-pair inverse x workgroups at
+    // n = 128; the z passes keep 8
     static constexpr int COLS = cmin<H, 2048 / M>();          // forward y pass
     static constexpr int ZCOLS = cmin<H, 2048 / M>();         // z passes
     static constexpr int YZB = 1;                              // z rows per y-pass workgroup
     static constexpr int ICOLS = cmin<H, 2048 / N>();         // inverse y pass
-    static constexpr int XCOLS = cmin<N * N / 2, 4096 / N>(); // inverse x pass (line pairs)
+    static constexpr int XCOLS = cmin<N * N / 2, 2048 / N>(); // inverse x pass (line pairs)
 };
 
 // a2: y pass over [slab][z][y][mx] -> [slab][z][my][mx], M points pruned to N,
