@@ -626,10 +626,11 @@ __device__ __forceinline__ float fixed_to_float(unsigned long long u, float inv)
     return (float)(d * (double)inv);
 }
 
-// One spreading tile (z row z0, y rows y0 .. y0+TY-1 of rotation s).  Entered
-// by the whole workgroup; the LDS regions are laid out by the caller.
+// One spreading tile (z row z0, y rows y0 .. y0+TY-1 of rotation s), for the
+// components c0 .. c1-1 (c0 even).  Entered by the whole workgroup; the LDS
+// regions are laid out by the caller.
 template <int M>
-__device__ void spread_tile(int s, int z0, int y0, int yt, const int* __restrict__ bin_start,
+__device__ void spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const int* __restrict__ bin_start,
                             unsigned char* __restrict__ tile_live, const int* __restrict__ scell,
                             const float* __restrict__ skbw, const float* __restrict__ swts, int64_t nk, int q, int w,
                             int cap, float fix_scale, float fix_inv, float2* __restrict__ out, float2* lds,
@@ -673,17 +674,17 @@ __device__ void spread_tile(int s, int z0, int y0, int yt, const int* __restrict
         return make_float2(wp[0] * f, c + 1 < q ? wp[1] * f : 0.0f);
     };
     if (rounds == 1) {
-        for (int i = threadIdx.x; i < nfilt; i += NT) st.wq[i] = pair_weights(i, 0);
+        for (int i = threadIdx.x; i < nfilt; i += NT) st.wq[i] = pair_weights(i, c0);
     }
-    for (int cp = 0; cp < q; cp += 2) {
+    for (int cp = c0; cp < c1; cp += 2) {
         // with every knot staged, the next pair's weights are read while this
         // pair is spread (a thread per staged knot)
-        const bool prefetch = rounds == 1 && cp + 2 < q && (int)threadIdx.x < nfilt;
+        const bool prefetch = rounds == 1 && cp + 2 < c1 && (int)threadIdx.x < nfilt;
         float2 nxt = make_float2(0.f, 0.f);
         static_assert(kSpreadThreads >= 512, "one staged knot per thread");
         for (int r = 0; r < rounds; ++r) {
             if (rounds > 1) {
-                if (r > 0 || cp > 0)
+                if (r > 0 || cp > c0)
                     stage_knots<M>(sc_, kb_, w, y0, z0, rstart, rpre, nr, r * cap, cap, st, wave_tot);
                 for (int i = threadIdx.x; i < min(cap, nfilt - r * cap); i += NT) st.wq[i] = pair_weights(i, cp);
             }
@@ -752,15 +753,23 @@ __device__ void spread_tile(int s, int z0, int y0, int yt, const int* __restrict
                                   : make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
             out[((((size_t)s * q + cp + comp) * M + z0) * M + y0 + l) * H + mm] = o;
         }
-        if (cp + 2 < q) {
+        if (cp + 2 < c1) {
             __syncthreads();
             for (int t = threadIdx.x; t < 2 * TY * LS; t += NT) acc[t] = 0ull;
         }
     }
 }
 
-// Persistent spreading pass: each workgroup takes tiles of the plan's lists
-// (largest candidate sets first) from a shared counter until none are left.
+// Persistent spreading pass: each workgroup takes work items of the plan's
+// lists (largest candidate sets first) from a shared counter until none are
+// left.  An item is a tile, or, when the pass has fewer live tiles than twice
+// the workgroups, a tile of the buckets from kSplitBucket up is cut into one
+// item per component pair: the heaviest tiles then no longer set the pass's
+// length.  Each pair's output is written by one item only, with exact sums, so
+// the result does not depend on the cut.
+constexpr int kSplitBucket = 5;  // candidate sets of 256 knots or more
+constexpr int kSplitParts = 5;   // items per cut tile (at most the component pairs)
+
 template <int M>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __restrict__ bin_start,
                                                                 unsigned char* __restrict__ tile_live,
@@ -776,14 +785,18 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __res
     extern __shared__ float2 lds[];
     __shared__ int wave_tot[kSpreadThreads / 64];
     __shared__ int rstart[kMaxRanges], rpre[kMaxRanges + 1];
-    __shared__ int first[kPlanBuckets], size[kPlanBuckets], cur, total;
+    __shared__ int first[kPlanBuckets], size[kPlanBuckets], parts[kPlanBuckets], cur, total;
     load_table<M, kSpreadThreads>(lds + 2 * SS::TY * SS::LS, twm);
     if (threadIdx.x == 0) {
+        int tiles = 0;
+        for (int b = 0; b < kPlanBuckets; ++b) tiles += plan[b];
+        const bool cut = tiles < 2 * (int)gridDim.x;
         int run = 0;
         for (int b = kPlanBuckets - 1; b >= 0; --b) {
             first[b] = run;
             size[b] = plan[b];
-            run += size[b];
+            parts[b] = cut && b >= kSplitBucket ? min(kSplitParts, (q + 1) / 2) : 1;
+            run += size[b] * parts[b];
         }
         total = run;
     }
@@ -793,11 +806,14 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __res
         const int k = cur;
         if (k >= total) break;
         int b = kPlanBuckets - 1;
-        while (k >= first[b] + size[b]) --b;
-        const int id = list[(size_t)b * list_cap + (k - first[b])];
+        while (k >= first[b] + size[b] * parts[b]) --b;
+        const int e = (k - first[b]) / parts[b], part = (k - first[b]) % parts[b];
+        const int id = list[(size_t)b * list_cap + e];
         const int s = id / TILES, tile = id % TILES;
-        spread_tile<M>(s, tile / NTY, (tile % NTY) * SS::TY, tile % NTY, bin_start, tile_live, scell, skbw, swts,
-                       nk, q, w, cap, fix_scale, fix_inv, out, lds, wave_tot, rstart, rpre);
+        const int ppp = ((q + 1) / 2 + parts[b] - 1) / parts[b];  // component pairs per part
+        const int c0 = 2 * part * ppp, c1 = min(c0 + 2 * ppp, q);  // c0 < q as parts <= pairs
+        spread_tile<M>(s, tile / NTY, (tile % NTY) * SS::TY, tile % NTY, c0, c1, bin_start, tile_live, scell, skbw,
+                       swts, nk, q, w, cap, fix_scale, fix_inv, out, lds, wave_tot, rstart, rpre);
     }
 }
 
