@@ -840,6 +840,36 @@ struct ColShape {
     static constexpr int XCOLS = cmin<N * N / 2, 2048 / N>(); // inverse x pass (line pairs)
 };
 
+// fft_cols (columns interleaved) with its first, radix-8 pass taken on values
+// the caller already holds in registers: v[u][r] is element (row j + r LEN/8,
+// column c) of the thread's u-th butterfly, t = u NT + threadIdx.x, j = t / COLS,
+// c = t % COLS -- the elements that pass reads -- so the input never goes
+// through LDS.  The same butterflies in the same order: the result equals
+// fft_cols bit for bit.  `a` must not be read by any thread on entry.
+template <int LEN, int COLS, int NT = kThreads>
+struct RegPass {
+    static_assert(LEN >= 8, "radix-8 first pass");
+    static constexpr int NB = LEN / 8, WORK = NB * COLS, NBF = (WORK + NT - 1) / NT;
+};
+
+template <int LEN, int SIGN, int COLS, int NBF, int NT = kThreads>
+__device__ __forceinline__ void fft_cols_regs(float2 (&v)[NBF][8], float2* a, const float2* tw) {
+    using P = RegPass<LEN, COLS, NT>;
+    static_assert(NBF == P::NBF, "one register row per first-pass butterfly");
+#pragma unroll
+    for (int u = 0; u < P::NBF; ++u) {
+        const int t = u * NT + (int)threadIdx.x;
+        if (P::WORK % NT == 0 || t < P::WORK) {
+            const int c = t % COLS, j = t / COLS;
+            dft8<SIGN>(v[u]);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) a[(j * 8 + r) * COLS + c] = v[u][r];
+        }
+    }
+    __syncthreads();
+    fft_passes<LEN, 8, SIGN, COLS, COLS, 1, NT>(a, tw);
+}
+
 // a2: y pass over [slab][z][y][mx] -> [slab][z][my][mx], M points pruned to N,
 // slab = rotation * q + component.  A workgroup takes YZB z rows of one slab
 // and column block; dead z rows are skipped (their output is never read) and
@@ -866,12 +896,21 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ i
         __syncthreads();
         const size_t plane = (size_t)blockIdx.z * M + z;  // slab * M + z
         const float2* src = in + plane * M * H + c0;
-        for (int t = threadIdx.x; t < M * COLS; t += kThreads) {
-            const int y = t / COLS;
-            a[t] = live[y / TY] ? src[(size_t)y * H + t % COLS] : make_float2(0.f, 0.f);
+        using P = RegPass<M, COLS>;
+        float2 v[P::NBF][8];
+#pragma unroll
+        for (int u = 0; u < P::NBF; ++u) {
+            const int t = u * kThreads + (int)threadIdx.x;
+            if (P::WORK % kThreads == 0 || t < P::WORK) {
+                const int c = t % COLS, j = t / COLS;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int y = j + r * P::NB;
+                    v[u][r] = live[y / TY] ? src[(size_t)y * H + c] : make_float2(0.f, 0.f);
+                }
+            }
         }
-        __syncthreads();
-        fft_cols<M, -1, COLS, false>(a, twl);
+        fft_cols_regs<M, -1, COLS>(v, a, twl);
         float2* dst = out + plane * N * H + c0;
         for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
             const int o = t / COLS, c = t % COLS;
@@ -897,21 +936,25 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
                                              const float2* twl, const unsigned char* zlive,
                                              float2 (&acc)[ZAcc<M>::PER]) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ZCOLS, PER = ZAcc<M>::PER;
-    constexpr int LD = (M * COLS + kThreads - 1) / kThreads;  // column values per thread
+    using P = RegPass<M, COLS>;
     const int my = iy < N / 2 ? iy : iy - N;
 #pragma unroll
     for (int k = 0; k < PER; ++k) acc[k] = make_float2(0.f, 0.f);
-    // component c's columns are read into registers while component c-1 is
-    // being transformed
-    float2 nxt[LD];
+    // component c's columns are read into registers, in the order of the
+    // transform's first pass, while component c-1 is being transformed
+    float2 nxt[P::NBF][8];
     auto fetch = [&](int c) {
         const float2* src = in + (((size_t)s * q + c) * M) * N * H + (size_t)iy * H + c0;
 #pragma unroll
-        for (int k = 0; k < LD; ++k) {
-            const int t = k * kThreads + (int)threadIdx.x;
-            if ((M * COLS) % kThreads == 0 || t < M * COLS) {
-                const int z = t / COLS;
-                nxt[k] = zlive[z] ? src[(size_t)z * N * H + t % COLS] : make_float2(0.f, 0.f);
+        for (int u = 0; u < P::NBF; ++u) {
+            const int t = u * kThreads + (int)threadIdx.x;
+            if (P::WORK % kThreads == 0 || t < P::WORK) {
+                const int cc = t % COLS, j = t / COLS;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int z = j + r * P::NB;
+                    nxt[u][r] = zlive[z] ? src[(size_t)z * N * H + cc] : make_float2(0.f, 0.f);
+                }
             }
         }
     };
@@ -930,19 +973,18 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
     }
     fetch(0);
     for (int c = 0; c < q; ++c) {
+        float2 v[P::NBF][8];
 #pragma unroll
-        for (int k = 0; k < LD; ++k) {
-            const int t = k * kThreads + (int)threadIdx.x;
-            if ((M * COLS) % kThreads == 0 || t < M * COLS) a[t] = nxt[k];
-        }
+        for (int u = 0; u < P::NBF; ++u)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) v[u][r] = nxt[u][r];
         if (c + 1 < q) {
             fetch(c + 1);
             const float* vt = vtab + (size_t)(c + 1) * m2n;
 #pragma unroll
             for (int k = 0; k < PER; ++k) vnxt[k] = vidx[k] >= 0 ? vt[vidx[k]] : 0.f;
         }
-        __syncthreads();
-        fft_cols<M, -1, COLS, false>(a, twl);
+        fft_cols_regs<M, -1, COLS>(v, a, twl);
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             if (vidx[k] >= 0) {
@@ -1073,14 +1115,23 @@ __global__ __launch_bounds__(kThreads) void k_product_ifft_z(const float2* __res
     }
     load_table<N>(twnl, twn);
     const float2* src = accs + (size_t)s * N * N * H + (size_t)iy * H + c0;
-    for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
-        const int o = t / COLS, cc = t % COLS;
-        const float2 acc = src[(size_t)o * N * H + cc];
-        const float2 A = fa[((size_t)o * N + iy) * H + c0 + cc];
-        a[t] = cmul(cmul(A, make_float2(acc.x, -acc.y)), shift_factor(phase, N, c0 + cc, iy, o));
+    using P = RegPass<N, COLS>;
+    float2 v[P::NBF][8];
+#pragma unroll
+    for (int u = 0; u < P::NBF; ++u) {
+        const int t = u * kThreads + (int)threadIdx.x;
+        if (P::WORK % kThreads == 0 || t < P::WORK) {
+            const int cc = t % COLS, j = t / COLS;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int o = j + r * P::NB;
+                const float2 acc = src[(size_t)o * N * H + cc];
+                const float2 A = fa[((size_t)o * N + iy) * H + c0 + cc];
+                v[u][r] = cmul(cmul(A, make_float2(acc.x, -acc.y)), shift_factor(phase, N, c0 + cc, iy, o));
+            }
+        }
     }
-    __syncthreads();
-    fft_cols<N, 1, COLS, false>(a, twnl);
+    fft_cols_regs<N, 1, COLS>(v, a, twnl);
     for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * N * H + t % COLS] = a[t];
 }
 
@@ -1096,9 +1147,18 @@ __global__ __launch_bounds__(kThreads) void k_ifft_y(const float2* in, float2* o
     const int c0 = blockIdx.x * COLS;
     const size_t plane = (size_t)blockIdx.z * N + blockIdx.y;
     const float2* src = in + plane * N * H + c0;
-    for (int t = threadIdx.x; t < N * COLS; t += kThreads) a[t] = src[(size_t)(t / COLS) * H + t % COLS];
-    __syncthreads();
-    fft_cols<N, 1, COLS, false>(a, twl);
+    using P = RegPass<N, COLS>;
+    float2 v[P::NBF][8];
+#pragma unroll
+    for (int u = 0; u < P::NBF; ++u) {
+        const int t = u * kThreads + (int)threadIdx.x;
+        if (P::WORK % kThreads == 0 || t < P::WORK) {
+            const int c = t % COLS, j = t / COLS;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) v[u][r] = src[(size_t)(j + r * P::NB) * H + c];
+        }
+    }
+    fft_cols_regs<N, 1, COLS>(v, a, twl);
     float2* dst = out + plane * N * H + c0;
     for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * H + t % COLS] = a[t];
 }
