@@ -150,7 +150,10 @@ int corr_info(const corr_ctx* ctx, corr_info_t* out);
 #define CORR_STAGE_IFFT_X         7  /* a5: inverse x pass (to real) + block peaks    */
 #define CORR_STAGE_PEAK           8  /* a5: per-rotation peak                         */
 #define CORR_STAGE_QUERY          9  /* single-configuration query (corr_query)       */
-#define CORR_N_STAGES            10
+#define CORR_STAGE_GRAPH         10  /* a whole evaluation replayed as one hipGraph
+                                        (corr_tuning.graph); its stages are not timed
+                                        one by one                                      */
+#define CORR_N_STAGES            11
 
 /* Turn per-stage timing on (enable != 0) or off.  While on, every stage launch
  * on the context's stream is bracketed by a pair of HIP events. */
@@ -250,6 +253,60 @@ typedef struct {
 
 int corr_pass_info(corr_ctx* ctx, corr_pass_t* out);
 
+/* ---- launch shapes, autotuning and graph replay --------------------------- */
+
+/*
+ * How a context cuts its pipeline into launches.  No setting changes the
+ * arithmetic or its order, so every tuning gives bitwise the same outputs; only
+ * the time differs.  A new context starts from the defaults (the slot count of
+ * corr_grid.batch, two spreading workgroups per CU, each pass's default width,
+ * graph off).
+ */
+typedef struct {
+    int32_t slots;       /* rotations per pipeline pass, 1..256; changing it reallocates
+                            the workspace (after the stream has drained)               */
+    int32_t spread_wgs;  /* persistent workgroups of the spreading pass, 1 .. 2 x CUs   */
+    int32_t cols_y;      /* columns per forward-y workgroup                              */
+    int32_t cols_z;      /* columns per z-pass workgroup                                 */
+    int32_t cols_iy;     /* columns per inverse-y (and slice-product) workgroup          */
+    int32_t pairs_ix;    /* line pairs per inverse-x workgroup                           */
+    int32_t graph;       /* 1: corr_eval and corr_eval_slices capture all launches of a
+                            call (every batch of rotations) into a hipGraph on a private
+                            stream and replay it with one hipGraphLaunch on the
+                            context's stream.  The graph is kept and replayed while the
+                            call's n_rot, output pointers and threshold, the slices and
+                            the tuning stay the same; otherwise it is captured again.
+                            The rotations are copied to a device array first (one
+                            host-to-device copy per call).  0: launch by launch.     */
+} corr_tuning;
+
+/* The context's current tuning. */
+int corr_get_tuning(const corr_ctx* ctx, corr_tuning* out);
+
+/* Set every field (start from corr_get_tuning).  The widths must be among
+ * corr_tuning_choices.  Errors: CORR_EINVAL (a value outside its choices),
+ * CORR_ENOMEM / CORR_EHIP (workspace); the old tuning then stays in force
+ * unless the workspace was lost. */
+int corr_set_tuning(corr_ctx* ctx, const corr_tuning* tuning);
+
+/* The widths allowed for column pass `pass` (0 cols_y, 1 cols_z, 2 cols_iy,
+ * 3 pairs_ix) on this context's grid: the default first, then half and twice
+ * it where the pass's shape allows.  out3 receives *count (1..3) values. */
+int corr_tuning_choices(const corr_ctx* ctx, int32_t pass, int32_t* out3, int32_t* count);
+
+/*
+ * Autotuner.  Evaluates these rotations (arguments as for corr_eval) under
+ * candidate tunings and keeps the fastest: coordinate descent over slots
+ * (powers of two up to n_rot, workspace <= 8 GiB), spread_wgs (one or two per
+ * CU) and the four column widths, each candidate timed by HIP events as the
+ * least of `reps` (1..100) evaluations after an untimed one.  The graph setting
+ * is kept as it is.  Synchronous; the outputs hold the last evaluation's
+ * results, which equal corr_eval's under any tuning.  *out (may be NULL)
+ * receives the tuning kept.
+ */
+int corr_autotune(corr_ctx* ctx, const double* quat_wxyz, int64_t n_rot, float* scores_dev, float* peak_val_dev,
+                  int64_t* peak_idx_dev, int32_t reps, corr_tuning* out);
+
 /* ---- uneven batches of pairs --------------------------------------------- */
 
 /* One shape pair with its own translation grid (grid.batch is ignored). */
@@ -283,6 +340,12 @@ int corr_batch_create(const corr_pair* pairs, int32_t n_pairs, int32_t slots, vo
  */
 int corr_batch_eval(corr_batch* b, const double* quat_wxyz, const int64_t* rot_offsets, float* scores_dev,
                     const int64_t* score_offsets, float* peak_val_dev, int64_t* peak_idx_dev);
+
+/* enable = 1: corr_batch_eval captures all pairs' launches of a call into one
+ * hipGraph and replays it with one hipGraphLaunch while the call's rotation
+ * offsets, score offsets and output pointers stay the same (see
+ * corr_tuning.graph); 0: launch by launch (the default). */
+int corr_batch_set_graph(corr_batch* b, int32_t enable);
 
 int corr_batch_info(const corr_batch* b, int32_t pair, corr_info_t* out);
 int corr_batch_destroy(corr_batch* b);

@@ -32,12 +32,13 @@ CORR_MAX_SLICES = 16
 
 EXPORTS = ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
            "corr_profile_read", "corr_pass_info", "corr_query", "corr_set_offsets", "corr_eval_slices",
+           "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune",
            "corr_destroy", "corr_last_error",
            "corr_batch_create",
-           "corr_batch_eval",
+           "corr_batch_eval", "corr_batch_set_graph",
            "corr_batch_info", "corr_batch_destroy", "corr_batch_last_error")
 STAGES = ("rotate", "bin", "spread_fft_x", "fft_y", "fft_z_spectrum", "fft_z_product", "ifft_y", "ifft_x", "peak",
-          "query")
+          "query", "graph")
 
 
 class corr_grid(ctypes.Structure):
@@ -63,6 +64,15 @@ class corr_pass_t(ctypes.Structure):
 class corr_slices_out(ctypes.Structure):
     _fields_ = [("scores", ctypes.c_void_p), ("peak_val", ctypes.c_void_p), ("peak_idx", ctypes.c_void_p),
                 ("obstacle", ctypes.c_void_p), ("obstacle_count", ctypes.c_void_p), ("threshold", ctypes.c_float)]
+
+
+class corr_tuning(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("spread_wgs", ctypes.c_int32), ("cols_y", ctypes.c_int32),
+                ("cols_z", ctypes.c_int32), ("cols_iy", ctypes.c_int32), ("pairs_ix", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
+
+
+TUNING_FIELDS = tuple(k for k, _ in corr_tuning._fields_)
 
 
 class CorrError(RuntimeError):
@@ -94,12 +104,16 @@ def load_library(path: str = LIB_PATH):
     lib.corr_query.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(ctypes.c_int64)]
     lib.corr_set_offsets.argtypes = [vp, vp, i32]
     lib.corr_eval_slices.argtypes = [vp, vp, i64, ctypes.POINTER(corr_slices_out)]
+    lib.corr_get_tuning.argtypes = [vp, ctypes.POINTER(corr_tuning)]
+    lib.corr_set_tuning.argtypes = [vp, ctypes.POINTER(corr_tuning)]
+    lib.corr_tuning_choices.argtypes = [vp, i32, vp, ctypes.POINTER(i32)]
+    lib.corr_autotune.argtypes = [vp, vp, i64, vp, vp, vp, i32, ctypes.POINTER(corr_tuning)]
     lib.corr_destroy.argtypes = [vp]
     lib.corr_last_error.argtypes = [vp]
     lib.corr_last_error.restype = ctypes.c_char_p
     for name in ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
                  "corr_profile_read", "corr_pass_info", "corr_query", "corr_set_offsets", "corr_eval_slices",
-                 "corr_destroy"):
+                 "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune", "corr_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -189,6 +203,38 @@ def corr_eval_slices(ctx, quats, scores_ptr=None, peak_val_ptr=None, peak_idx_pt
     _check(load_library().corr_eval_slices(ctx, q.ctypes.data if len(q) else None, len(q), ctypes.byref(o)), ctx)
 
 
+def corr_get_tuning(ctx) -> dict:
+    t = corr_tuning()
+    _check(load_library().corr_get_tuning(ctx, ctypes.byref(t)), ctx)
+    return {k: getattr(t, k) for k in TUNING_FIELDS}
+
+
+def corr_set_tuning(ctx, **fields):
+    """Change the named fields of the context's tuning (the others stay)."""
+    t = corr_tuning()
+    _check(load_library().corr_get_tuning(ctx, ctypes.byref(t)), ctx)
+    for k, v in fields.items():
+        if k not in TUNING_FIELDS:
+            raise KeyError("unknown tuning field %r" % k)
+        setattr(t, k, int(v))
+    _check(load_library().corr_set_tuning(ctx, ctypes.byref(t)), ctx)
+
+
+def corr_tuning_choices(ctx, pass_id) -> list:
+    out = (ctypes.c_int32 * 3)()
+    cnt = ctypes.c_int32()
+    _check(load_library().corr_tuning_choices(ctx, int(pass_id), out, ctypes.byref(cnt)), ctx)
+    return [out[i] for i in range(cnt.value)]
+
+
+def corr_autotune(ctx, quats, scores_ptr, peak_val_ptr, peak_idx_ptr, reps=3) -> dict:
+    q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
+    t = corr_tuning()
+    _check(load_library().corr_autotune(ctx, q.ctypes.data if len(q) else None, len(q), scores_ptr or None,
+                                        peak_val_ptr or None, peak_idx_ptr or None, int(reps), ctypes.byref(t)), ctx)
+    return {k: getattr(t, k) for k in TUNING_FIELDS}
+
+
 def corr_destroy(ctx):
     load_library().corr_destroy(ctx)
 
@@ -276,6 +322,26 @@ class Correlator:
 
     def pass_info(self):
         return corr_pass_info(self.ctx)
+
+    def tuning(self):
+        return corr_get_tuning(self.ctx)
+
+    def set_tuning(self, **fields):
+        with self.torch.cuda.device(self.device):
+            corr_set_tuning(self.ctx, **fields)
+
+    def autotune(self, quats, scores=True, peaks=True, reps=3):
+        """Run the autotuner on these rotations; returns the tuning kept."""
+        torch = self.torch
+        q = np.asarray(quats, dtype=np.float64).reshape(-1, 4)
+        r, n = len(q), self.n
+        s = torch.empty((r, n, n, n), dtype=torch.float32, device=self.device) if scores else None
+        pv = torch.empty(r, dtype=torch.float32, device=self.device) if peaks else None
+        pi = torch.empty(r, dtype=torch.int64, device=self.device) if peaks else None
+        with torch.cuda.device(self.device):
+            return corr_autotune(self.ctx, q, s.data_ptr() if s is not None else None,
+                                 pv.data_ptr() if pv is not None else None, pi.data_ptr() if pi is not None else None,
+                                 reps)
 
     def query(self, quat, t, mode_radius2):
         """Score at translations t ([n][3]) over the modes |m|^2 <= mode_radius2;
@@ -470,7 +536,7 @@ class Proposer:
 
 # ---- uneven batches (corr_batch_*) ---------------------------------------------
 
-BATCH_EXPORTS = ("corr_batch_create", "corr_batch_eval", "corr_batch_info", "corr_batch_destroy",
+BATCH_EXPORTS = ("corr_batch_create", "corr_batch_eval", "corr_batch_set_graph", "corr_batch_info", "corr_batch_destroy",
                  "corr_batch_last_error")
 
 
@@ -485,6 +551,7 @@ def _batch_lib():
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         lib.corr_batch_create.argtypes = [vp, i32, i32, vp, ctypes.POINTER(vp)]
         lib.corr_batch_eval.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        lib.corr_batch_set_graph.argtypes = [vp, i32]
         lib.corr_batch_info.argtypes = [vp, i32, ctypes.POINTER(corr_info_t)]
         lib.corr_batch_destroy.argtypes = [vp]
         lib.corr_batch_last_error.argtypes = [vp]
@@ -527,6 +594,10 @@ def corr_batch_eval(b, quats, rot_offsets, scores_ptr, score_offsets, peak_val_p
                                          peak_idx_ptr or None), b)
 
 
+def corr_batch_set_graph(b, enable):
+    _bcheck(_batch_lib().corr_batch_set_graph(b, int(bool(enable))), b)
+
+
 def corr_batch_info(b, pair) -> dict:
     info = corr_info_t()
     _bcheck(_batch_lib().corr_batch_info(b, int(pair), ctypes.byref(info)), b)
@@ -552,17 +623,26 @@ class Batch:
             self.b = corr_batch_create([(A, B, make_grid(n, box, origin)) for A, B, n, box, origin in pairs], slots,
                                        self.stream.cuda_stream)
 
-    def eval(self, quats_per_pair, scores=False):
+    def set_graph(self, enable):
+        corr_batch_set_graph(self.b, enable)
+
+    def eval(self, quats_per_pair, scores=False, out=None):
+        """out = (packed scores or None, peak_val, peak_idx) reuses caller tensors
+        (a graph is replayed only while the output pointers stay the same)."""
         torch = self.torch
         counts = [len(q) for q in quats_per_pair]
         offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
         q = np.concatenate([np.asarray(x, dtype=np.float64).reshape(-1, 4) for x in quats_per_pair])
-        pv = torch.empty(int(offs[-1]), dtype=torch.float32, device=self.device)
-        pi = torch.empty(int(offs[-1]), dtype=torch.int64, device=self.device)
-        s = None
-        if scores:
-            total = sum(c * n ** 3 for c, n in zip(counts, self.ns))
-            s = torch.empty(total, dtype=torch.float32, device=self.device)
+        total = sum(c * n ** 3 for c, n in zip(counts, self.ns))
+        if out is not None:
+            s, pv, pi = out
+            if pv.numel() != int(offs[-1]) or pi.numel() != int(offs[-1]) or (s is not None and s.numel() != total):
+                raise ValueError("output tensors do not match the rotations")
+            scores = s is not None
+        else:
+            pv = torch.empty(int(offs[-1]), dtype=torch.float32, device=self.device)
+            pi = torch.empty(int(offs[-1]), dtype=torch.int64, device=self.device)
+            s = torch.empty(total, dtype=torch.float32, device=self.device) if scores else None
         with torch.cuda.device(self.device):
             corr_batch_eval(self.b, q, offs, s.data_ptr() if s is not None else None, None, pv.data_ptr(),
                             pi.data_ptr())

@@ -10,6 +10,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -41,16 +42,19 @@ def build_library(verbose: bool = False) -> str:
     hipcc = _hipcc()
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src, lang in (("corr_kernels.hip", "hip"), ("corr_host.cpp", "hip"), ("prop_kernels.hip", "hip"),
                       ("prop_host.cpp", "hip")):
         obj = os.path.join(bdir, src + ".o")
-        cmd = [hipcc, "-x", lang, "--offload-arch=" + ARCH, *COMMON, *DEVICE_FLAGS, "-c",
-               os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        _run(cmd)
+        cmds.append([hipcc, "-x", lang, "--offload-arch=" + ARCH, *COMMON, *DEVICE_FLAGS, "-c",
+                     os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    # the four translation units compile side by side
+    with ThreadPoolExecutor(max_workers=len(cmds)) as pool:
+        for cmd in cmds:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+        list(pool.map(_run, cmds))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

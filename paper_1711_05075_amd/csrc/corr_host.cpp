@@ -370,6 +370,42 @@ struct Workspace {
 
 }  // namespace corr
 
+// Graph replay of whole evaluations: every launch of one corr_eval (or
+// corr_batch_eval) call, all batches of rotations, is captured once on a
+// private stream and replayed by one hipGraphLaunch on the caller's stream as
+// long as the call's device pointers, sizes and launch shapes stay the same
+// (`key`).  The rotations are the only per-call input the graph reads: they
+// are copied into a device array of fixed address before each launch.
+struct GraphState {
+    hipStream_t cap = nullptr;      // capture stream (default priority)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> key;      // what `exec` was captured for
+    double* d_quats = nullptr;      // device [cap_rot][4]
+    double* h_quats = nullptr;      // pinned [cap_rot][4]
+    int64_t cap_rot = 0;
+    hipEvent_t copied = nullptr;    // the last copy out of h_quats
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        key.clear();
+    }
+    void release() {
+        drop_graph();
+        if (d_quats) (void)hipFree(d_quats);
+        if (h_quats) (void)hipHostFree(h_quats);
+        if (copied) (void)hipEventDestroy(copied);
+        if (cap) (void)hipStreamDestroy(cap);
+        d_quats = nullptr;
+        h_quats = nullptr;
+        copied = nullptr;
+        cap = nullptr;
+        cap_rot = 0;
+    }
+};
+
 struct corr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -377,6 +413,9 @@ struct corr_ctx {
     double box = 0, origin[3] = {0, 0, 0}, sigma = 2, tol = 1e-6;
     double sc_r0 = 0, sc_lam = 0;  // shape-complementarity kernel parameters (0, 0: overlap score)
     uint32_t flags = 0;
+    bool graph = false;       // replay evaluations as captured hipGraphs (corr_set_tuning)
+    uint64_t shape_gen = 0;   // bumped whenever launch shapes, workspace or slices change
+    GraphState gs;
     int qmax = 1;
     int64_t nkmax = 1;  // max(nA, nB, 1)
     Shape A, B;
@@ -693,7 +732,7 @@ corr::WsReq ws_req(const corr_ctx* c) {
     r.nkq = (size_t)c->nkmax * c->qmax;
     r.counts = (size_t)corr::bin_keys(g.m);
     r.bins = (size_t)corr::bin_keys(g.m) + 1;
-    r.blocks = (size_t)corr::ifft_x_blocks(g);
+    r.blocks = (size_t)corr::ifft_x_blocks_max(g);  // any inverse-x width
     r.tiles = (size_t)g.m * corr::spread_tiles(g);
     r.list = (size_t)corr::plan_buckets() * r.tiles;
     return r;
@@ -709,24 +748,24 @@ struct EvalOut {
     float thr = 0.f;
 };
 
+void check_eval_args(int64_t n_rot, const EvalOut& o);
+
 // Score n_rot rotations of B (validated here) against each fixed spectrum in
 // fas, batch by batch: B is spread and transformed once per batch, then each
 // slice takes the product and inverse passes (the inverse y pass works in
 // place, so B's transformed components stay for the next slice).
 void eval_impl(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, const std::vector<const float2*>& fas,
-               const EvalOut& o) {
-    if (n_rot < 0) fail(CORR_EINVAL, "n_rot < 0");
-    if ((o.peak_val == nullptr) != (o.peak_idx == nullptr))
-        fail(CORR_EINVAL, "peak_val and peak_idx must both be set or both be NULL");
-    if (!std::isfinite(o.thr)) fail(CORR_EINVAL, "threshold must be finite");
-    validate_quats(quat_wxyz, n_rot);
+               const EvalOut& o, const double* d_quats = nullptr) {
+    check_eval_args(n_rot, o);
+    if (!d_quats) validate_quats(quat_wxyz, n_rot);
     const Geom& g = c->g;
     const size_t n3 = (size_t)g.n * g.n * g.n;
     const int nb = corr::ifft_x_blocks(g);
     for (int64_t r0 = 0; r0 < n_rot; r0 += c->ws->slots) {
         const int S = (int)std::min<int64_t>(c->ws->slots, n_rot - r0);
-        stage_quats(c, quat_wxyz + 4 * r0, S);
-        run_spectrum_stages(c, c->B, c->ws->quats, S);
+        // rotations already on the device (graph replay), or staged per batch
+        if (!d_quats) stage_quats(c, quat_wxyz + 4 * r0, S);
+        run_spectrum_stages(c, c->B, d_quats ? d_quats + 4 * r0 : c->ws->quats, S);
         // several slices: B's z sums once, into the second half of buf1
         // (buf1 holds q m^2 n/2 >= 2 n^2 n/2 values per slot)
         float2* zsums = c->ws->buf1 + (size_t)c->ws->slots * g.n * g.n * g.half;
@@ -763,13 +802,120 @@ void eval_impl(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, const std::v
     }
 }
 
+// ---- graph replay ------------------------------------------------------------
+
+// Copy n host rotations into gs's device array (grown on demand, which drops
+// the captured graph: it reads the old array) on stream st.
+const double* graph_quats(GraphState& gs, hipStream_t st, const double* q, int64_t n) {
+    if (n > gs.cap_rot) {
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        gs.drop_graph();
+        if (gs.d_quats) (void)hipFree(gs.d_quats);
+        if (gs.h_quats) (void)hipHostFree(gs.h_quats);
+        gs.d_quats = nullptr;
+        gs.h_quats = nullptr;
+        gs.cap_rot = 0;
+        const int64_t cap = std::max<int64_t>(n, 64);
+        hip_check(hipMalloc((void**)&gs.d_quats, sizeof(double) * 4 * cap), "hipMalloc (graph rotations)");
+        hip_check(hipHostMalloc((void**)&gs.h_quats, sizeof(double) * 4 * cap, hipHostMallocDefault), "hipHostMalloc");
+        gs.cap_rot = cap;
+        if (!gs.copied) hip_check(hipEventCreateWithFlags(&gs.copied, hipEventDisableTiming), "hipEventCreate");
+    } else {
+        hip_check(hipEventSynchronize(gs.copied), "event sync");  // h_quats free again
+    }
+    std::memcpy(gs.h_quats, q, sizeof(double) * 4 * n);
+    hip_check(hipMemcpyAsync(gs.d_quats, gs.h_quats, sizeof(double) * 4 * n, hipMemcpyHostToDevice, st),
+              "rotations H2D");
+    hip_check(hipEventRecord(gs.copied, st), "hipEventRecord");
+    return gs.d_quats;
+}
+
+// While capturing: the contexts' launches go to the capture stream, without
+// per-stage timing events.
+struct CaptureScope {
+    std::vector<corr_ctx*> cs;
+    std::vector<hipStream_t> streams;
+    std::vector<bool> prof;
+    CaptureScope(const std::vector<corr_ctx*>& ctxs, hipStream_t cap) : cs(ctxs) {
+        for (corr_ctx* c : cs) {
+            streams.push_back(c->stream);
+            prof.push_back(c->profiling);
+            c->stream = cap;
+            c->profiling = false;
+        }
+    }
+    ~CaptureScope() {
+        for (size_t i = 0; i < cs.size(); ++i) {
+            cs[i]->stream = streams[i];
+            cs[i]->profiling = prof[i];
+        }
+    }
+};
+
+// Launch the graph captured for `key` on st, capturing it first (body(stream)
+// enqueues the evaluation) if there is none or it was captured for another key.
+template <class Body>
+void graph_launch(GraphState& gs, hipStream_t st, std::vector<uint64_t> key, const std::vector<corr_ctx*>& ctxs,
+                  corr_ctx* timed, Body&& body) {
+    key.push_back((uint64_t)(uintptr_t)gs.d_quats);
+    if (!gs.exec || key != gs.key) {
+        gs.drop_graph();
+        if (!gs.cap) hip_check(hipStreamCreateWithFlags(&gs.cap, hipStreamNonBlocking), "hipStreamCreate");
+        hip_check(hipStreamBeginCapture(gs.cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+            CaptureScope scope(ctxs, gs.cap);
+            body();
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(gs.cap, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        hip_check(hipStreamEndCapture(gs.cap, &gs.graph), "hipStreamEndCapture");
+        hip_check(hipGraphInstantiate(&gs.exec, gs.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        gs.key = std::move(key);
+    }
+    if (timed)
+        stage(timed, CORR_STAGE_GRAPH, "hipGraphLaunch", [&] { return hipGraphLaunch(gs.exec, st); });
+    else
+        hip_check(hipGraphLaunch(gs.exec, st), "hipGraphLaunch");
+}
+
+void check_eval_args(int64_t n_rot, const EvalOut& o) {
+    if (n_rot < 0) fail(CORR_EINVAL, "n_rot < 0");
+    if ((o.peak_val == nullptr) != (o.peak_idx == nullptr))
+        fail(CORR_EINVAL, "peak_val and peak_idx must both be set or both be NULL");
+    if (!std::isfinite(o.thr)) fail(CORR_EINVAL, "threshold must be finite");
+}
+
+// An evaluation: enqueued launch by launch, or (graph mode) as one graph launch.
+void eval_entry(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, const std::vector<const float2*>& fas,
+                const EvalOut& o) {
+    if (!c->graph) {
+        eval_impl(c, quat_wxyz, n_rot, fas, o);
+        return;
+    }
+    check_eval_args(n_rot, o);
+    validate_quats(quat_wxyz, n_rot);
+    if (n_rot == 0) return;
+    const double* dq = graph_quats(c->gs, c->stream, quat_wxyz, n_rot);
+    float thr_bits = o.thr;
+    uint32_t tb;
+    std::memcpy(&tb, &thr_bits, 4);
+    std::vector<uint64_t> key = {1, c->shape_gen, (uint64_t)n_rot, (uint64_t)(uintptr_t)o.scores,
+                                 (uint64_t)(uintptr_t)o.peak_val, (uint64_t)(uintptr_t)o.peak_idx,
+                                 (uint64_t)(uintptr_t)o.mask, (uint64_t)(uintptr_t)o.count, tb};
+    for (const float2* f : fas) key.push_back((uint64_t)(uintptr_t)f);
+    graph_launch(c->gs, c->stream, std::move(key), {c}, c, [&] { eval_impl(c, nullptr, n_rot, fas, o, dq); });
+}
+
 void eval_plain(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* scores_dev, float* peak_val_dev,
                 int64_t* peak_idx_dev) {
     EvalOut o;
     o.scores = scores_dev;
     o.peak_val = peak_val_dev;
     o.peak_idx = peak_idx_dev;
-    eval_impl(c, quat_wxyz, n_rot, {c->fa}, o);
+    eval_entry(c, quat_wxyz, n_rot, {c->fa}, o);
 }
 
 // Plan and compute the offset slices of A (corr_set_offsets).
@@ -810,6 +956,7 @@ void set_offsets(corr_ctx* c, const double* offsets, int32_t n) {
             hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
             const int slots = c->ws->slots;
             c->ws->release();
+            c->shape_gen++;
             c->qmax = qmax;
             c->ws->allocate(slots, ws_req(c), c->stream);
         }
@@ -824,6 +971,7 @@ void set_offsets(corr_ctx* c, const double* offsets, int32_t n) {
     c->slice_mem.release();
     c->slices = std::move(ns);
     c->slice_mem = nm;
+    c->shape_gen++;
 }
 
 template <class F>
@@ -853,6 +1001,7 @@ void destroy_ctx(corr_ctx* c) {
         if (g->p) (void)hipFree(g->p);
     if (c->q_host) (void)hipHostFree(c->q_host);
     if (c->q_done) (void)hipEventDestroy(c->q_done);
+    c->gs.release();
     c->mem.release();
     c->slice_mem.release();
     if (c->own_ws && c->ws) {
@@ -868,9 +1017,197 @@ void destroy_ctx(corr_ctx* c) {
     delete c;
 }
 
+// ---- launch shapes and the autotuner ---------------------------------------
+
+int cu_count(const corr_ctx* c) {
+    int cus = 0;
+    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device), "CU count");
+    return std::max(cus, 1);
+}
+
+corr_tuning get_tuning(const corr_ctx* c) {
+    corr_tuning t;
+    std::memset(&t, 0, sizeof t);
+    int def[3];
+    t.slots = c->ws->slots;
+    t.spread_wgs = c->g.spread_wgs;
+    t.cols_y = c->g.cols_y ? c->g.cols_y : (corr::col_choices(c->g.m, 0, def), def[0]);
+    t.cols_z = c->g.cols_z ? c->g.cols_z : (corr::col_choices(c->g.m, 1, def), def[0]);
+    t.cols_iy = c->g.cols_iy ? c->g.cols_iy : (corr::col_choices(c->g.m, 2, def), def[0]);
+    t.pairs_ix = c->g.pairs_ix ? c->g.pairs_ix : (corr::col_choices(c->g.m, 3, def), def[0]);
+    t.graph = c->graph ? 1 : 0;
+    return t;
+}
+
+// Validate t against the context's choices; then apply it (the workspace is
+// reallocated, after the stream has drained, when the slot count changes).
+void set_tuning(corr_ctx* c, const corr_tuning& t) {
+    const int widths[4] = {t.cols_y, t.cols_z, t.cols_iy, t.pairs_ix};
+    static const char* names[4] = {"cols_y", "cols_z", "cols_iy", "pairs_ix"};
+    for (int p = 0; p < 4; ++p) {
+        int ch[3];
+        const int k = corr::col_choices(c->g.m, p, ch);
+        bool ok = false;
+        for (int i = 0; i < k; ++i) ok = ok || ch[i] == widths[p];
+        if (!ok) fail(CORR_EINVAL, "%s = %d is not one of this grid's widths (corr_tuning_choices)", names[p], widths[p]);
+    }
+    const int cus = cu_count(c);
+    if (t.spread_wgs < 1 || t.spread_wgs > 2 * cus)
+        fail(CORR_EINVAL, "spread_wgs = %d; allowed 1..%d (two per CU)", t.spread_wgs, 2 * cus);
+    if (t.slots < 1 || t.slots > 256) fail(CORR_EINVAL, "slots = %d; allowed 1..256", t.slots);
+    if (t.graph != 0 && t.graph != 1) fail(CORR_EINVAL, "graph must be 0 or 1");
+    if (t.slots != c->ws->slots) {
+        if (!c->own_ws) fail(CORR_EUNSUPPORTED, "the pairs of a batch share their workspace: slots are fixed");
+        hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+        c->gs.drop_graph();
+        c->shape_gen++;
+        c->ws->release();
+        c->ws->allocate(t.slots, ws_req(c), c->stream);
+    }
+    Geom& g = c->g;
+    if (g.cols_y != t.cols_y || g.cols_z != t.cols_z || g.cols_iy != t.cols_iy || g.pairs_ix != t.pairs_ix ||
+        g.spread_wgs != t.spread_wgs)
+        c->shape_gen++;
+    g.cols_y = t.cols_y;
+    g.cols_z = t.cols_z;
+    g.cols_iy = t.cols_iy;
+    g.pairs_ix = t.pairs_ix;
+    g.spread_wgs = t.spread_wgs;
+    c->graph = t.graph != 0;
+}
+
+// Coordinate descent over the launch shapes: each setting in turn takes the
+// candidate whose evaluation of these rotations is fastest (the least of
+// `reps` timed runs after one untimed run), the others held.  Results do not
+// depend on the launch shape, so only time is compared.
+corr_tuning autotune(corr_ctx* c, const double* q, int64_t n_rot, float* scores, float* pv, int64_t* pi,
+                     int reps) {
+    if (n_rot < 1) fail(CORR_EINVAL, "autotuning needs n_rot >= 1");
+    if (reps < 1 || reps > 100) fail(CORR_EINVAL, "reps = %d; allowed 1..100", reps);
+    if ((pv == nullptr) != (pi == nullptr)) fail(CORR_EINVAL, "peak_val and peak_idx must both be set or both be NULL");
+    validate_quats(q, n_rot);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    const bool prof = c->profiling;
+    c->profiling = false;
+    const corr_tuning start = get_tuning(c);
+    try {
+        auto timed = [&](const corr_tuning& t) {
+            set_tuning(c, t);
+            eval_plain(c, q, n_rot, scores, pv, pi);  // untimed: first touch, graph capture
+            float best = INFINITY;
+            for (int r = 0; r < reps; ++r) {
+                hip_check(hipEventRecord(e0, c->stream), "hipEventRecord");
+                eval_plain(c, q, n_rot, scores, pv, pi);
+                hip_check(hipEventRecord(e1, c->stream), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                best = std::min(best, ms);
+            }
+            return best;
+        };
+        corr_tuning cur = start;
+        float cur_ms = timed(cur);
+        auto try_field = [&](int32_t corr_tuning::*field, const std::vector<int>& cands) {
+            for (int v : cands) {
+                if (v == cur.*field) continue;
+                corr_tuning t = cur;
+                t.*field = v;
+                const float ms = timed(t);
+                if (ms < cur_ms) {
+                    cur = t;
+                    cur_ms = ms;
+                }
+            }
+        };
+        if (c->own_ws) {
+            // rotations per pass: powers of two up to the rotations given,
+            // with the workspace under 8 GiB
+            const size_t per = ws_req(c).slot_bytes();
+            std::vector<int> sl;
+            for (int sv = 1; sv <= 256; sv *= 2)
+                if ((sv <= n_rot || sv / 2 < n_rot) && (size_t)sv * per <= ((size_t)8 << 30)) sl.push_back(sv);
+            try_field(&corr_tuning::slots, sl);
+        }
+        const int cus = cu_count(c);
+        try_field(&corr_tuning::spread_wgs, {cus, 2 * cus});
+        int32_t corr_tuning::*fields[4] = {&corr_tuning::cols_y, &corr_tuning::cols_z, &corr_tuning::cols_iy,
+                                           &corr_tuning::pairs_ix};
+        for (int p = 0; p < 4; ++p) {
+            int ch[3];
+            const int k = corr::col_choices(c->g.m, p, ch);
+            try_field(fields[p], std::vector<int>(ch, ch + k));
+        }
+        set_tuning(c, cur);
+    } catch (...) {
+        (void)hipStreamSynchronize(c->stream);
+        try {
+            set_tuning(c, start);
+        } catch (...) {
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c->profiling = prof;
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->profiling = prof;
+    return get_tuning(c);
+}
+
 }  // namespace
 
 extern "C" {
+
+int corr_get_tuning(const corr_ctx* c, corr_tuning* out) {
+    if (!c || !out) {
+        g_thread_error = "corr_get_tuning: NULL argument";
+        return CORR_EINVAL;
+    }
+    return guarded(const_cast<corr_ctx*>(c), [&] { *out = get_tuning(c); });
+}
+
+int corr_set_tuning(corr_ctx* c, const corr_tuning* t) {
+    if (!c) {
+        g_thread_error = "corr_set_tuning: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] {
+        if (!t) fail(CORR_EINVAL, "tuning is NULL");
+        set_tuning(c, *t);
+    });
+}
+
+int corr_tuning_choices(const corr_ctx* c, int32_t pass, int32_t* out3, int32_t* count) {
+    if (!c || !out3 || !count) {
+        g_thread_error = "corr_tuning_choices: NULL argument";
+        return CORR_EINVAL;
+    }
+    int ch[3];
+    const int k = (pass >= 0 && pass < 4) ? corr::col_choices(c->g.m, pass, ch) : 0;
+    if (k == 0) {
+        g_thread_error = "corr_tuning_choices: pass must be 0..3";
+        return CORR_EINVAL;
+    }
+    for (int i = 0; i < k; ++i) out3[i] = ch[i];
+    *count = k;
+    return CORR_OK;
+}
+
+int corr_autotune(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* scores_dev, float* peak_val_dev,
+                  int64_t* peak_idx_dev, int32_t reps, corr_tuning* out) {
+    if (!c) {
+        g_thread_error = "corr_autotune: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] {
+        const corr_tuning t = autotune(c, quat_wxyz, n_rot, scores_dev, peak_val_dev, peak_idx_dev, reps);
+        if (out) *out = t;
+    });
+}
 
 int corr_create(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t nB, const corr_grid* grid,
                 void* hip_stream, corr_ctx** out) {
@@ -934,7 +1271,7 @@ int corr_eval_slices(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, const 
         std::vector<const float2*> fas;
         for (const Slice& sl : c->slices) fas.push_back(sl.fa);
         if (fas.empty()) fas.push_back(c->fa);
-        eval_impl(c, quat_wxyz, n_rot, fas, o);
+        eval_entry(c, quat_wxyz, n_rot, fas, o);
     });
 }
 
@@ -1155,6 +1492,8 @@ struct corr_batch {
     hipStream_t stream = nullptr;
     std::vector<corr_ctx*> pairs;
     corr::Workspace ws;
+    bool graph = false;  // replay whole batch evaluations as one captured hipGraph
+    GraphState gs;
     std::string err = "no error";
 };
 
@@ -1204,21 +1543,49 @@ int corr_batch_eval(corr_batch* b, const double* quat_wxyz, const int64_t* rot_o
         if ((peak_val_dev == nullptr) != (peak_idx_dev == nullptr))
             fail(CORR_EINVAL, "peak_val_dev and peak_idx_dev must both be set or both be NULL");
         validate_quats(quat_wxyz, rot_offsets[np]);
-        int64_t packed = 0;
-        for (int p = 0; p < np; ++p) {
-            corr_ctx* c = b->pairs[p];
-            cur = c;
-            const int64_t r0 = rot_offsets[p], nr = rot_offsets[p + 1] - rot_offsets[p];
-            const int64_t n3 = (int64_t)c->g.n * c->g.n * c->g.n;
-            float* sc = nullptr;
-            if (scores_dev) sc = scores_dev + (score_offsets ? score_offsets[p] : packed);
-            packed += nr * n3;
-            eval_plain(c, quat_wxyz + 4 * r0, nr, sc, peak_val_dev ? peak_val_dev + r0 : nullptr,
-                       peak_idx_dev ? peak_idx_dev + r0 : nullptr);
+        // every pair's outputs; with a graph, its rotations come from dq
+        auto run = [&](const double* dq) {
+            int64_t packed = 0;
+            for (int p = 0; p < np; ++p) {
+                corr_ctx* c = b->pairs[p];
+                cur = c;
+                const int64_t r0 = rot_offsets[p], nr = rot_offsets[p + 1] - rot_offsets[p];
+                const int64_t n3 = (int64_t)c->g.n * c->g.n * c->g.n;
+                EvalOut o;
+                if (scores_dev) o.scores = scores_dev + (score_offsets ? score_offsets[p] : packed);
+                packed += nr * n3;
+                o.peak_val = peak_val_dev ? peak_val_dev + r0 : nullptr;
+                o.peak_idx = peak_idx_dev ? peak_idx_dev + r0 : nullptr;
+                eval_impl(c, dq ? nullptr : quat_wxyz + 4 * r0, nr, {c->fa}, o, dq ? dq + 4 * r0 : nullptr);
+            }
+        };
+        if (!b->graph || rot_offsets[np] == 0) {
+            run(nullptr);
+            return;
         }
+        const double* dq = graph_quats(b->gs, b->stream, quat_wxyz, rot_offsets[np]);
+        std::vector<uint64_t> key = {2, (uint64_t)(uintptr_t)scores_dev, (uint64_t)(uintptr_t)peak_val_dev,
+                                     (uint64_t)(uintptr_t)peak_idx_dev, score_offsets ? 1u : 0u};
+        for (int p = 0; p <= np; ++p) key.push_back((uint64_t)rot_offsets[p]);
+        if (score_offsets)
+            for (int p = 0; p < np; ++p) key.push_back((uint64_t)score_offsets[p]);
+        graph_launch(b->gs, b->stream, std::move(key), b->pairs, nullptr, [&] { run(dq); });
     });
     if (rc != CORR_OK) b->err = cur && cur->err != "no error" ? cur->err : g_thread_error;
     return rc;
+}
+
+int corr_batch_set_graph(corr_batch* b, int32_t enable) {
+    if (!b) {
+        g_thread_error = "corr_batch_set_graph: NULL batch";
+        return CORR_EINVAL;
+    }
+    if (enable != 0 && enable != 1) {
+        b->err = "corr_batch_set_graph: enable must be 0 or 1";
+        return CORR_EINVAL;
+    }
+    b->graph = enable != 0;
+    return CORR_OK;
 }
 
 int corr_batch_info(const corr_batch* b, int32_t pair, corr_info_t* out) {
@@ -1233,6 +1600,7 @@ int corr_batch_destroy(corr_batch* b) {
     if (!b) return CORR_OK;
     (void)hipStreamSynchronize(b->stream);
     for (corr_ctx* c : b->pairs) destroy_ctx(c);
+    b->gs.release();
     b->ws.release();
     delete b;
     return CORR_OK;

@@ -20,7 +20,17 @@ struct Geom {
     float inv_i0beta = 0.f;   // 1 / I0(beta): window normalised to 1 at its centre
     double inv_hf = 0.0;      // 1 / spreading-cell size
     int spread_wgs = 0;       // workgroups of the persistent spreading pass (two per CU)
+    // column batch of each column-FFT pass (0: the pass's default width; else
+    // the default, half of it or twice it, see col_choices): forward y, z
+    // passes, inverse y and slice products, inverse x (line pairs)
+    int cols_y = 0, cols_z = 0, cols_iy = 0, pairs_ix = 0;
 };
+
+// Widths a column pass may take at spreading-grid size m: out[0] is the
+// default, then the others (half and twice the default where the pass allows
+// them).  pass: 0 forward y, 1 z passes, 2 inverse y, 3 inverse x.  Returns
+// the count (1..3), 0 for an unsupported m or pass.
+int col_choices(int m, int pass, int out[3]);
 
 // Which parts of a rotation's spreading grid hold knots.  z row z is live iff
 // some knot's z-window reaches it, which the z-sorted bin starts tell directly;
@@ -109,6 +119,8 @@ hipError_t launch_product_ifft_z(const Geom& g, const float2* d_acc, int S, cons
 hipError_t launch_ifft_y(const Geom& g, const float2* d_in, int S, float2* d_out,
                          const float2* d_twn, hipStream_t st);
 int ifft_x_blocks(const Geom& g);
+// The most inverse-x blocks any allowed pairs_ix gives (workspace sizing).
+int ifft_x_blocks_max(const Geom& g);
 hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scores, unsigned* d_mask, float thr,
                          float* d_pval, int* d_pidx, int* d_pcnt, const float2* d_twn, hipStream_t st);
 // Per rotation: peak (d_peak_val, d_peak_idx; NULL: skipped) and obstacle count

@@ -826,6 +826,20 @@ __device__ __forceinline__ int kept_source(int o) {
     return (mo + M) & (M - 1);
 }
 
+// The widths of one column pass: the default D and, where they stay within
+// [LO, HI], D / 2 and 2 D (the kernels are instantiated for each).
+template <int D, int LO, int HI>
+struct Cols {
+    static constexpr int DEF = D, DN = D / 2 >= LO ? D / 2 : D, UP = 2 * D <= HI ? 2 * D : D;
+    static int list(int out[3]) {
+        int k = 0;
+        out[k++] = D;
+        if (DN != D) out[k++] = DN;
+        if (UP != D) out[k++] = UP;
+        return k;
+    }
+};
+
 template <int M>
 struct ColShape {
     static constexpr int N = M / 2, H = N / 2;
@@ -838,6 +852,12 @@ struct ColShape {
     static constexpr int YZB = 1;                              // z rows per y-pass workgroup
     static constexpr int ICOLS = cmin<H, 2048 / N>();         // inverse y pass
     static constexpr int XCOLS = cmin<N * N / 2, 2048 / N>(); // inverse x pass (line pairs)
+    // the widths the autotuner may choose from; the inverse x pass needs whole
+    // output loops, 2 XCOLS N a multiple of the workgroup size
+    using Y = Cols<COLS, 1, H>;
+    using Z = Cols<ZCOLS, 1, H>;
+    using IY = Cols<ICOLS, 1, H>;
+    using IX = Cols<XCOLS, (128 / N > 1 ? 128 / N : 1), N * N / 2>;
 };
 
 // fft_cols (columns interleaved) with its first, radix-8 pass taken on values
@@ -874,12 +894,12 @@ __device__ __forceinline__ void fft_cols_regs(float2 (&v)[NBF][8], float2* a, co
 // slab = rotation * q + component.  A workgroup takes YZB z rows of one slab
 // and column block; dead z rows are skipped (their output is never read) and
 // rows of dead y tiles are zero.
-template <int M>
+template <int M, int COLS>
 __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ in, float2* __restrict__ out,
                                                     const float2* __restrict__ twm, int q,
                                                     const int* __restrict__ bin_start,
                                                     const unsigned char* __restrict__ tile_live, int64_t nk, int w) {
-    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::COLS, YZB = ColShape<M>::YZB;
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, YZB = ColShape<M>::YZB;
     constexpr int TY = SpreadShape<M>::TY, NT = M / TY;
     extern __shared__ float2 lds[];
     __shared__ unsigned char live[NT];
@@ -923,19 +943,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ i
 // Shared part of the z pass: transform each component's z-columns for one my
 // row and accumulate sum_c vtab[c][|m|^2] * G_c into per-thread registers
 // (thread t holds entries t + k*kThreads of the [mz][col] block).
-template <int M>
+template <int M, int COLS>
 struct ZAcc {
-    static constexpr int N = M / 2, COLS = ColShape<M>::ZCOLS;
+    static constexpr int N = M / 2;
     static constexpr int PER = (N * COLS + kThreads - 1) / kThreads;
 };
 
 // zlive[z] (LDS) tells which z rows the y pass wrote; the others are zero.
-template <int M>
+template <int M, int COLS>
 __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int s, int q, int iy, int c0,
                                              const float* __restrict__ vtab, int m2n, float2* a,
                                              const float2* twl, const unsigned char* zlive,
-                                             float2 (&acc)[ZAcc<M>::PER]) {
-    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ZCOLS, PER = ZAcc<M>::PER;
+                                             float2 (&acc)[ZAcc<M, COLS>::PER]) {
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, PER = ZAcc<M, COLS>::PER;
     using P = RegPass<M, COLS>;
     const int my = iy < N / 2 ? iy : iy - N;
 #pragma unroll
@@ -1003,13 +1023,13 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
 // a2 (z) + a3 for the fixed shape or a single spectrum: F = D(m) * acc; with
 // deconv NULL the plain sums acc (the rotated shape's z pass shared by several
 // products, each finished by k_product_ifft_z).
-template <int M>
+template <int M, int COLS>
 __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __restrict__ in, int q,
                                                              const float* __restrict__ vtab, int m2n,
                                                              const double* __restrict__ deconv,
                                                              float2* __restrict__ spec, const float2* __restrict__ twm,
                                                              const int* __restrict__ bin_start, int64_t nk, int w) {
-    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ZCOLS, PER = ZAcc<M>::PER;
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, PER = ZAcc<M, COLS>::PER;
     extern __shared__ float2 lds[];
     __shared__ unsigned char zlive[M];
     float2* a = lds;
@@ -1025,7 +1045,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __res
     for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, t);
     __syncthreads();
     float2 acc[PER];
-    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, twl, zlive, acc);
+    z_accumulate<M, COLS>(in, s, q, iy, c0, vtab, m2n, a, twl, zlive, acc);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int t = threadIdx.x + k * kThreads;
@@ -1053,7 +1073,7 @@ __device__ __forceinline__ float2 shift_factor(const double2* __restrict__ phase
 // a2 (z) + a3 + a4 + inverse z for the rotated shape:
 //   S = F_A * conj(acc) * prod_d D(m_d) exp(i k_d o_d) / L   (factor in FP64),
 // then the unnormalised inverse transform along z.
-template <int M>
+template <int M, int COLS>
 __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __restrict__ in, int q,
                                                             const float* __restrict__ vtab, int m2n,
                                                             const double2* __restrict__ phase,
@@ -1061,7 +1081,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
                                                             const float2* __restrict__ twm,
                                                             const float2* __restrict__ twn,
                                                             const int* __restrict__ bin_start, int64_t nk, int w) {
-    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ZCOLS, PER = ZAcc<M>::PER;
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, PER = ZAcc<M, COLS>::PER;
     extern __shared__ float2 lds[];
     __shared__ unsigned char zlive[M];
     float2* a = lds;
@@ -1079,7 +1099,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
     for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, t);
     __syncthreads();
     float2 acc[PER];
-    z_accumulate<M>(in, s, q, iy, c0, vtab, m2n, a, twl, zlive, acc);
+    z_accumulate<M, COLS>(in, s, q, iy, c0, vtab, m2n, a, twl, zlive, acc);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int t = threadIdx.x + k * kThreads;
@@ -1097,12 +1117,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
 // a4 + inverse z for one more fixed spectrum, from the rotated shape's z sums
 // acc [s][mz][my][mx] (k_fft_z_spectrum without deconvolution): the same
 // product and transform as k_fft_z_product, in the same order of operations.
-template <int M>
+template <int M, int COLS>
 __global__ __launch_bounds__(kThreads) void k_product_ifft_z(const float2* __restrict__ accs,
                                                              const double2* __restrict__ phase,
                                                              const float2* __restrict__ fa, float2* __restrict__ out,
                                                              const float2* __restrict__ twn) {
-    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ICOLS;
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H;
     extern __shared__ float2 lds[];
     float2* a = lds;
     float2* twnl = a + N * COLS;
@@ -1137,9 +1157,9 @@ __global__ __launch_bounds__(kThreads) void k_product_ifft_z(const float2* __res
 
 // a5: inverse y over [s][z][my][mx] -> [s][z][y][mx].  A workgroup reads all of
 // its columns before it writes them back, so in == out (in place) is allowed.
-template <int M>
+template <int M, int COLS>
 __global__ __launch_bounds__(kThreads) void k_ifft_y(const float2* in, float2* out, const float2* __restrict__ twn) {
-    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::ICOLS;
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H;
     extern __shared__ float2 lds[];
     float2* a = lds;
     float2* twl = a + N * COLS;
@@ -1170,12 +1190,12 @@ __global__ __launch_bounds__(kThreads) void k_ifft_y(const float2* in, float2* o
 // reduces its scores to (max, lowest index of the max) and, for the obstacle
 // predicate (Sec. 3.1 eq. eq_obs), writes the bits score > thr of its points
 // (bit b of word w: linear index 32 w + b) and counts them.
-template <int M>
+template <int M, int COLS>
 __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ in, float* __restrict__ scores,
                                                      unsigned* __restrict__ mask, float thr,
                                                      float* __restrict__ pval, int* __restrict__ pidx,
                                                      int* __restrict__ pcnt, const float2* __restrict__ twn) {
-    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, COLS = ColShape<M>::XCOLS, SC = N + 1;
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H, SC = N + 1;
     // whole iterations of the output loop: every lane takes part in each ballot,
     // and a wave's 64 points are two whole mask words
     static_assert((2 * COLS * N) % kThreads == 0, "output loop must be whole");
@@ -1467,15 +1487,42 @@ namespace {
 // Call f(std::integral_constant<int, M>) for the spreading-grid size m.
 template <class F>
 hipError_t with_m(int m, F&& f) {
+    // f may return the error of a dispatch of its own (with_cols)
+    auto call = [&](auto mc) -> hipError_t {
+        if constexpr (std::is_same_v<decltype(f(mc)), hipError_t>) {
+            return f(mc);
+        } else {
+            f(mc);
+            return hipSuccess;
+        }
+    };
+    hipError_t e;
     switch (m) {
-        case 32: f(std::integral_constant<int, 32>{}); break;
-        case 64: f(std::integral_constant<int, 64>{}); break;
-        case 128: f(std::integral_constant<int, 128>{}); break;
-        case 256: f(std::integral_constant<int, 256>{}); break;
-        case 512: f(std::integral_constant<int, 512>{}); break;
+        case 32: e = call(std::integral_constant<int, 32>{}); break;
+        case 64: e = call(std::integral_constant<int, 64>{}); break;
+        case 128: e = call(std::integral_constant<int, 128>{}); break;
+        case 256: e = call(std::integral_constant<int, 256>{}); break;
+        case 512: e = call(std::integral_constant<int, 512>{}); break;
         default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
     return hipGetLastError();
+}
+
+// Call f(std::integral_constant<int, COLS>) for the width `want` (0: default)
+// of a pass whose widths are C; an unlisted width is an error.
+template <class C, class F>
+hipError_t with_cols(int want, F&& f) {
+    if (want == 0 || want == C::DEF) {
+        f(std::integral_constant<int, C::DEF>{});
+    } else if (want == C::DN) {
+        f(std::integral_constant<int, C::DN>{});
+    } else if (want == C::UP) {
+        f(std::integral_constant<int, C::UP>{});
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipSuccess;
 }
 
 // two spreading workgroups per CU: dynamic LDS plus the kernel's static arrays
@@ -1562,9 +1609,10 @@ size_t max_lds_bytes(const Geom& g, int qmax) {
         constexpr int N = M / 2;
         using C = ColShape<M>;
         need = std::max(need, spread_lds_t<M>(g.w));
-        need = std::max(need, sizeof(float2) * ((size_t)M * C::COLS + M + N));
-        need = std::max(need, sizeof(float2) * ((size_t)N * C::ICOLS + N));
-        need = std::max(need, sizeof(float2) * ((size_t)C::XCOLS * (N + 1) + N) + 12 * kThreads);
+        // the widest width of each pass
+        need = std::max(need, sizeof(float2) * ((size_t)M * std::max(C::Y::UP, C::Z::UP) + M + N));
+        need = std::max(need, sizeof(float2) * ((size_t)N * C::IY::UP + N));
+        need = std::max(need, sizeof(float2) * ((size_t)C::IX::UP * (N + 1) + N) + 12 * kThreads);
     });
     return need;
 }
@@ -1598,9 +1646,12 @@ hipError_t launch_fft_y(const Geom& g, int S, int q, const Occupancy& occ, const
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
-        hipLaunchKernelGGL(k_fft_y<M>, dim3(C::H / C::COLS, M / C::YZB, S * q), dim3(kThreads),
-                           sizeof(float2) * ((size_t)M * C::COLS + M), st, d_in, d_out, d_twm, q, occ.bin_start,
-                           occ.tile_live, occ.nk, g.w);
+        return with_cols<typename C::Y>(g.cols_y, [&](auto cc) {
+            constexpr int COLS = decltype(cc)::value;
+            hipLaunchKernelGGL((k_fft_y<M, COLS>), dim3(C::H / COLS, M / C::YZB, S * q), dim3(kThreads),
+                               sizeof(float2) * ((size_t)M * COLS + M), st, d_in, d_out, d_twm, q, occ.bin_start,
+                               occ.tile_live, occ.nk, g.w);
+        });
     });
 }
 
@@ -1610,9 +1661,12 @@ hipError_t launch_fft_z_spectrum(const Geom& g, const float2* d_in, int S, int q
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
-        hipLaunchKernelGGL(k_fft_z_spectrum<M>, dim3(C::H / C::ZCOLS, C::N, S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)M * C::ZCOLS + M), st, d_in, q, d_vtab, g.m2n, d_deconv,
-                           d_spec, d_twm, occ.bin_start, occ.nk, g.w);
+        return with_cols<typename C::Z>(g.cols_z, [&](auto cc) {
+            constexpr int COLS = decltype(cc)::value;
+            hipLaunchKernelGGL((k_fft_z_spectrum<M, COLS>), dim3(C::H / COLS, C::N, S), dim3(kThreads),
+                               sizeof(float2) * ((size_t)M * COLS + M), st, d_in, q, d_vtab, g.m2n, d_deconv,
+                               d_spec, d_twm, occ.bin_start, occ.nk, g.w);
+        });
     });
 }
 
@@ -1622,9 +1676,12 @@ hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q,
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
-        hipLaunchKernelGGL(k_fft_z_product<M>, dim3(C::H / C::ZCOLS, C::N, S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)M * C::ZCOLS + M + C::N), st, d_in, q, d_vtab, g.m2n,
-                           d_phase, d_fa, d_out, d_twm, d_twn, occ.bin_start, occ.nk, g.w);
+        return with_cols<typename C::Z>(g.cols_z, [&](auto cc) {
+            constexpr int COLS = decltype(cc)::value;
+            hipLaunchKernelGGL((k_fft_z_product<M, COLS>), dim3(C::H / COLS, C::N, S), dim3(kThreads),
+                               sizeof(float2) * ((size_t)M * COLS + M + C::N), st, d_in, q, d_vtab, g.m2n,
+                               d_phase, d_fa, d_out, d_twm, d_twn, occ.bin_start, occ.nk, g.w);
+        });
     });
 }
 
@@ -1633,8 +1690,11 @@ hipError_t launch_product_ifft_z(const Geom& g, const float2* d_acc, int S, cons
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
-        hipLaunchKernelGGL(k_product_ifft_z<M>, dim3(C::H / C::ICOLS, C::N, S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)C::N * C::ICOLS + C::N), st, d_acc, d_phase, d_fa, d_out, d_twn);
+        return with_cols<typename C::IY>(g.cols_iy, [&](auto cc) {
+            constexpr int COLS = decltype(cc)::value;
+            hipLaunchKernelGGL((k_product_ifft_z<M, COLS>), dim3(C::H / COLS, C::N, S), dim3(kThreads),
+                               sizeof(float2) * ((size_t)C::N * COLS + C::N), st, d_acc, d_phase, d_fa, d_out, d_twn);
+        });
     });
 }
 
@@ -1643,8 +1703,11 @@ hipError_t launch_ifft_y(const Geom& g, const float2* d_in, int S, float2* d_out
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
-        hipLaunchKernelGGL(k_ifft_y<M>, dim3(C::H / C::ICOLS, C::N, S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)C::N * C::ICOLS + C::N), st, d_in, d_out, d_twn);
+        return with_cols<typename C::IY>(g.cols_iy, [&](auto cc) {
+            constexpr int COLS = decltype(cc)::value;
+            hipLaunchKernelGGL((k_ifft_y<M, COLS>), dim3(C::H / COLS, C::N, S), dim3(kThreads),
+                               sizeof(float2) * ((size_t)C::N * COLS + C::N), st, d_in, d_out, d_twn);
+        });
     });
 }
 
@@ -1653,9 +1716,36 @@ int ifft_x_blocks(const Geom& g) {
     (void)with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
-        nb = C::N * C::N / (2 * C::XCOLS);
+        const int px = g.pairs_ix == 0 ? C::XCOLS : g.pairs_ix;
+        nb = C::N * C::N / (2 * px);
     });
     return nb;
+}
+
+int ifft_x_blocks_max(const Geom& g) {
+    int nb = 0;
+    (void)with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        using C = ColShape<M>;
+        nb = C::N * C::N / (2 * C::IX::DN);
+    });
+    return nb;
+}
+
+int col_choices(int m, int pass, int out[3]) {
+    int k = 0;
+    (void)with_m(m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        using C = ColShape<M>;
+        switch (pass) {
+            case 0: k = C::Y::list(out); break;
+            case 1: k = C::Z::list(out); break;
+            case 2: k = C::IY::list(out); break;
+            case 3: k = C::IX::list(out); break;
+            default: k = 0;
+        }
+    });
+    return k;
 }
 
 hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scores, unsigned* d_mask, float thr,
@@ -1663,9 +1753,12 @@ hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scor
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         using C = ColShape<M>;
-        hipLaunchKernelGGL(k_ifft_x<M>, dim3(C::N * C::N / (2 * C::XCOLS), S), dim3(kThreads),
-                           sizeof(float2) * ((size_t)C::XCOLS * (C::N + 1) + C::N), st, d_in, d_scores, d_mask,
-                           thr, d_pval, d_pidx, d_pcnt, d_twn);
+        return with_cols<typename C::IX>(g.pairs_ix, [&](auto cc) {
+            constexpr int COLS = decltype(cc)::value;
+            hipLaunchKernelGGL((k_ifft_x<M, COLS>), dim3(C::N * C::N / (2 * COLS), S), dim3(kThreads),
+                               sizeof(float2) * ((size_t)COLS * (C::N + 1) + C::N), st, d_in, d_scores, d_mask,
+                               thr, d_pval, d_pidx, d_pcnt, d_twn);
+        });
     });
 }
 

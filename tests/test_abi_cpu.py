@@ -118,6 +118,14 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.corr_info(None, None) == pkg.CORR_EINVAL
     assert lib.corr_destroy(None) == pkg.CORR_OK
     assert "NULL" in pkg.corr_last_error(None)
+    t = pkg.corr_tuning()
+    cnt = ctypes.c_int32()
+    out3 = (ctypes.c_int32 * 3)()
+    assert lib.corr_get_tuning(None, ctypes.byref(t)) == pkg.CORR_EINVAL
+    assert lib.corr_set_tuning(None, ctypes.byref(t)) == pkg.CORR_EINVAL
+    assert lib.corr_tuning_choices(None, 0, out3, ctypes.byref(cnt)) == pkg.CORR_EINVAL
+    assert lib.corr_autotune(None, None, 1, None, None, None, 3, None) == pkg.CORR_EINVAL
+    assert pkg._batch_lib().corr_batch_set_graph(None, 1) == pkg.CORR_EINVAL
 
 
 def test_prop_rejects_bad_arguments(lib):
