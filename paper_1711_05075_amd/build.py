@@ -22,6 +22,10 @@ ARCH = "gfx950"
 # packed FP32 instructions stay off: hipcc may otherwise form v_pk_* float ops
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
+# the correlation kernels contract no multiply-add on their own: their fused
+# operations are written out, so results are bitwise the same for every launch
+# shape the autotuner may pick
+PER_FILE = {"corr_kernels.hip": ["-ffp-contract=off"]}
 
 
 def _hipcc() -> str:
@@ -46,8 +50,8 @@ def build_library(verbose: bool = False) -> str:
     for src, lang in (("corr_kernels.hip", "hip"), ("corr_host.cpp", "hip"), ("prop_kernels.hip", "hip"),
                       ("prop_host.cpp", "hip")):
         obj = os.path.join(bdir, src + ".o")
-        cmds.append([hipcc, "-x", lang, "--offload-arch=" + ARCH, *COMMON, *DEVICE_FLAGS, "-c",
-                     os.path.join(CSRC, src), "-o", obj])
+        cmds.append([hipcc, "-x", lang, "--offload-arch=" + ARCH, *COMMON, *DEVICE_FLAGS, *PER_FILE.get(src, []),
+                     "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     # the four translation units compile side by side
     with ThreadPoolExecutor(max_workers=len(cmds)) as pool:

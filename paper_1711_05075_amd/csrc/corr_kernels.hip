@@ -31,8 +31,12 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// This file is built without floating-point contraction: every fused
+// multiply-add is written out (fmaf), so the arithmetic and its rounding are
+// fixed by the source and do not depend on how a kernel is instantiated
+// (column batch, launch shape) or scheduled.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -1011,8 +1015,8 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
                 const int t = threadIdx.x + k * kThreads;
                 const int o = t / COLS, cc = t % COLS;
                 const float2 g = a[kept_source<N, M>(o) * COLS + cc];
-                acc[k].x += vcur[k] * g.x;
-                acc[k].y += vcur[k] * g.y;
+                acc[k].x = fmaf(vcur[k], g.x, acc[k].x);
+                acc[k].y = fmaf(vcur[k], g.y, acc[k].y);
             }
             vcur[k] = vnxt[k];
         }
