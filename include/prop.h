@@ -8,12 +8,18 @@
  * correlation whose peaks it learns is the score of Behandish & Ilies (CAD
  * 2016), Sec. 3.1 eq. eq_relg_0, evaluated by the Fourier route of Sec. 3.2.
  *
- * Network: inputs x = (q (4), descriptor of A (64), descriptor of B (64)),
- * zero-padded to 160; layers 160 -> 256 -> 256 -> 256 -> 1 with ReLU between.
- * q is the unit rotation quaternion (w, x, y, z) with w >= 0.  A descriptor is
- * the histogram of ball volume (weight * r^3) over the distance of each centre
- * from the volume-weighted centroid, 64 bins of width 1/64 on [0, 1] (farther
- * centres in the last bin), normalised to sum 1.
+ * Network: layers 160 -> 256 -> 256 -> 256 -> 1 with ReLU between.  Inputs
+ * (155 used, zero-padded to 160):
+ *   x[0..8]     the rotation matrix R(q) of the quaternion, row-major (the same
+ *               for q and -q, and continuous over all rotations, which a
+ *               canonical quaternion with w >= 0 is not across w = 0);
+ *   x[9..17]    sin(pi R_e) and x[18..26] cos(pi R_e) of each entry (a fixed
+ *               Fourier feature map of the rotation);
+ *   x[27..90]   64 * descriptor of A, x[91..154] 64 * descriptor of B (scaled
+ *               by the bin count so that an entry is 1 on average).
+ * A descriptor is the histogram of ball volume (weight * r^3) over the
+ * distance of each centre from the volume-weighted centroid, 64 bins of width
+ * 1/64 on [0, 1] (farther centres in the last bin), normalised to sum 1.
  *
  * Arithmetic: the layer products run on the matrix cores with bfloat16 weights
  * and bfloat16 layer inputs, accumulating in FP32 (forward and backward);
@@ -50,8 +56,8 @@ int prop_create(int32_t batch, uint64_t seed, void* hip_stream, prop_ctx** out);
 /* Descriptor of a ball set (host corr_ball[n], n >= 1) into desc_dev[64] (device float). */
 int prop_descriptor(prop_ctx* p, const corr_ball* balls, int64_t n, float* desc_dev);
 
-/* Network inputs X_dev[n][160] (device float) for n quaternions (host double
- * [n][4], normalised and canonicalised here) and two device descriptors. */
+/* Network inputs X_dev[n][160] (device float, layout above) for n quaternions
+ * (host double [n][4], any non-zero norm) and two device descriptors. */
 int prop_features(prop_ctx* p, const double* quat_wxyz, int64_t n, const float* desc_a_dev,
                   const float* desc_b_dev, float* X_dev);
 

@@ -2,8 +2,9 @@
 
 The network maps a rotation quaternion and two 64-bin radial shape descriptors
 to a predicted peak score: four linear layers 160 -> 256 -> 256 -> 256 -> 1 with
-ReLU between them (input: q (4) + descriptor of A (64) + descriptor of B (64),
-zero-padded to 160).  On the GPU the weights and the inputs of every layer are
+ReLU between them.  Input: the quaternion's rotation matrix R (9), sin(pi R) and
+cos(pi R) entrywise (9 + 9), 64 x descriptor of A (64), 64 x descriptor of B
+(64), zero-padded to 160.  On the GPU the weights and the inputs of every layer are
 rounded to bfloat16 and the products accumulate in FP32; with ``quant=True`` this
 reference applies the same roundings and then computes in FP64, so the two can
 be compared at the size of FP32 accumulation error.
@@ -16,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 DIMS = (160, 256, 256, 256, 1)
-IN_USED = 132
+IN_USED = 155
 BINS = 64
 
 
@@ -114,14 +115,29 @@ def descriptor(balls, bins: int = BINS) -> np.ndarray:
     return h / h.sum()
 
 
+def rotation_matrix(q) -> np.ndarray:
+    """R(q) of a quaternion (w, x, y, z), Hamilton convention: the matrix of
+    v -> q v q* for the normalised q, i.e. the rotation by angle 2 acos(w)
+    about (x, y, z); q and -q give the same matrix."""
+    q = np.asarray(q, dtype=np.float64)
+    q = q / np.linalg.norm(q)
+    w, v = q[0], q[1:]
+    # Rodrigues form: R = (w^2 - |v|^2) I + 2 v v^T + 2 w [v]_x
+    vx = np.array([[0.0, -v[2], v[1]], [v[2], 0.0, -v[0]], [-v[1], v[0], 0.0]])
+    return (w * w - v @ v) * np.eye(3) + 2.0 * np.outer(v, v) + 2.0 * w * vx
+
+
 def features(quats, desc_a, desc_b) -> np.ndarray:
-    """Network inputs: quaternion with w >= 0 (q and -q are the same rotation),
-    both descriptors, zero padding to 160."""
+    """Network inputs: the rotation matrix of each quaternion (row-major, the
+    same for q and -q), sin and cos of pi times each entry, both descriptors
+    times the bin count, zero padding to 160."""
     q = np.atleast_2d(np.asarray(quats, dtype=np.float64))
-    q = q / np.linalg.norm(q, axis=1, keepdims=True)
-    q = np.where(q[:, :1] < 0, -q, q)
     X = np.zeros((len(q), DIMS[0]))
-    X[:, :4] = q
-    X[:, 4:4 + BINS] = desc_a
-    X[:, 4 + BINS:4 + 2 * BINS] = desc_b
+    for i in range(len(q)):
+        R = rotation_matrix(q[i]).reshape(-1)
+        X[i, 0:9] = R
+        X[i, 9:18] = np.sin(np.pi * R)
+        X[i, 18:27] = np.cos(np.pi * R)
+    X[:, 27:27 + BINS] = BINS * np.asarray(desc_a, dtype=np.float64)
+    X[:, 27 + BINS:27 + 2 * BINS] = BINS * np.asarray(desc_b, dtype=np.float64)
     return X

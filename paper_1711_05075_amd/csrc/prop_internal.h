@@ -10,6 +10,7 @@ namespace prop {
 constexpr int kIn = 160;
 constexpr int kHidden = 256;
 constexpr int kBins = 64;
+constexpr int kRot = 9;  // rotation-matrix entries; the inputs hold R, sin(pi R), cos(pi R)
 constexpr int kRankMax = 8192;
 
 constexpr int kEpiHidden = 0;  // z = acc + bias -> z (f32), relu(z) -> bf16

@@ -218,15 +218,31 @@ __global__ __launch_bounds__(kT) void k_features(const double* __restrict__ q, i
     const int64_t r = idx / kIn;
     const int k = (int)(idx % kIn);
     float v = 0.f;
-    if (k < 4) {
+    if (k < 3 * kRot) {
+        // entry e of R(q), built in FP64 from the normalised quaternion (the same
+        // matrix for q and -q), then R_e, sin(pi R_e) or cos(pi R_e)
         const double* qq = q + 4 * r;
-        const double nn = sqrt(qq[0] * qq[0] + qq[1] * qq[1] + qq[2] * qq[2] + qq[3] * qq[3]);
-        const double sgn = qq[0] < 0 ? -1.0 : 1.0;
-        v = (float)(sgn * qq[k] / nn);
-    } else if (k < 4 + kBins) {
-        v = da[k - 4];
-    } else if (k < 4 + 2 * kBins) {
-        v = db[k - 4 - kBins];
+        const double nn = qq[0] * qq[0] + qq[1] * qq[1] + qq[2] * qq[2] + qq[3] * qq[3];
+        const double w = qq[0], x = qq[1], y = qq[2], z = qq[3], s = 2.0 / nn;
+        const int e = k % kRot;
+        double m;
+        switch (e) {
+            case 0: m = 1.0 - s * (y * y + z * z); break;
+            case 1: m = s * (x * y - w * z); break;
+            case 2: m = s * (x * z + w * y); break;
+            case 3: m = s * (x * y + w * z); break;
+            case 4: m = 1.0 - s * (x * x + z * z); break;
+            case 5: m = s * (y * z - w * x); break;
+            case 6: m = s * (x * z - w * y); break;
+            case 7: m = s * (y * z + w * x); break;
+            default: m = 1.0 - s * (x * x + y * y); break;
+        }
+        const int part = k / kRot;
+        v = (float)(part == 0 ? m : part == 1 ? sin(M_PI * m) : cos(M_PI * m));
+    } else if (k < 3 * kRot + kBins) {
+        v = (float)kBins * da[k - 3 * kRot];
+    } else if (k < 3 * kRot + 2 * kBins) {
+        v = (float)kBins * db[k - 3 * kRot - kBins];
     }
     X[idx] = v;
 }

@@ -78,7 +78,8 @@ def test_descriptor_and_features_match_reference(pkg):
     q = synth.random_quaternions(50, 9)
     X = p.features(q, da, db).cpu().numpy()
     ref = mlp.features(q, da.cpu().numpy().astype(np.float64), db.cpu().numpy().astype(np.float64))
-    np.testing.assert_allclose(X, ref, atol=1e-7)
+    # one FP64 -> FP32 rounding per input
+    np.testing.assert_allclose(X, ref, rtol=1.2e-7, atol=1e-7)
     p.close()
 
 

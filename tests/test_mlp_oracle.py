@@ -73,9 +73,44 @@ def test_descriptor_invariants():
     assert one[0] == 1.0
 
 
-def test_features_canonical_quaternion():
-    q = np.array([[-0.5, 0.5, -0.5, 0.5], [0.6, 0.8, 0, 0]])
-    X = mlp.features(q, np.full(64, 1 / 64), np.zeros(64))
-    assert X.shape == (2, 160)
-    np.testing.assert_allclose(X[0, :4], [0.5, -0.5, 0.5, -0.5])
-    assert np.all(X[:, 132:] == 0)
+def _hamilton(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def test_rotation_matrix_is_the_quaternion_rotation():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        q1, q2 = rng.standard_normal(4), rng.standard_normal(4)
+        R = mlp.rotation_matrix(q1)
+        np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-14)
+        assert abs(np.linalg.det(R) - 1) < 1e-14
+        np.testing.assert_allclose(mlp.rotation_matrix(-q1), R, atol=1e-15)
+        # a homomorphism: the product of quaternions is the product of rotations
+        np.testing.assert_allclose(mlp.rotation_matrix(_hamilton(q1, q2)), R @ mlp.rotation_matrix(q2), atol=1e-13)
+        # R v equals the quaternion sandwich q (0, v) q*
+        qn = q1 / np.linalg.norm(q1)
+        v = rng.standard_normal(3)
+        conj = qn * np.array([1, -1, -1, -1])
+        np.testing.assert_allclose(_hamilton(_hamilton(qn, np.r_[0.0, v]), conj)[1:], R @ v, atol=1e-13)
+    # a quarter turn about z takes x to y
+    h = np.sqrt(0.5)
+    np.testing.assert_allclose(mlp.rotation_matrix([h, 0, 0, h]) @ [1, 0, 0], [0, 1, 0], atol=1e-15)
+
+
+def test_features_layout():
+    q = np.array([[-0.5, 0.5, -0.5, 0.5], [0.6, 0.8, 0, 0], [2.0, 0, 0, 0]])
+    da = np.arange(64) / np.arange(64).sum()
+    X = mlp.features(q, da, np.zeros(64))
+    assert X.shape == (3, 160)
+    # q and -q: the same inputs
+    np.testing.assert_allclose(mlp.features(-q, da, np.zeros(64)), X, atol=1e-15)
+    # the identity (any positive scale): R = I, sin(pi R) = 0, cos(pi R) = -1 on the diagonal, 1 off it
+    np.testing.assert_allclose(X[2, 0:9], np.eye(3).reshape(-1), atol=1e-15)
+    np.testing.assert_allclose(X[2, 9:18], 0, atol=1e-15)
+    np.testing.assert_allclose(X[2, 18:27], np.where(np.eye(3).reshape(-1) > 0, -1.0, 1.0), atol=1e-15)
+    np.testing.assert_allclose(X[:, 9:18] ** 2 + X[:, 18:27] ** 2, 1.0, atol=1e-14)
+    np.testing.assert_allclose(X[0, 27:91], 64 * da, atol=1e-15)
+    assert np.all(X[:, 91:155] == 0) and np.all(X[:, mlp.IN_USED:] == 0)
