@@ -95,14 +95,16 @@ def test_rank_is_sorted_predictions(pkg):
 
 
 def test_training_fits_a_smooth_target(pkg):
-    # a smooth function of the rotation: training must cut the loss well down
+    # a smooth function of the rotation (of R(q), so equal for q and -q):
+    # training must cut the loss well down
     _say("case: training on 8192 samples, 30 epochs")
     p = pkg.Proposer(batch=256, seed=13)
     q = synth.random_quaternions(8192, 41, canonical=True)
     da = mlp.descriptor(synth.mixture_balls(300, 1))
     db = mlp.descriptor(synth.mixture_balls(300, 2))
     X = mlp.features(q, da, db)
-    y = np.cos(3 * q[:, 1]) * np.sin(2 * q[:, 2]) + 0.5 * q[:, 3] ** 2
+    R = np.array([mlp.rotation_matrix(v) for v in q])
+    y = np.cos(3 * R[:, 0, 1]) * np.sin(2 * R[:, 1, 2]) + 0.5 * R[:, 2, 0] ** 2
     Xt = torch.tensor(X, dtype=torch.float32, device="cuda")
     yt = torch.tensor(y, dtype=torch.float32, device="cuda")
     losses = p.train(Xt, yt, 30, 1e-3)
