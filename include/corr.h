@@ -109,7 +109,13 @@ int corr_create(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t nB,
                 const corr_grid* grid, void* hip_stream, corr_ctx** out);
 
 /* Recompute A's spectrum from the device-resident balls of A (the first stage
- * of corr_create, without any host transfer).  Asynchronous. */
+ * of corr_create, without any host transfer).  Asynchronous: the work is forked
+ * from the context's stream onto a private side stream of the library (default
+ * priority) with buffers of its own, so that it overlaps the rotated shape's
+ * first stages in the next corr_eval; every later call on the context joins it
+ * into the context's stream before it reads A's spectrum or the context's
+ * device state (corr_eval before its product stage).  Contexts of a batch
+ * compute it on the batch's stream. */
 int corr_prepare_a(corr_ctx* ctx);
 
 /*

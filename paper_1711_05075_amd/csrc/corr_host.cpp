@@ -430,6 +430,13 @@ struct corr_ctx {
     double* ident_q = nullptr;     // the identity quaternion (1, 0, 0, 0), device
     corr::Workspace* ws = nullptr;  // per-rotation buffers (shared by the pairs of a batch)
     bool own_ws = false;
+    // A's spectrum on a side stream (contexts with a workspace of their own):
+    // forked from `stream`, with buffers of its own, joined back by a_done
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, a_done = nullptr;
+    bool a_pending = false;          // a_done not yet waited for on `stream`
+    corr::Workspace* ws_a = nullptr;
+    corr::Workspace* last_ws = nullptr;  // buffers of the last spreading pass
     // the last spreading pass: rotations, components, knots
     int last_S = 0, last_q = 0;
     int64_t last_nk = 0;
@@ -575,6 +582,7 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
     c->last_S = S;
     c->last_q = q;
     c->last_nk = s.n;
+    c->last_ws = c->ws;
     stage(c, CORR_STAGE_ROTATE, "rotate", [&] {
         return corr::launch_rotate_bin(g, d_quats, S, s.pos, s.n, c->ws->cell, c->ws->kbw, c->ws->rank, c->ws->counts,
                                        c->ws->bin_start, c->ws->plan, c->stream);
@@ -604,7 +612,58 @@ void fixed_spectrum(corr_ctx* c, const Shape& a, float2* fa) {
     });
 }
 
-void prepare_a(corr_ctx* c) { fixed_spectrum(c, c->A, c->fa); }
+corr::WsReq ws_req(const corr_ctx* c);
+
+// Make the context's stream wait for a pending A spectrum.
+void join_a(corr_ctx* c) {
+    if (!c->a_pending) return;
+    hip_check(hipStreamWaitEvent(c->stream, c->a_done, 0), "hipStreamWaitEvent");
+    c->a_pending = false;
+}
+
+// A's spectrum into fa.  A context with a workspace of its own computes it on
+// a private side stream of default priority, forked from the context's stream
+// and with buffers of its own, so that it overlaps the rotated shape's stages
+// of the next evaluation; the evaluation joins it before the product, and
+// every other call that touches the context's device state joins it first.
+void prepare_a(corr_ctx* c) {
+    if (!c->own_ws) {
+        fixed_spectrum(c, c->A, c->fa);
+        return;
+    }
+    if (!c->side) {
+        hip_check(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "hipStreamCreate");
+        hip_check(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming), "hipEventCreate");
+        hip_check(hipEventCreateWithFlags(&c->a_done, hipEventDisableTiming), "hipEventCreate");
+    }
+    if (!c->ws_a) {
+        auto* w = new corr::Workspace();
+        try {
+            w->allocate(1, ws_req(c), c->stream);  // its counter clearing is on `stream`, before the fork
+        } catch (...) {
+            w->release();
+            delete w;
+            throw;
+        }
+        c->ws_a = w;
+    }
+    hip_check(hipEventRecord(c->fork_ev, c->stream), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(c->side, c->fork_ev, 0), "hipStreamWaitEvent");
+    struct Swap {
+        corr_ctx* c;
+        hipStream_t st;
+        corr::Workspace* ws;
+        ~Swap() {
+            c->stream = st;
+            c->ws = ws;
+        }
+    } swap{c, c->stream, c->ws};
+    c->stream = c->side;
+    c->ws = c->ws_a;
+    fixed_spectrum(c, c->A, c->fa);
+    hip_check(hipEventRecord(c->a_done, c->side), "hipEventRecord");
+    c->a_pending = true;
+}
 
 // host quaternions -> pinned staging -> device, S at a time
 void stage_quats(corr_ctx* c, const double* q, int S) {
@@ -774,6 +833,7 @@ void eval_impl(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, const std::v
                 return corr::launch_fft_z_spectrum(g, reinterpret_cast<float2*>(c->ws->buf0), S, c->B.ex.q,
                                                    occupancy(c, c->B), c->B.vtab, nullptr, zsums, c->twm, c->stream);
             });
+        join_a(c);  // F_A is read from here on
         for (size_t k = 0; k < fas.size(); ++k) {
             const size_t first = (size_t)k * n_rot + r0;  // this slice's first rotation of the batch
             stage(c, CORR_STAGE_FFT_Z_PRODUCT, "fft z product", [&] {
@@ -898,6 +958,7 @@ void eval_entry(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, const std::
     check_eval_args(n_rot, o);
     validate_quats(quat_wxyz, n_rot);
     if (n_rot == 0) return;
+    join_a(c);  // outside the capture: the graph waits on nothing it did not record
     const double* dq = graph_quats(c->gs, c->stream, quat_wxyz, n_rot);
     float thr_bits = o.thr;
     uint32_t tb;
@@ -920,6 +981,7 @@ void eval_plain(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* scor
 
 // Plan and compute the offset slices of A (corr_set_offsets).
 void set_offsets(corr_ctx* c, const double* offsets, int32_t n) {
+    join_a(c);
     if (c->flags & CORR_SC_SCORE)
         fail(CORR_EUNSUPPORTED, "offset slices with CORR_SC_SCORE: its kernel already offsets the balls");
     if (n < 0 || n > CORR_MAX_SLICES) fail(CORR_EINVAL, "n_offsets = %d; allowed 0..%d", n, CORR_MAX_SLICES);
@@ -996,6 +1058,7 @@ int guarded(corr_ctx* c, F&& body) {
 
 void destroy_ctx(corr_ctx* c) {
     if (!c) return;
+    if (c->side) (void)hipStreamSynchronize(c->side);
     (void)hipStreamSynchronize(c->stream);
     for (auto* g : {&c->q_modes, &c->q_part, &c->q_P, &c->q_t, &c->q_quat, &c->q_tpart})
         if (g->p) (void)hipFree(g->p);
@@ -1009,6 +1072,13 @@ void destroy_ctx(corr_ctx* c) {
         delete c->ws;
     }
     c->ws = nullptr;
+    if (c->ws_a) {
+        c->ws_a->release();
+        delete c->ws_a;
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->a_done) (void)hipEventDestroy(c->a_done);
+    if (c->side) (void)hipStreamDestroy(c->side);
     for (auto& mk : c->marks) {
         (void)hipEventDestroy(mk.a);
         (void)hipEventDestroy(mk.b);
@@ -1042,6 +1112,7 @@ corr_tuning get_tuning(const corr_ctx* c) {
 // Validate t against the context's choices; then apply it (the workspace is
 // reallocated, after the stream has drained, when the slot count changes).
 void set_tuning(corr_ctx* c, const corr_tuning& t) {
+    join_a(c);
     const int widths[4] = {t.cols_y, t.cols_z, t.cols_iy, t.pairs_ix};
     static const char* names[4] = {"cols_y", "cols_z", "cols_iy", "pairs_ix"};
     for (int p = 0; p < 4; ++p) {
@@ -1282,6 +1353,7 @@ int corr_spectrum(corr_ctx* c, int32_t which, const double* quat_wxyz, float* ou
     }
     return guarded(c, [&] {
         if (which != 0 && which != 1) fail(CORR_EINVAL, "which must be 0 (A) or 1 (B)");
+        join_a(c);
         if (!out_dev) fail(CORR_EINVAL, "out_dev is NULL");
         static const double ident[4] = {1, 0, 0, 0};
         const double* q = which == 0 ? ident : quat_wxyz;
@@ -1310,7 +1382,8 @@ int corr_info(const corr_ctx* c, corr_info_t* out) {
     out->n_a = c->A.n;
     out->n_b = c->B.n;
     out->batch = c->ws->slots;
-    out->workspace_bytes = (int64_t)(c->mem.bytes + (c->own_ws ? c->ws->mem.bytes : 0));
+    out->workspace_bytes =
+        (int64_t)(c->mem.bytes + (c->own_ws ? c->ws->mem.bytes : 0) + (c->ws_a ? c->ws_a->mem.bytes : 0));
     out->beta = c->g.beta;
     out->radius_err_a = c->A.ex.err;
     out->radius_err_b = c->B.ex.err;
@@ -1337,6 +1410,7 @@ int corr_profile_read(corr_ctx* c, double* ms, int64_t* launches, int32_t n_stag
             ms[i] = 0;
             launches[i] = 0;
         }
+        join_a(c);  // marks recorded on the side stream complete before a_done
         hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
         for (auto& mk : c->marks) {
             float t = 0;
@@ -1369,8 +1443,10 @@ int corr_pass_info(corr_ctx* c, corr_pass_t* out) {
         r.tiles = (int64_t)c->last_S * c->g.m * nty;
         if (r.tiles > 0 && r.knots > 0) {
             std::vector<unsigned char> live((size_t)r.tiles);
+            join_a(c);
             hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-            hip_check(hipMemcpy(live.data(), c->ws->tile_live, live.size(), hipMemcpyDeviceToHost), "tile flags D2H");
+            hip_check(hipMemcpy(live.data(), c->last_ws->tile_live, live.size(), hipMemcpyDeviceToHost),
+                      "tile flags D2H");
             for (int64_t row = 0; row < (int64_t)c->last_S * c->g.m; ++row) {
                 int64_t n = 0;
                 for (int t = 0; t < nty; ++t) n += live[(size_t)row * nty + t] != 0;
@@ -1441,6 +1517,7 @@ int corr_query(corr_ctx* c, const double* quat_wxyz, const double* t_host, int64
         validate_quats(quat_wxyz, 1);
         for (int64_t i = 0; i < 3 * n_t; ++i)
             if (!std::isfinite(t_host[i])) fail(CORR_EINVAL, "translation %lld is not finite", (long long)(i / 3));
+        join_a(c);  // F_A is read below
         const Geom& g = c->g;
         const int32_t full = 3 * (g.n / 2 - 1) * (g.n / 2 - 1);
         const int32_t r2 = std::min(mode_radius2, full);

@@ -232,3 +232,42 @@ def test_batch_graph_replays_match_the_eager_batch():
         torch.cuda.synchronize()
     _say("  4 replays bitwise equal")
     b.close()
+
+
+def test_side_stream_spectrum_of_a_is_joined_everywhere():
+    # corr_prepare_a runs on a side stream; every later call must see its result
+    import paper_1711_05075_amd as pkg
+    A, B, g = _pair(64, na=1500, nb=700, seed=17)
+    q = synth.random_quaternions(3, 3017)
+    _say("case: A's spectrum on the side stream, 1500+700 balls, n=64")
+    c = _corr(A, B, g)
+    out = _outs(3, 64)
+    ref = _eval(c, q, out)
+    spec_a = c.spectrum(0).clone()
+    t = np.array([[0.01, -0.02, 0.03], [0.0, 0.0, 0.0]])
+    qry_ref, _ = c.query(q[0], t, 100)
+    qry_ref = qry_ref.clone()
+    pkg.corr_profile(c.ctx, True)
+    for k in range(3):
+        c.prepare_a()
+        _same(_eval(c, q, out), ref, "eval after prepare_a %d" % k)
+    prof = pkg.corr_profile_read(c.ctx)
+    assert prof["spread_fft_x"][1] == 6  # three A passes and three B passes, all timed
+    pkg.corr_profile(c.ctx, False)
+    c.prepare_a()
+    info = c.pass_info()
+    assert info["knots"] == len(A) and info["rotations"] == 1 and info["live_tiles"] > 0
+    c.prepare_a()
+    assert torch.equal(c.spectrum(0), spec_a)
+    c.prepare_a()
+    got, _ = c.query(q[0], t, 100)
+    torch.cuda.synchronize()
+    assert torch.equal(got, qry_ref)
+    c.prepare_a()
+    c.set_tuning(graph=1)
+    _same(_eval(c, q, out), ref, "graph after prepare_a")
+    c.prepare_a()
+    _same(_eval(c, q, out), ref, "graph replay after prepare_a")
+    c.prepare_a()
+    c.close()  # destroy with the side stream's work still queued
+    _say("  evaluations, pass report, spectrum, query and graph replays after prepare_a: bitwise equal")
