@@ -392,6 +392,11 @@ def run_uneven(args, torch, pkg):
     def step():
         b.eval(quats, out=(s, pv, pi))
 
+    slots = {}
+    for p, n in enumerate(ns):
+        slots.setdefault(str(n), set()).add(int(b.info(p)["batch"]))
+    print("rotations per pass by grid size: %s" % {k: sorted(v) for k, v in slots.items()}, file=sys.stderr,
+          flush=True)
     rows = {"default": _timed(torch, step, args.warmup, args.steps)}
     b.set_graph(True)
     rows["graph"] = _timed(torch, step, args.warmup, args.steps)
@@ -419,6 +424,7 @@ def run_uneven(args, torch, pkg):
                                   "32 rotations each, one corr_batch_eval call (scores and peaks)",
                       "pairs_per_n": {str(n): ns.count(n) for n in (32, 64, 128)}, "correlations": nrot},
            "modes_ms": rows, "best_mode": best,
+           "rotations_per_pass_by_n": {k: sorted(v) for k, v in slots.items()},
            "e_rel_vs_fp64_worst": max((r["e_rel_rot0"] for r in per_pair), default=None),
            "oracle_seconds": time.perf_counter() - t0,
            "per_pair": per_pair}

@@ -328,9 +328,14 @@ typedef struct corr_batch corr_batch;
 
 /*
  * Plan every pair (ball counts and grid sizes may all differ) and share one
- * device workspace among them, sized for the largest pair and `slots`
- * rotations per pass (0 = largest that fits 4 GiB, at most 64).  Computes every
- * A spectrum.  Pair p is validated like corr_create; its errors name the pair.
+ * device workspace among them.  Rotations per pass (corr_batch_info's batch):
+ *   slots = 0   per pair, the most (at most 64) whose buffers fit 4 GiB for that
+ *               pair; each workspace buffer is sized for the pair needing most
+ *               of it, so pairs on small grids run many rotations per pass;
+ *   slots > 0   `slots` for the pair needing most, and as many as fit in the
+ *               same buffers for the others (at most 256).
+ * Computes every A spectrum.  Pair p is validated like corr_create; its errors
+ * name the pair.
  */
 int corr_batch_create(const corr_pair* pairs, int32_t n_pairs, int32_t slots, void* hip_stream,
                       corr_batch** out);

@@ -302,6 +302,23 @@ struct WsReq {
         tiles = std::max(tiles, o.tiles);
         list = std::max(list, o.list);
     }
+    // The request of k slots, as one slot.
+    WsReq scaled(size_t k) const {
+        WsReq o = *this;
+        o.buf0 *= k; o.buf1 *= k; o.nk *= k; o.nkw *= k; o.nkq *= k;
+        o.counts *= k; o.bins *= k; o.blocks *= k; o.tiles *= k; o.list *= k;
+        return o;
+    }
+    // Rotations per pass that fit, for a plan needing `o` per slot, in buffers
+    // sized for `slots` slots of this request (each array is indexed by the
+    // plan's own geometry, so a smaller plan packs more rotations into them).
+    int slots_for(const WsReq& o, int slots) const {
+        size_t fit = 256;
+        const size_t have[10] = {buf0, buf1, nk, nkw, nkq, counts, bins, blocks, tiles, list};
+        const size_t need[10] = {o.buf0, o.buf1, o.nk, o.nkw, o.nkq, o.counts, o.bins, o.blocks, o.tiles, o.list};
+        for (int k = 0; k < 10; ++k) fit = std::min(fit, (size_t)slots * have[k] / std::max<size_t>(need[k], 1));
+        return (int)std::max<size_t>(fit, 1);
+    }
     size_t slot_bytes() const {
         return 4 * buf0 + 8 * buf1 + 4 * (3 * nk + nkw + nkq) + 12 * nkw + 4 * (counts + bins) + 12 * blocks + tiles +
                4 * list + 32;
@@ -332,10 +349,12 @@ struct Workspace {
     double* host_quats = nullptr;  // pinned [slots][4]
     hipEvent_t quat_done = nullptr;
 
-    void allocate(int nslots, const WsReq& r, hipStream_t st) {
+    // qslots: rotations the staging of quaternions must hold (at least nslots)
+    void allocate(int nslots, const WsReq& r, hipStream_t st, int qslots = 0) {
         slots = nslots;
         req = r;
         const size_t S = (size_t)nslots;
+        const size_t SQ = (size_t)std::max(nslots, qslots);
         buf0 = mem.alloc<float>(S * r.buf0);
         buf1 = mem.alloc<float2>(S * r.buf1);
         cell = mem.alloc<int>(S * r.nk);
@@ -351,11 +370,11 @@ struct Workspace {
         scell = mem.alloc<int>(S * r.nk);
         skbw = mem.alloc<float>(S * r.nkw);
         swts = mem.alloc<float>(S * r.nkq);
-        quats = mem.alloc<double>(S * 4);
+        quats = mem.alloc<double>(SQ * 4);
         pval = mem.alloc<float>(S * r.blocks);
         pidx = mem.alloc<int>(S * r.blocks);
         pcnt = mem.alloc<int>(S * r.blocks);
-        hip_check(hipHostMalloc((void**)&host_quats, sizeof(double) * 4 * S, hipHostMallocDefault), "hipHostMalloc");
+        hip_check(hipHostMalloc((void**)&host_quats, sizeof(double) * 4 * SQ, hipHostMallocDefault), "hipHostMalloc");
         hip_check(hipEventCreateWithFlags(&quat_done, hipEventDisableTiming), "hipEventCreate");
         hip_check(hipEventRecord(quat_done, st), "event");
     }
@@ -430,6 +449,7 @@ struct corr_ctx {
     double* ident_q = nullptr;     // the identity quaternion (1, 0, 0, 0), device
     corr::Workspace* ws = nullptr;  // per-rotation buffers (shared by the pairs of a batch)
     bool own_ws = false;
+    int slots_eff = 0;  // rotations per pass of a batch pair (0: the workspace's slots)
     // A's spectrum on a side stream (contexts with a workspace of their own):
     // forked from `stream`, with buffers of its own, joined back by a_done
     hipStream_t side = nullptr;
@@ -820,8 +840,9 @@ void eval_impl(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, const std::v
     const Geom& g = c->g;
     const size_t n3 = (size_t)g.n * g.n * g.n;
     const int nb = corr::ifft_x_blocks(g);
-    for (int64_t r0 = 0; r0 < n_rot; r0 += c->ws->slots) {
-        const int S = (int)std::min<int64_t>(c->ws->slots, n_rot - r0);
+    const int slots = c->slots_eff > 0 ? c->slots_eff : c->ws->slots;
+    for (int64_t r0 = 0; r0 < n_rot; r0 += slots) {
+        const int S = (int)std::min<int64_t>(slots, n_rot - r0);
         // rotations already on the device (graph replay), or staged per batch
         if (!d_quats) stage_quats(c, quat_wxyz + 4 * r0, S);
         run_spectrum_stages(c, c->B, d_quats ? d_quats + 4 * r0 : c->ws->quats, S);
@@ -1381,7 +1402,7 @@ int corr_info(const corr_ctx* c, corr_info_t* out) {
     out->q_b = c->B.ex.q;
     out->n_a = c->A.n;
     out->n_b = c->B.n;
-    out->batch = c->ws->slots;
+    out->batch = c->slots_eff > 0 ? c->slots_eff : c->ws->slots;
     out->workspace_bytes =
         (int64_t)(c->mem.bytes + (c->own_ws ? c->ws->mem.bytes : 0) + (c->ws_a ? c->ws_a->mem.bytes : 0));
     out->beta = c->g.beta;
@@ -1591,8 +1612,29 @@ int corr_batch_create(const corr_pair* pairs, int32_t n_pairs, int32_t slots, vo
             b->pairs.push_back(plan_pair(pr.A, pr.nA, pr.B, pr.nB, &pr.grid, hip_stream, who));
             r.merge(ws_req(b->pairs.back()));
         }
-        if (slots == 0) slots = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 30) / r.slot_bytes()));
-        b->ws.allocate(slots, r, b->stream);
+        if (slots == 0) {
+            // rotations per pass chosen per pair, from a 4 GiB budget (at most
+            // 64): every buffer is sized for the pair that needs most of it, and
+            // each pair indexes the buffers by its own geometry
+            corr::WsReq all;
+            int qslots = 1;
+            for (corr_ctx* c : b->pairs) {
+                const corr::WsReq rp = ws_req(c);
+                c->slots_eff = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 30) / rp.slot_bytes()));
+                all.merge(rp.scaled((size_t)c->slots_eff));
+                qslots = std::max(qslots, c->slots_eff);
+            }
+            b->ws.allocate(1, all, b->stream, qslots);
+        } else {
+            // `slots` rotations per pass for the pair that needs most; a pair on a
+            // smaller grid (or with fewer knots) packs more into the same buffers
+            int qslots = slots;
+            for (corr_ctx* c : b->pairs) {
+                c->slots_eff = r.slots_for(ws_req(c), slots);
+                qslots = std::max(qslots, c->slots_eff);
+            }
+            b->ws.allocate(slots, r, b->stream, qslots);
+        }
         for (corr_ctx* c : b->pairs) {
             c->ws = &b->ws;
             c->own_ws = false;
