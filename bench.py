@@ -116,7 +116,9 @@ def run_proposal(args, torch, pkg):
     X_parts, y_parts, records = [], [], []
     for p, (A, B, g) in enumerate(seen + unseen):
         is_seen = p < n_train
-        qtrain = synth.random_quaternions(rot_train, 6000 + p, canonical=True) if is_seen else np.zeros((0, 4))
+        # training rotations: an evenly spread set (super-Fibonacci spiral, turned per
+        # pair); candidates: fresh uniform random rotations
+        qtrain = synth.super_fibonacci_quaternions(rot_train, 6000 + p) if is_seen else np.zeros((0, 4))
         qcand = synth.random_quaternions(n_cand, 7000 + p, canonical=True)
         ytr, peaks, coarse, t64, t_exh, t_coarse = visit(A, B, g, qtrain, qcand)
         vv = volume(A) * volume(B)

@@ -83,6 +83,28 @@ def random_quaternions(n: int, seed: int, canonical: bool = False) -> np.ndarray
     return q
 
 
+def super_fibonacci_quaternions(n: int, seed: int) -> np.ndarray:
+    """n unit quaternions (w, x, y, z), w >= 0, spread evenly over the rotations:
+    the super-Fibonacci spiral of Alexa (CVPR 2022), point i of which has
+    s = i + 1/2, radii sqrt(s/n) and sqrt(1 - s/n) in the two planes of R^4 and
+    angles 2 pi s / sqrt(2) and 2 pi s / psi, psi the real root > 1 of
+    psi^4 = psi + 4.  The whole set is turned by one rotation drawn from `seed`,
+    so that different seeds give differently placed, equally even sets."""
+    psi = 1.533751168755204288118041
+    s = np.arange(n, dtype=np.float64) + 0.5
+    t = s / n
+    r, rr = np.sqrt(t), np.sqrt(1.0 - t)
+    a, b = 2.0 * np.pi * s / math.sqrt(2.0), 2.0 * np.pi * s / psi
+    p = np.stack([r * np.sin(a), r * np.cos(a), rr * np.sin(b), rr * np.cos(b)], axis=1)
+    g = random_quaternions(1, seed)[0]
+    w1, x1, y1, z1 = g
+    w2, x2, y2, z2 = p.T
+    q = np.stack([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                  w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2], axis=1)
+    q[q[:, 0] < 0] *= -1.0
+    return q
+
+
 def loguniform_int(g: np.random.Generator, lo: int, hi: int, size: int) -> np.ndarray:
     return np.exp(math.log(lo) + (math.log(hi) - math.log(lo)) * g.random(size)).astype(np.int64)
 
