@@ -117,3 +117,42 @@ def test_training_fits_a_smooth_target(pkg):
     np.testing.assert_array_equal(p.predict(Xt[:500]).cpu().numpy(), p2.predict(Xt[:500]).cpu().numpy())
     p.close()
     p2.close()
+
+
+def test_trained_network_beats_search_without_it(pkg):
+    # The method without the network picks rotations blindly: the best of k random
+    # candidates holds the exhaustive peak with probability k / candidates.  The
+    # trained network's top-k must hold it far more often (small workload: 12
+    # pairs on 32^3 grids, 600 evenly spread training rotations each, top 32 of
+    # 1024 fresh candidates).
+    n_pairs, n_train, n_cand, top = 12, 600, 1024, 32
+    _say("case: proposal gain, %d pairs, n=32, top %d of %d" % (n_pairs, top, n_cand))
+    pairs = synth.proposal_pairs(n_pairs, 8100, lo=300, hi=1500, n=32)
+    prop = pkg.Proposer(batch=256, seed=5)
+    X, y, evals = [], [], []
+    for p, (A, B, g) in enumerate(pairs):
+        c = pkg.Correlator(A, B, g.n, g.box, g.origin, batch=64)
+        qt = synth.super_fibonacci_quaternions(n_train, 8200 + p)
+        qc = synth.random_quaternions(n_cand, 8300 + p, canonical=True)
+        yt = c.eval(qt, scores=False)[1].double().cpu().numpy()
+        peaks = c.eval(qc, scores=False)[1].double().cpu().numpy()
+        c.close()
+        da, db = prop.descriptor(A), prop.descriptor(B)
+        X.append(prop.features(qt, da, db))
+        y.append(torch.tensor((yt - yt.mean()) / yt.std(), dtype=torch.float32, device="cuda"))
+        evals.append((prop.features(qc, da, db), peaks))
+    X, y = torch.cat(X), torch.cat(y)
+    for ep, lr in ((100, 1e-3), (40, 3e-4), (20, 1e-4)):
+        losses = prop.train(X, y, ep, lr)
+    rng = np.random.default_rng(8400)
+    hit_net = hit_rand = 0
+    for Xc, peaks in evals:
+        best = peaks.max()
+        idx = prop.rank(Xc, top).cpu().numpy()
+        hit_net += peaks[idx].max() >= (1 - 1e-4) * best
+        hit_rand += peaks[rng.choice(n_cand, top, replace=False)].max() >= (1 - 1e-4) * best
+    prop.close()
+    _say("  final loss %.3g; exhaustive peak in the network's top %d: %d of %d pairs; in %d random: %d"
+         % (losses[-1], top, hit_net, n_pairs, top, hit_rand))
+    assert hit_net >= n_pairs // 2
+    assert hit_net >= hit_rand + n_pairs // 3
