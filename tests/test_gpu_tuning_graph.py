@@ -124,6 +124,13 @@ def test_autotune_keeps_a_valid_tuning_and_the_results():
         assert t[f] in pkg.corr_tuning_choices(c.ctx, p)
     assert 1 <= t["slots"] <= 256 and t["graph"] == 0
     _same(_eval(c, q, out), ref, "after autotune")
+    # tuning in graph mode: every candidate is captured and replayed
+    c.set_tuning(graph=1)
+    t = c.autotune(q, reps=1)
+    _say("  kept in graph mode:", t)
+    assert t["graph"] == 1
+    _same(_eval(c, q, out), ref, "after autotune in graph mode")
+    _same(_eval(c, q, out), ref, "replay after autotune in graph mode")
     c.close()
 
 
