@@ -634,6 +634,30 @@ void fixed_spectrum(corr_ctx* c, const Shape& a, float2* fa) {
 
 corr::WsReq ws_req(const corr_ctx* c);
 
+// Replace the context's own workspace by one of `slots` slots for the current
+// plan (ws_req).  The new one is allocated first: if that fails, the old one
+// stays in use.  The last pass's occupancy record is dropped with the old one.
+void replace_workspace(corr_ctx* c, int slots) {
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    auto* nw = new corr::Workspace();
+    try {
+        nw->allocate(slots, ws_req(c), c->stream);
+    } catch (...) {
+        nw->release();
+        delete nw;
+        throw;
+    }
+    c->gs.drop_graph();
+    c->shape_gen++;
+    if (c->last_ws == c->ws) {
+        c->last_ws = nullptr;
+        c->last_S = 0;
+    }
+    c->ws->release();
+    delete c->ws;
+    c->ws = nw;
+}
+
 // Make the context's stream wait for a pending A spectrum.
 void join_a(corr_ctx* c) {
     if (!c->a_pending) return;
@@ -1036,12 +1060,14 @@ void set_offsets(corr_ctx* c, const double* offsets, int32_t n) {
             hip_check(hipGetDeviceProperties(&prop, c->device), "hipGetDeviceProperties");
             if (corr::max_lds_bytes(c->g, qmax) > prop.sharedMemPerBlock)
                 fail(CORR_EUNSUPPORTED, "offset slices need %d radius components: too much LDS", qmax);
-            hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-            const int slots = c->ws->slots;
-            c->ws->release();
-            c->shape_gen++;
-            c->qmax = qmax;
-            c->ws->allocate(slots, ws_req(c), c->stream);
+            const int old_q = c->qmax;
+            c->qmax = qmax;  // ws_req plans for the slices' components
+            try {
+                replace_workspace(c, c->ws->slots);
+            } catch (...) {
+                c->qmax = old_q;
+                throw;
+            }
         }
         for (int k = 0; k < n; ++k) fixed_spectrum(c, ns[k].A, ns[k].fa);
         hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
@@ -1150,11 +1176,7 @@ void set_tuning(corr_ctx* c, const corr_tuning& t) {
     if (t.graph != 0 && t.graph != 1) fail(CORR_EINVAL, "graph must be 0 or 1");
     if (t.slots != c->ws->slots) {
         if (!c->own_ws) fail(CORR_EUNSUPPORTED, "the pairs of a batch share their workspace: slots are fixed");
-        hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-        c->gs.drop_graph();
-        c->shape_gen++;
-        c->ws->release();
-        c->ws->allocate(t.slots, ws_req(c), c->stream);
+        replace_workspace(c, t.slots);
     }
     Geom& g = c->g;
     if (g.cols_y != t.cols_y || g.cols_z != t.cols_z || g.cols_iy != t.cols_iy || g.pairs_ix != t.pairs_ix ||
