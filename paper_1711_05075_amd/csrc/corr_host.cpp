@@ -693,6 +693,8 @@ void prepare_a(corr_ctx* c) {
     }
     hip_check(hipEventRecord(c->fork_ev, c->stream), "hipEventRecord");
     hip_check(hipStreamWaitEvent(c->side, c->fork_ev, 0), "hipStreamWaitEvent");
+    // on every exit, also after a failed launch: the context's stream and
+    // buffers come back, and whatever reached the side stream is joined
     struct Swap {
         corr_ctx* c;
         hipStream_t st;
@@ -700,13 +702,13 @@ void prepare_a(corr_ctx* c) {
         ~Swap() {
             c->stream = st;
             c->ws = ws;
+            c->a_pending = hipEventRecord(c->a_done, c->side) == hipSuccess;
+            if (!c->a_pending) (void)hipStreamSynchronize(c->side);
         }
     } swap{c, c->stream, c->ws};
     c->stream = c->side;
     c->ws = c->ws_a;
     fixed_spectrum(c, c->A, c->fa);
-    hip_check(hipEventRecord(c->a_done, c->side), "hipEventRecord");
-    c->a_pending = true;
 }
 
 // host quaternions -> pinned staging -> device, S at a time
