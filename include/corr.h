@@ -329,7 +329,7 @@ typedef struct corr_batch corr_batch;
 /*
  * Plan every pair (ball counts and grid sizes may all differ) and share one
  * device workspace among them.  Rotations per pass (corr_batch_info's batch):
- *   slots = 0   per pair, the most (at most 64) whose buffers fit 4 GiB for that
+ *   slots = 0   per pair, the most (at most 64) whose buffers fit 8 GiB for that
  *               pair; each workspace buffer is sized for the pair needing most
  *               of it, so pairs on small grids run many rotations per pass;
  *   slots > 0   `slots` for the pair needing most, and as many as fit in the

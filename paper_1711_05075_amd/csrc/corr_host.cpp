@@ -1637,14 +1637,14 @@ int corr_batch_create(const corr_pair* pairs, int32_t n_pairs, int32_t slots, vo
             r.merge(ws_req(b->pairs.back()));
         }
         if (slots == 0) {
-            // rotations per pass chosen per pair, from a 4 GiB budget (at most
+            // rotations per pass chosen per pair, from an 8 GiB budget (at most
             // 64): every buffer is sized for the pair that needs most of it, and
             // each pair indexes the buffers by its own geometry
             corr::WsReq all;
             int qslots = 1;
             for (corr_ctx* c : b->pairs) {
                 const corr::WsReq rp = ws_req(c);
-                c->slots_eff = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)4 << 30) / rp.slot_bytes()));
+                c->slots_eff = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)8 << 30) / rp.slot_bytes()));
                 all.merge(rp.scaled((size_t)c->slots_eff));
                 qslots = std::max(qslots, c->slots_eff);
             }
