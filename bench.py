@@ -8,7 +8,10 @@ scores and peaks), inputs resident on the device.
 
 Prints one JSON line with the throughput, the dominant kernel's roofline
 (algorithmic bytes per launch / its mean event-timed duration) and the FP64
-oracle timed on the host for one rotation of the same workload.
+oracle timed on the host for one rotation of the same workload.  The line also
+holds, under "batched", the 512-rotation workload (20000 + 2000 balls, 64^3)
+timed launch by launch, as a hipGraph and autotuned (--no-batched skips it).
+Other workloads: --batched, --uneven, --proposal, --query, --slices, --sc.
 """
 import argparse
 import json
@@ -330,7 +333,7 @@ def _o2_rel(A, B, q, g, s_gpu):
     return float(np.abs(s_gpu - ref).max() / np.abs(ref).max())
 
 
-def run_batched(args, torch, pkg):
+def measure_batched(args, torch, pkg, sample=(0, 255, 511)):
     """Batched rotations: 20000 + 2000 mixture balls, 512 rotations, n = 64, all
     in one corr_eval call.  Timed launch by launch with the default launch
     shapes, as one replayed hipGraph, and as a graph after the autotuner; the
@@ -360,7 +363,6 @@ def run_batched(args, torch, pkg):
     ms = rows[best][0]
     step()
     torch.cuda.synchronize()
-    sample = [0, R // 2, R - 1]
     errs = [_o2_rel(A, B, q[r], g, s[r].double().cpu().numpy()) for r in sample]
     out = {"metric": "rotations*translations scored/s at <=1e-4 rel err vs FP64", "value": R * n ** 3 / (ms * 1e-3),
            "unit": "rot*trans/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -372,7 +374,11 @@ def run_batched(args, torch, pkg):
            "autotune_seconds": tune_s,
            "e_rel_vs_fp64_sampled": {str(r): e for r, e in zip(sample, errs)}}
     c.close()
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def run_batched(args, torch, pkg):
+    print(json.dumps(measure_batched(args, torch, pkg)), flush=True)
 
 
 def run_uneven(args, torch, pkg):
@@ -440,6 +446,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 512-rotation batched workload that the default run also reports")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (reference for hardware byte counters)")
     ap.add_argument("--proposal", action="store_true",
@@ -591,6 +599,11 @@ def main():
                                          "one rotation of the same workload, full 128^3 grid"}
         out["e_rel_vs_fp64"] = float(np.abs(s_gpu - ref).max() / np.abs(ref).max())
     c.close()
+    if not args.no_batched and not sc:
+        # the batched-rotations workload as well, so that one run reports both
+        b = measure_batched(args, torch, pkg, sample=(0,))
+        out["batched"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "config", "best_mode", "modes",
+                                            "autotune_seconds", "e_rel_vs_fp64_sampled")}
     print(json.dumps(out), flush=True)
 
 
