@@ -371,7 +371,7 @@ def measure_batched(args, torch, pkg, sample=(0, 255, 511)):
     c.set_tuning(graph=1)
     rows["graph"] = (_timed(torch, step, args.warmup, args.steps), c.tuning())
     t0 = time.perf_counter()
-    pkg.corr_autotune(c.ctx, q, s.data_ptr(), pv.data_ptr(), pi.data_ptr(), 2)
+    pkg.corr_autotune(c.ctx, q, s.data_ptr(), pv.data_ptr(), pi.data_ptr(), reps=2)
     tune_s = time.perf_counter() - t0
     rows["autotuned graph"] = (_timed(torch, step, args.warmup, args.steps), c.tuning())
     for k, (ms, t) in rows.items():
@@ -463,6 +463,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default launch shapes instead of autotuning them first")
+    ap.add_argument("--tuning", type=str, default=None, metavar="K=V,...",
+                    help="fixed launch shapes (corr_tuning fields), e.g. spread_wgs=384,cols_y=16; skips the autotuner")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 512-rotation batched workload that the default run also reports")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -534,6 +538,20 @@ def main():
         pkg.corr_prepare_a(c.ctx)
         pkg.corr_eval(c.ctx, q, scores.data_ptr(), pv.data_ptr(), pi.data_ptr())
 
+    # launch shapes: fixed by --tuning, or chosen by the library's autotuner for
+    # this very step (A's spectrum + one rotation), or the defaults
+    tune_s = None
+    if args.tuning:
+        c.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
+        tuning_source = "fixed (--tuning)"
+    elif args.no_autotune:
+        tuning_source = "defaults"
+    else:
+        t0 = time.perf_counter()
+        pkg.corr_autotune(c.ctx, q, scores.data_ptr(), pv.data_ptr(), pi.data_ptr(), reps=10, with_a=True)
+        tune_s = time.perf_counter() - t0
+        tuning_source = "autotuned on corr_prepare_a + corr_eval"
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -593,6 +611,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                      "alg_bytes_per_launch": dom_bytes, "mean_launch_ms": dom_ms},
+        "tuning": c.tuning(), "tuning_source": tuning_source, "autotune_seconds": tune_s,
         "occupancy": {"a": {k: pass_a[k] for k in ("tiles", "live_tiles", "live_rows")},
                       "b": {k: pass_b[k] for k in ("tiles", "live_tiles", "live_rows")}},
     }

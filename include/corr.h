@@ -300,18 +300,24 @@ int corr_set_tuning(corr_ctx* ctx, const corr_tuning* tuning);
  * it where the pass's shape allows.  out3 receives *count (1..3) values. */
 int corr_tuning_choices(const corr_ctx* ctx, int32_t pass, int32_t* out3, int32_t* count);
 
+/* flags of corr_autotune */
+#define CORR_TUNE_WITH_A 1u  /* time corr_prepare_a + corr_eval as one unit (the fixed
+                                shape's spectrum is recomputed with every
+                                evaluation), not corr_eval alone                  */
+
 /*
  * Autotuner.  Evaluates these rotations (arguments as for corr_eval) under
  * candidate tunings and keeps the fastest: coordinate descent over slots
- * (powers of two up to n_rot, workspace <= 8 GiB), spread_wgs (one or two per
- * CU) and the four column widths, each candidate timed by HIP events as the
- * least of `reps` (1..100) evaluations after an untimed one.  The graph setting
- * is kept as it is.  Synchronous; the outputs hold the last evaluation's
- * results, which equal corr_eval's under any tuning.  *out (may be NULL)
- * receives the tuning kept.
+ * (powers of two up to n_rot, workspace <= 8 GiB), spread_wgs (one, one and a
+ * half or two per CU) and the four column widths, each candidate timed by HIP
+ * events as the least of `reps` (1..100) runs after an untimed one.  A run is
+ * corr_eval, or with CORR_TUNE_WITH_A corr_prepare_a + corr_eval.  The graph
+ * setting is kept as it is.  Synchronous; the outputs hold the last
+ * evaluation's results, which equal corr_eval's under any tuning.  *out (may
+ * be NULL) receives the tuning kept.
  */
 int corr_autotune(corr_ctx* ctx, const double* quat_wxyz, int64_t n_rot, float* scores_dev, float* peak_val_dev,
-                  int64_t* peak_idx_dev, int32_t reps, corr_tuning* out);
+                  int64_t* peak_idx_dev, int32_t reps, uint32_t flags, corr_tuning* out);
 
 /* ---- uneven batches of pairs --------------------------------------------- */
 

@@ -28,6 +28,7 @@ CORR_EHIP = -3
 CORR_EUNSUPPORTED = -4
 CORR_DETERMINISTIC = 1
 CORR_SC_SCORE = 2
+CORR_TUNE_WITH_A = 1
 CORR_MAX_SLICES = 16
 
 EXPORTS = ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
@@ -107,7 +108,7 @@ def load_library(path: str = LIB_PATH):
     lib.corr_get_tuning.argtypes = [vp, ctypes.POINTER(corr_tuning)]
     lib.corr_set_tuning.argtypes = [vp, ctypes.POINTER(corr_tuning)]
     lib.corr_tuning_choices.argtypes = [vp, i32, vp, ctypes.POINTER(i32)]
-    lib.corr_autotune.argtypes = [vp, vp, i64, vp, vp, vp, i32, ctypes.POINTER(corr_tuning)]
+    lib.corr_autotune.argtypes = [vp, vp, i64, vp, vp, vp, i32, ctypes.c_uint32, ctypes.POINTER(corr_tuning)]
     lib.corr_destroy.argtypes = [vp]
     lib.corr_last_error.argtypes = [vp]
     lib.corr_last_error.restype = ctypes.c_char_p
@@ -227,11 +228,13 @@ def corr_tuning_choices(ctx, pass_id) -> list:
     return [out[i] for i in range(cnt.value)]
 
 
-def corr_autotune(ctx, quats, scores_ptr, peak_val_ptr, peak_idx_ptr, reps=3) -> dict:
+def corr_autotune(ctx, quats, scores_ptr, peak_val_ptr, peak_idx_ptr, reps=3, with_a=False) -> dict:
+    """with_a: time corr_prepare_a + corr_eval as one unit (CORR_TUNE_WITH_A)."""
     q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
     t = corr_tuning()
     _check(load_library().corr_autotune(ctx, q.ctypes.data if len(q) else None, len(q), scores_ptr or None,
-                                        peak_val_ptr or None, peak_idx_ptr or None, int(reps), ctypes.byref(t)), ctx)
+                                        peak_val_ptr or None, peak_idx_ptr or None, int(reps),
+                                        CORR_TUNE_WITH_A if with_a else 0, ctypes.byref(t)), ctx)
     return {k: getattr(t, k) for k in TUNING_FIELDS}
 
 
@@ -330,8 +333,9 @@ class Correlator:
         with self.torch.cuda.device(self.device):
             corr_set_tuning(self.ctx, **fields)
 
-    def autotune(self, quats, scores=True, peaks=True, reps=3):
-        """Run the autotuner on these rotations; returns the tuning kept."""
+    def autotune(self, quats, scores=True, peaks=True, reps=3, with_a=False):
+        """Run the autotuner on these rotations (with_a: timing A's spectrum with
+        each evaluation); returns the tuning kept."""
         torch = self.torch
         q = np.asarray(quats, dtype=np.float64).reshape(-1, 4)
         r, n = len(q), self.n
@@ -341,7 +345,7 @@ class Correlator:
         with torch.cuda.device(self.device):
             return corr_autotune(self.ctx, q, s.data_ptr() if s is not None else None,
                                  pv.data_ptr() if pv is not None else None, pi.data_ptr() if pi is not None else None,
-                                 reps)
+                                 reps, with_a)
 
     def query(self, quat, t, mode_radius2):
         """Score at translations t ([n][3]) over the modes |m|^2 <= mode_radius2;

@@ -1197,9 +1197,11 @@ void set_tuning(corr_ctx* c, const corr_tuning& t) {
 // `reps` timed runs after one untimed run), the others held.  Results do not
 // depend on the launch shape, so only time is compared.
 corr_tuning autotune(corr_ctx* c, const double* q, int64_t n_rot, float* scores, float* pv, int64_t* pi,
-                     int reps) {
+                     int reps, uint32_t flags) {
     if (n_rot < 1) fail(CORR_EINVAL, "autotuning needs n_rot >= 1");
     if (reps < 1 || reps > 100) fail(CORR_EINVAL, "reps = %d; allowed 1..100", reps);
+    if (flags & ~CORR_TUNE_WITH_A) fail(CORR_EINVAL, "unknown autotune flag bits 0x%x", flags);
+    const bool with_a = (flags & CORR_TUNE_WITH_A) != 0;
     if ((pv == nullptr) != (pi == nullptr)) fail(CORR_EINVAL, "peak_val and peak_idx must both be set or both be NULL");
     validate_quats(q, n_rot);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1209,13 +1211,19 @@ corr_tuning autotune(corr_ctx* c, const double* q, int64_t n_rot, float* scores,
     c->profiling = false;
     const corr_tuning start = get_tuning(c);
     try {
+        // the timed unit: corr_eval, or corr_prepare_a + corr_eval (A's spectrum
+        // forks off the context's stream after e0 and is joined before e1)
+        auto unit = [&] {
+            if (with_a) prepare_a(c);
+            eval_plain(c, q, n_rot, scores, pv, pi);
+        };
         auto timed = [&](const corr_tuning& t) {
             set_tuning(c, t);
-            eval_plain(c, q, n_rot, scores, pv, pi);  // untimed: first touch, graph capture
+            unit();  // untimed: first touch, graph capture
             float best = INFINITY;
             for (int r = 0; r < reps; ++r) {
                 hip_check(hipEventRecord(e0, c->stream), "hipEventRecord");
-                eval_plain(c, q, n_rot, scores, pv, pi);
+                unit();
                 hip_check(hipEventRecord(e1, c->stream), "hipEventRecord");
                 hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
                 float ms = 0;
@@ -1248,7 +1256,7 @@ corr_tuning autotune(corr_ctx* c, const double* q, int64_t n_rot, float* scores,
             try_field(&corr_tuning::slots, sl);
         }
         const int cus = cu_count(c);
-        try_field(&corr_tuning::spread_wgs, {cus, 2 * cus});
+        try_field(&corr_tuning::spread_wgs, {cus, cus + cus / 2, 2 * cus});
         int32_t corr_tuning::*fields[4] = {&corr_tuning::cols_y, &corr_tuning::cols_z, &corr_tuning::cols_iy,
                                            &corr_tuning::pairs_ix};
         for (int p = 0; p < 4; ++p) {
@@ -1314,13 +1322,13 @@ int corr_tuning_choices(const corr_ctx* c, int32_t pass, int32_t* out3, int32_t*
 }
 
 int corr_autotune(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, float* scores_dev, float* peak_val_dev,
-                  int64_t* peak_idx_dev, int32_t reps, corr_tuning* out) {
+                  int64_t* peak_idx_dev, int32_t reps, uint32_t flags, corr_tuning* out) {
     if (!c) {
         g_thread_error = "corr_autotune: NULL context";
         return CORR_EINVAL;
     }
     return guarded(c, [&] {
-        const corr_tuning t = autotune(c, quat_wxyz, n_rot, scores_dev, peak_val_dev, peak_idx_dev, reps);
+        const corr_tuning t = autotune(c, quat_wxyz, n_rot, scores_dev, peak_val_dev, peak_idx_dev, reps, flags);
         if (out) *out = t;
     });
 }

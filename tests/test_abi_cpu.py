@@ -124,7 +124,7 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.corr_get_tuning(None, ctypes.byref(t)) == pkg.CORR_EINVAL
     assert lib.corr_set_tuning(None, ctypes.byref(t)) == pkg.CORR_EINVAL
     assert lib.corr_tuning_choices(None, 0, out3, ctypes.byref(cnt)) == pkg.CORR_EINVAL
-    assert lib.corr_autotune(None, None, 1, None, None, None, 3, None) == pkg.CORR_EINVAL
+    assert lib.corr_autotune(None, None, 1, None, None, None, 3, 0, None) == pkg.CORR_EINVAL
     assert pkg._batch_lib().corr_batch_set_graph(None, 1) == pkg.CORR_EINVAL
 
 

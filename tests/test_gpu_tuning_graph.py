@@ -124,6 +124,11 @@ def test_autotune_keeps_a_valid_tuning_and_the_results():
         assert t[f] in pkg.corr_tuning_choices(c.ctx, p)
     assert 1 <= t["slots"] <= 256 and t["graph"] == 0
     _same(_eval(c, q, out), ref, "after autotune")
+    # timing A's spectrum with each evaluation (the side stream joined inside)
+    t = c.autotune(q, reps=1, with_a=True)
+    _say("  kept with A's spectrum timed:", t)
+    assert t["spread_wgs"] in (t["spread_wgs"],) and 1 <= t["spread_wgs"]
+    _same(_eval(c, q, out), ref, "after autotune with A")
     # tuning in graph mode: every candidate is captured and replayed
     c.set_tuning(graph=1)
     t = c.autotune(q, reps=1)
