@@ -69,8 +69,9 @@ typedef struct {
     double box;        /* period L > 0 of the translation grid; h = box / n       */
     double origin[3];  /* translation at index (0, 0, 0)                          */
     double sigma;      /* oversampling of the spreading grid; 2.0 (0 = default 2) */
-    int32_t kb_width;  /* Kaiser-Bessel window width in fine cells: even, 4..12
-                          (0 = default 8)                                          */
+    int32_t kb_width;  /* Kaiser-Bessel window width in fine cells: even, 6..12
+                          (0 = default 8); 4 is rejected (CORR_EUNSUPPORTED): its
+                          window error, ~1e-3, exceeds the 1e-4 tolerance          */
     double tol;        /* tolerance of the radius expansion of the ball transform,
                           relative to the largest ball volume (0 = default 1e-6)   */
     uint32_t flags;    /* CORR_DETERMINISTIC or 0                                  */

@@ -53,7 +53,10 @@ typedef struct prop_ctx prop_ctx;
  * batch: training mini-batch size, 64..8192, a multiple of 64. */
 int prop_create(int32_t batch, uint64_t seed, void* hip_stream, prop_ctx** out);
 
-/* Descriptor of a ball set (host corr_ball[n], n >= 1) into desc_dev[64] (device float). */
+/* Descriptor of a ball set (host corr_ball[n], n >= 1; finite centres, radii
+ * > 0 and weights > 0, else CORR_EINVAL) into desc_dev[64] (device float): the
+ * histogram of the volumes w r^3 over the centres' distance from the
+ * volume-weighted centroid, normalised to sum 1. */
 int prop_descriptor(prop_ctx* p, const corr_ball* balls, int64_t n, float* desc_dev);
 
 /* Network inputs X_dev[n][160] (device float, layout above) for n quaternions

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -572,8 +573,14 @@ hipEvent_t take_event(corr_ctx* c) {
 }
 
 // Launch one stage, bracketed by timing events when profiling is on.
+// Failure paths are testable from the host: with the environment variable
+// CORR_TEST_FAIL_STAGE set to a stage id, that stage reports a launch failure
+// (CORR_EHIP) instead of launching, like CORR_TEST_MAX_BYTES does for device
+// allocations.
 template <class L>
 void stage(corr_ctx* c, int id, const char* what, L&& launch) {
+    if (const char* f = std::getenv("CORR_TEST_FAIL_STAGE"))
+        if (*f && std::atoi(f) == id) fail(CORR_EHIP, "%s: launch failure forced by CORR_TEST_FAIL_STAGE", what);
     hipEvent_t a = nullptr, b = nullptr;
     if (c->profiling) {
         a = take_event(c);
@@ -749,7 +756,11 @@ corr_ctx* plan_pair(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t 
     const double sigma = gr.sigma == 0 ? 2.0 : gr.sigma;
     if (sigma != 2.0) fail(CORR_EUNSUPPORTED, "%ssigma = %g; supported: 2", who, sigma);
     const int w = gr.kb_width == 0 ? 8 : gr.kb_width;
-    if (w < 4 || w > 12 || (w & 1)) fail(CORR_EUNSUPPORTED, "%skb_width = %d; supported: even 4..12", who, w);
+    // at w = 4 the window alone leaves a relative error of ~1e-3 (sigma = 2),
+    // above the 1e-4 tolerance of the path; 6 leaves ~1e-5, 8 ~1e-7
+    if (w < 6 || w > 12 || (w & 1))
+        fail(CORR_EUNSUPPORTED, "%skb_width = %d; supported: even 6..12 (narrower windows miss the 1e-4 tolerance)",
+             who, w);
     const double tol = gr.tol == 0 ? 1e-6 : gr.tol;
     if (!std::isfinite(tol) || !(tol > 0) || tol >= 1) fail(CORR_EINVAL, "%stol must be in (0, 1)", who);
     if (gr.flags & ~(CORR_DETERMINISTIC | CORR_SC_SCORE)) fail(CORR_EINVAL, "%sunknown flag bits 0x%x", who, gr.flags);

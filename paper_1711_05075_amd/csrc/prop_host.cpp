@@ -211,6 +211,9 @@ int prop_descriptor(prop_ctx* c, const corr_ball* balls, int64_t n, float* desc_
             if (!std::isfinite(b.x) || !std::isfinite(b.y) || !std::isfinite(b.z) || !std::isfinite(b.w) ||
                 !std::isfinite(b.r) || !(b.r > 0))
                 fail(CORR_EINVAL, "ball %lld: non-finite value or radius <= 0", (long long)i);
+            // the histogram is of volumes w r^3, normalised by their total: a
+            // weight <= 0 has no volume (and a zero total no normalisation)
+            if (!(b.w > 0)) fail(CORR_EINVAL, "ball %lld: weight must be > 0 for a volume descriptor", (long long)i);
         }
         std::vector<void*> tmp;
         try {

@@ -71,6 +71,7 @@ GOOD = np.array([[0.0, 0.0, 0.0, 0.05, 1.0], [0.1, 0.0, 0.0, 0.04, 1.0]])
     (dict(origin=(0, float("inf"), 0)), pkg.CORR_EINVAL),
     (dict(sigma=1.5), pkg.CORR_EUNSUPPORTED),
     (dict(kb_width=7), pkg.CORR_EUNSUPPORTED),
+    (dict(kb_width=4), pkg.CORR_EUNSUPPORTED),
     (dict(kb_width=14), pkg.CORR_EUNSUPPORTED),
     (dict(tol=-1.0), pkg.CORR_EINVAL),
     (dict(tol=2.0), pkg.CORR_EINVAL),

@@ -33,9 +33,13 @@ def _o2(A, B, q, g):
     return oracle.o2_scores_from_spectra(FA, FB, g.box, g.origin)
 
 
-def test_small_uneven_batch_scores(pkg):
-    # six pairs, three grid sizes, ragged rotation counts (one pair with none),
-    # passes of 3 rotation slots shared by all pairs
+@pytest.mark.parametrize("slots", [3, 0])
+def test_small_uneven_batch_scores(pkg, slots):
+    # six pairs, three grid sizes, ragged rotation counts (one pair with none);
+    # slots = 3: passes of 3 rotation slots for the pair needing most, more for
+    # the others in the same buffers; slots = 0: rotations per pass chosen per
+    # pair from the memory budget, every buffer sized for the pair needing most
+    # of it and indexed by each pair's own geometry
     spec = [(120, 900, 32, 3), (700, 60, 64, 5), (2000, 1500, 32, 0), (300, 300, 128, 2), (50, 4000, 64, 4),
             (1000, 200, 16, 7)]
     pairs, quats, grids = [], [], []
@@ -46,8 +50,9 @@ def test_small_uneven_batch_scores(pkg):
         pairs.append((A, B, g.n, g.box, g.origin))
         quats.append(synth.random_quaternions(nr, 7000 + p))
         grids.append(g)
-    _say("case: 6-pair uneven batch, slots=3")
-    b = pkg.Batch(pairs, slots=3)
+    _say("case: 6-pair uneven batch, slots=%d" % slots)
+    b = pkg.Batch(pairs, slots=slots)
+    _say("  rotations per pass: %s" % [b.info(p)["batch"] for p in range(len(pairs))])
     scores, pv, pi, offs = b.eval(quats, scores=True)
     torch.cuda.synchronize()
     for p, (A, B, n, box, origin) in enumerate(pairs):
@@ -63,28 +68,46 @@ def test_small_uneven_batch_scores(pkg):
     b.close()
 
 
-def test_full_uneven_batch_peaks_sampled():
+def test_full_uneven_batch_largest_pairs_elementwise():
     import paper_1711_05075_amd as pkg
-    # 64 pairs, ball counts log-uniform in [500, 50000], grids of 32^3, 64^3 or
-    # 128^3, 32 rotations each, one batch; peaks of sampled pairs vs the oracle
+    # the full uneven batch in the launch configuration the benchmark times
+    # (64 pairs, ball counts log-uniform in [500, 50000], grids of 32^3, 64^3
+    # or 128^3, 32 rotations each, rotations per pass chosen per pair), scores
+    # of the largest pair of each grid size compared element by element with
+    # the FP64 oracle at rotations 0 and 31, and the peaks of the smallest
     cases = synth.uneven_batch_case()
-    _say("case: 64-pair uneven batch, 32 rotations each (2048 correlations)")
+    _say("case: 64-pair uneven batch, 32 rotations each (2048 correlations), scores kept")
     b = pkg.Batch([(A, B, g.n, g.box, g.origin) for A, B, q, g in cases])
-    _, pv, pi, offs = b.eval([q for A, B, q, g in cases])
+    scores, pv, pi, offs = b.eval([q for A, B, q, g in cases], scores=True)
     torch.cuda.synchronize()
     pv, pi = pv.cpu().numpy(), pi.cpu().numpy()
     assert np.all(np.isfinite(pv))
-    # the smallest pair of each grid size, two rotations each
     for n in (32, 64, 128):
         idx = [p for p, c in enumerate(cases) if c[3].n == n]
-        p = min(idx, key=lambda k: len(cases[k][0]) + len(cases[k][1]))
-        A, B, q, g = cases[p]
+        big = max(idx, key=lambda k: len(cases[k][0]) + len(cases[k][1]))
+        A, B, q, g = cases[big]
+        _say("  pair %d (n=%d, %d+%d balls, %d rotations per pass): oracle spectra..." % (
+            big, n, len(A), len(B), b.info(big)["batch"]))
+        FA = oracle.o2_spectrum(A, np.eye(3), g.n, g.box)
+        for r in (0, 31):
+            FB = oracle.o2_spectrum(B, oracle.quat_to_rot(q[r]), g.n, g.box)
+            ref = oracle.o2_scores_from_spectra(FA, FB, g.box, g.origin)
+            got = scores[big][r].double().cpu().numpy()
+            e = np.abs(got - ref).max() / np.abs(ref).max()
+            _say("  pair %d rot %d: e_rel = %.3g" % (big, r, e))
+            assert e <= TOL
+            k = offs[big] + r
+            assert float(pv[k]) == float(got.max())
+            assert int(pi[k]) == int(np.argmax(got.reshape(-1)))
+        small = min(idx, key=lambda k: len(cases[k][0]) + len(cases[k][1]))
+        A, B, q, g = cases[small]
         for r in (0, 31):
             ref = _o2(A, B, q[r], g)
             top = ref.max()
             scale = np.abs(ref).max()
-            got = pv[offs[p] + r]
-            _say("  pair %d (n=%d, %d+%d balls) rot %d: peak %.6g vs oracle %.6g" % (p, n, len(A), len(B), r, got, top))
+            got = pv[offs[small] + r]
+            _say("  pair %d (n=%d, %d+%d balls) rot %d: peak %.6g vs oracle %.6g" % (
+                small, n, len(A), len(B), r, got, top))
             assert abs(got - top) <= TOL * scale
-            assert ref.reshape(-1)[pi[offs[p] + r]] >= top - TOL * scale
+            assert ref.reshape(-1)[pi[offs[small] + r]] >= top - TOL * scale
     b.close()

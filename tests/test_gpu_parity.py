@@ -119,6 +119,43 @@ def test_mixture_pair_several_rotations_ragged_batches():
     c.close()
 
 
+@pytest.mark.parametrize("w", [6, 10, 12])
+def test_other_window_widths(w):
+    # every accepted Kaiser-Bessel width (8 is the default, covered above): the
+    # window's own error is ~1e-5 at w = 6 and far below it from 8 on, so the
+    # 1e-4 gate holds at each; w changes the staged-knot capacity, the 2w key
+    # ranges and the LDS layout of the spreading pass
+    A, B, q, g, _ = synth.tiny_case()
+    _say("case: tiny 64+64 balls, n=32, KB width %d" % w)
+    c = _corr(A, B, g, kb_width=w)
+    assert c.info["kb_width"] == w
+    s, _, _ = c.eval(q, peaks=False)
+    torch.cuda.synchronize()
+    _check_scores("tiny w=%d" % w, s.double().cpu().numpy(), _o2(A, B, q, g))
+    c.close()
+    # heavy tiles: more candidate knots than one staging round holds
+    A = synth.mixture_balls(20000, 1200 + w)
+    B = synth.mixture_balls(2000, 2200 + w)
+    g = synth.grid_for(A, B, 64)
+    q = synth.random_quaternions(2, 3200 + w)
+    _say("case: 20000+2000 mixture balls, n=64, KB width %d, 2 rotations" % w)
+    c = _corr(A, B, g, kb_width=w)
+    s, pv, pi = c.eval(q)
+    torch.cuda.synchronize()
+    s = s.double().cpu().numpy()
+    _check_scores("mixture w=%d" % w, s, _o2(A, B, q, g))
+    assert np.array_equal(pv.cpu().numpy(), s.reshape(len(q), -1).max(axis=1).astype(np.float32))
+    c.close()
+
+
+def test_window_width_4_is_rejected():
+    from paper_1711_05075_amd import CorrError, CORR_EUNSUPPORTED
+    A, B, q, g, _ = synth.tiny_case()
+    with pytest.raises(CorrError) as e:
+        _corr(A, B, g, kb_width=4)
+    assert e.value.code == CORR_EUNSUPPORTED
+
+
 @pytest.mark.parametrize("n", [16, 128, 256])
 def test_every_grid_size(n):
     A = synth.mixture_balls(24, 1100 + n)

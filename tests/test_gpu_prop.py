@@ -156,3 +156,17 @@ def test_trained_network_beats_search_without_it(pkg):
          % (losses[-1], top, hit_net, n_pairs, top, hit_rand))
     assert hit_net >= n_pairs // 2
     assert hit_net >= hit_rand + n_pairs // 3
+
+
+@pytest.mark.parametrize("w", [0.0, -1.0])
+def test_descriptor_rejects_weights_without_volume(pkg, w):
+    # the descriptor is a histogram of volumes w r^3 normalised by their total:
+    # a weight <= 0 is refused rather than giving an infinite scale
+    p = pkg.Proposer(batch=64, seed=1)
+    A = synth.mixture_balls(50, 79).copy()
+    A[7, 4] = w
+    with pytest.raises(pkg.CorrError) as e:
+        p.descriptor(A)
+    assert e.value.code == pkg.CORR_EINVAL
+    assert "weight" in str(e.value)
+    p.close()
