@@ -189,6 +189,25 @@ int corr_profile_read(corr_ctx* ctx, double* ms, int64_t* launches, int32_t n_st
 int corr_query(corr_ctx* ctx, const double* quat_wxyz, const double* t_host, int64_t n_t, int32_t mode_radius2,
                float* out_dev, int64_t* n_modes);
 
+/*
+ * corr_query for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same arguments,
+ * kernels and summation order as corr_query, hence bitwise its results, but no
+ * device, pinned or host heap allocation.  Its device buffers come from one
+ * static device array of 32 MiB per GPU (held by each GPU the library runs on
+ * until the process ends), shared by every call on that GPU: calls on one GPU
+ * must not overlap (they would race on it), whatever their contexts and
+ * streams.  The mode list, rotation and translations are copied into it from
+ * the caller's host memory (pageable copies on the context's stream; the
+ * caller's arrays may be reused on return).  Limits: at most 65536 half-space
+ * modes (mode_radius2 up to about 630 on grids with n >= 64), and all buffers
+ * of the call within the 32 MiB (about 8 n_modes x ceil(n_B / 256) + 28 n_t
+ * bytes); a larger request fails with CORR_EUNSUPPORTED before any device
+ * work.  Other errors as corr_query.
+ */
+int corr_query_noalloc(corr_ctx* ctx, const double* quat_wxyz, const double* t_host, int64_t n_t,
+                       int32_t mode_radius2, float* out_dev, int64_t* n_modes);
+
 /* ---- configuration obstacles and offset slices --------------------------- */
 
 #define CORR_MAX_SLICES 16

@@ -32,8 +32,8 @@ CORR_TUNE_WITH_A = 1
 CORR_MAX_SLICES = 16
 
 EXPORTS = ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
-           "corr_profile_read", "corr_pass_info", "corr_query", "corr_set_offsets", "corr_eval_slices",
-           "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune",
+           "corr_profile_read", "corr_pass_info", "corr_query", "corr_query_noalloc", "corr_set_offsets",
+           "corr_eval_slices", "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune",
            "corr_destroy", "corr_last_error",
            "corr_batch_create",
            "corr_batch_eval", "corr_batch_set_graph",
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
     lib.corr_profile_read.argtypes = [vp, vp, vp, i32]
     lib.corr_pass_info.argtypes = [vp, ctypes.POINTER(corr_pass_t)]
     lib.corr_query.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.corr_query_noalloc.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(ctypes.c_int64)]
     lib.corr_set_offsets.argtypes = [vp, vp, i32]
     lib.corr_eval_slices.argtypes = [vp, vp, i64, ctypes.POINTER(corr_slices_out)]
     lib.corr_get_tuning.argtypes = [vp, ctypes.POINTER(corr_tuning)]
@@ -113,8 +114,8 @@ def load_library(path: str = LIB_PATH):
     lib.corr_last_error.argtypes = [vp]
     lib.corr_last_error.restype = ctypes.c_char_p
     for name in ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
-                 "corr_profile_read", "corr_pass_info", "corr_query", "corr_set_offsets", "corr_eval_slices",
-                 "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune", "corr_destroy"):
+                 "corr_profile_read", "corr_pass_info", "corr_query", "corr_query_noalloc", "corr_set_offsets",
+                 "corr_eval_slices", "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune", "corr_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -188,6 +189,16 @@ def corr_query(ctx, quat, t, mode_radius2, out_ptr) -> int:
     nm = ctypes.c_int64()
     _check(load_library().corr_query(ctx, q.ctypes.data, t.ctypes.data if len(t) else None, len(t), int(mode_radius2),
                                      out_ptr or None, ctypes.byref(nm)), ctx)
+    return nm.value
+
+
+def corr_query_noalloc(ctx, quat, t, mode_radius2, out_ptr) -> int:
+    """corr_query without allocation (static per-device scratch); returns the number of modes summed."""
+    q = np.ascontiguousarray(np.asarray(quat, dtype=np.float64).reshape(4))
+    t = np.ascontiguousarray(np.asarray(t, dtype=np.float64).reshape(-1, 3))
+    nm = ctypes.c_int64()
+    _check(load_library().corr_query_noalloc(ctx, q.ctypes.data, t.ctypes.data if len(t) else None, len(t),
+                                             int(mode_radius2), out_ptr or None, ctypes.byref(nm)), ctx)
     return nm.value
 
 

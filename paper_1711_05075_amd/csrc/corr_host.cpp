@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1626,6 +1627,137 @@ int corr_query(corr_ctx* c, const double* quat_wxyz, const double* t_host, int64
             return corr::launch_query(g, qp, static_cast<const int*>(c->q_modes.p), nm, dq, B.pos, B.wts, B.n,
                                       B.ex.q, B.vtab, c->box, part, c->fa, P, dt, n_t, tpart, out_dev, c->stream);
         });
+    });
+}
+
+// ---------------------------------------------------------------------------
+// corr_query_noalloc: corr_query without any allocation.  Its device buffers
+// (mode list, rotation, translations and the three partial-sum arrays of the
+// query kernels) are carved out of one file-scope device array, `scratch`, of
+// kNoAllocScratch bytes, which each GPU the library runs on holds until the
+// process ends.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is taken once per device with
+// hipGetSymbolAddress (that device current) and only that address is used.
+// The host side works in fixed static arrays under a mutex, so the call makes
+// no device, pinned or heap allocation.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kNoAllocScratch = (size_t)32 << 20;  // bytes of scratch per device
+constexpr int kNoAllocModes = 1 << 16;                 // half-space modes per call
+constexpr int kNoAllocDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+std::mutex g_noalloc_mu;                      // guards everything below
+void* g_scratch_dev[kNoAllocDevices] = {};    // scratch's device address per device
+uint64_t g_mode_keys[kNoAllocModes];          // (|m|^2, mz, my, mx) sort keys
+int g_mode_list[kNoAllocModes];               // packed modes, as query_modes
+
+// Device address of `scratch` on `dev` (looked up once, with dev current).
+void* scratch_on(int dev) {
+    if (dev < 0 || dev >= kNoAllocDevices) fail(CORR_EUNSUPPORTED, "device %d: no scratch slot", dev);
+    if (g_scratch_dev[dev]) return g_scratch_dev[dev];
+    int cur = 0;
+    hip_check(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != dev) hip_check(hipSetDevice(dev), "hipSetDevice");
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    hip_check(e, "hipGetSymbolAddress (scratch)");
+    if (!ptr) fail(CORR_EHIP, "hipGetSymbolAddress (scratch): null address");
+    g_scratch_dev[dev] = ptr;
+    return ptr;
+}
+
+// The half-space modes of query_modes, in the same shell order, into
+// g_mode_list without allocating; returns the count (fails past the cap) and
+// the full-sphere count in *full.
+int query_modes_static(int n, int32_t r2, int64_t* full) {
+    const int h = n / 2 - 1;
+    int rad = 0;
+    while (rad < h && (int64_t)(rad + 1) * (rad + 1) <= r2) ++rad;
+    int nm = 0;
+    for (int mz = -rad; mz <= rad; ++mz)
+        for (int my = -rad; my <= rad; ++my)
+            for (int mx = 0; mx <= rad; ++mx) {
+                const int m2 = mx * mx + my * my + mz * mz;
+                if (m2 > r2) continue;
+                if (!(mx > 0 || (mx == 0 && (my > 0 || (my == 0 && mz >= 0))))) continue;
+                if (nm == kNoAllocModes)
+                    fail(CORR_EUNSUPPORTED, "mode_radius2 = %d keeps more than %d half-space modes, the most "
+                                            "corr_query_noalloc takes", r2, kNoAllocModes);
+                g_mode_keys[nm++] = ((uint64_t)m2 << 30) | ((uint64_t)(mz + 512) << 20) |
+                                    ((uint64_t)(my + 512) << 10) | (uint64_t)(mx + 512);
+            }
+    std::sort(g_mode_keys, g_mode_keys + nm);  // in place: (|m|^2, mz, my, mx)
+    for (int i = 0; i < nm; ++i) {
+        const uint64_t k = g_mode_keys[i];
+        g_mode_list[i] = (int)(k & 1023) | ((int)((k >> 10) & 1023) << 10) | ((int)((k >> 20) & 1023) << 20);
+    }
+    *full = 2 * (int64_t)nm - 1;
+    return nm;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+int corr_query_noalloc(corr_ctx* c, const double* quat_wxyz, const double* t_host, int64_t n_t,
+                       int32_t mode_radius2, float* out_dev, int64_t* n_modes) {
+    if (!c) {
+        g_thread_error = "corr_query_noalloc: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] {
+        if (n_t < 0 || n_t > INT32_MAX) fail(CORR_EINVAL, "n_t = %lld; allowed 0..2^31-1", (long long)n_t);
+        if (mode_radius2 < 0) fail(CORR_EINVAL, "mode_radius2 must be >= 0");
+        if (n_t > 0 && (!t_host || !out_dev)) fail(CORR_EINVAL, "NULL translations or output");
+        validate_quats(quat_wxyz, 1);
+        for (int64_t i = 0; i < 3 * n_t; ++i)
+            if (!std::isfinite(t_host[i])) fail(CORR_EINVAL, "translation %lld is not finite", (long long)(i / 3));
+        const Geom& g = c->g;
+        const int32_t full = 3 * (g.n / 2 - 1) * (g.n / 2 - 1);
+        const int32_t r2 = std::min(mode_radius2, full);
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        int64_t nfull = 0;
+        const int nm = query_modes_static(g.n, r2, &nfull);
+        if (n_modes) *n_modes = nfull;
+        if (n_t == 0) return;
+        const Shape& B = c->B;
+        const corr::QueryPlan qp = corr::query_plan(nm, B.n, n_t);
+        // scratch layout: modes, rotation, translations, chunk sums, mode
+        // products, translation partial sums (each 256-byte aligned)
+        const size_t b_modes = align256(sizeof(int) * nm), b_quat = align256(sizeof(double) * 4),
+                     b_t = align256(sizeof(double) * 3 * (size_t)n_t),
+                     b_part = align256(sizeof(float2) * (size_t)nm * qp.chunks), b_P = align256(sizeof(float2) * nm),
+                     b_tpart = align256(sizeof(float) * (size_t)n_t * qp.mblocks);
+        const size_t need = b_modes + b_quat + b_t + b_part + b_P + b_tpart;
+        if (need > kNoAllocScratch)
+            fail(CORR_EUNSUPPORTED, "this query needs %zu bytes of scratch; corr_query_noalloc holds %zu per device "
+                                    "(use fewer modes or translations, or corr_query)", need, kNoAllocScratch);
+        auto* base = static_cast<unsigned char*>(scratch_on(c->device));
+        int* d_modes = reinterpret_cast<int*>(base);
+        double* dq = reinterpret_cast<double*>(base + b_modes);
+        double* dt = reinterpret_cast<double*>(base + b_modes + b_quat);
+        auto* part = reinterpret_cast<float2*>(base + b_modes + b_quat + b_t);
+        auto* P = reinterpret_cast<float2*>(base + b_modes + b_quat + b_t + b_part);
+        auto* tpart = reinterpret_cast<float*>(base + b_modes + b_quat + b_t + b_part + b_P);
+        join_a(c);  // F_A is read below
+        // pageable copies: each returns once its source may be reused; every
+        // kernel below writes what it later reads, so nothing needs clearing
+        hip_check(hipMemcpyAsync(d_modes, g_mode_list, sizeof(int) * nm, hipMemcpyHostToDevice, c->stream),
+                  "mode list H2D");
+        hip_check(hipMemcpyAsync(dq, quat_wxyz, sizeof(double) * 4, hipMemcpyHostToDevice, c->stream), "quat H2D");
+        hip_check(hipMemcpyAsync(dt, t_host, sizeof(double) * 3 * n_t, hipMemcpyHostToDevice, c->stream),
+                  "translations H2D");
+        hip_check(corr::launch_query(g, qp, d_modes, nm, dq, B.pos, B.wts, B.n, B.ex.q, B.vtab, c->box, part, c->fa, P,
+                                     dt, n_t, tpart, out_dev, c->stream),
+                  "query");
     });
 }
 
