@@ -279,6 +279,16 @@ typedef struct {
 
 int corr_pass_info(corr_ctx* ctx, corr_pass_t* out);
 
+/* Work of the spreading launches (stage CORR_STAGE_SPREAD_FFT_X) since the
+ * last read, which clears it: out[0] bytes of kept x modes written (live tiles
+ * only, counted by the kernel on the device), out[1] bytes of the sorted knot
+ * records of the passes (cell, 3 w window weights and q component weights per
+ * knot and rotation), out[2] launches; A's side-stream passes included.
+ * These are the algorithmic bytes of the spreading kernel: each record read
+ * once, each kept mode written once.  Counted in graph replays too.
+ * Synchronises the context's stream.  out: host int64 [3]. */
+int corr_spread_work(corr_ctx* ctx, int64_t* out);
+
 /* ---- launch shapes, autotuning and graph replay --------------------------- */
 
 /*
@@ -385,6 +395,13 @@ int corr_batch_eval(corr_batch* b, const double* quat_wxyz, const int64_t* rot_o
 int corr_batch_set_graph(corr_batch* b, int32_t enable);
 
 int corr_batch_info(const corr_batch* b, int32_t pair, corr_info_t* out);
+
+/* corr_profile / corr_profile_read over every pair of the batch (the read
+ * sums the pairs' stage times and launch counts), and corr_spread_work of the
+ * batch's shared workspace. */
+int corr_batch_profile(corr_batch* b, int32_t enable);
+int corr_batch_profile_read(corr_batch* b, double* ms, int64_t* launches, int32_t n_stages);
+int corr_batch_spread_work(corr_batch* b, int64_t* out);
 int corr_batch_destroy(corr_batch* b);
 const char* corr_batch_last_error(const corr_batch* b);
 

@@ -62,8 +62,19 @@ def _load():
         lib.orc_o1_points.argtypes = [p, i64, p, i64, p, p, i64, p]
         lib.orc_o1_grid.argtypes = [p, i64, p, i64, p, p, d, i32, p]
         lib.orc_o2_spectrum.argtypes = [p, i64, p, i32, d, p, p]
+        lib.orc_set_threads.argtypes = [i32]
+        lib.orc_get_threads.restype = i32
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (for timing; results do not depend on it)."""
+    _load().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())
 
 
 def _f64(a) -> np.ndarray:

@@ -31,6 +31,7 @@
  * Python with an FP64 FFT.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -233,3 +234,9 @@ void orc_o2_spectrum(const double *balls, int64_t nb, const double *R, int n, do
     }
     free(bt); free(ef); free(cw);
 }
+
+/* Threads of the OpenMP loops above (timing only: results do not depend on
+ * it, every output element is summed by one thread in a fixed order). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
+int orc_get_threads(void) { return omp_get_max_threads(); }

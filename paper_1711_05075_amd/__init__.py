@@ -33,11 +33,12 @@ CORR_MAX_SLICES = 16
 
 EXPORTS = ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
            "corr_profile_read", "corr_pass_info", "corr_query", "corr_query_noalloc", "corr_set_offsets",
-           "corr_eval_slices", "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune",
+           "corr_eval_slices", "corr_spread_work", "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune",
            "corr_destroy", "corr_last_error",
            "corr_batch_create",
            "corr_batch_eval", "corr_batch_set_graph",
-           "corr_batch_info", "corr_batch_destroy", "corr_batch_last_error")
+           "corr_batch_info", "corr_batch_profile", "corr_batch_profile_read", "corr_batch_spread_work",
+           "corr_batch_destroy", "corr_batch_last_error")
 STAGES = ("rotate", "bin", "spread_fft_x", "fft_y", "fft_z_spectrum", "fft_z_product", "ifft_y", "ifft_x", "peak",
           "query", "graph")
 
@@ -102,6 +103,7 @@ def load_library(path: str = LIB_PATH):
     lib.corr_profile.argtypes = [vp, i32]
     lib.corr_profile_read.argtypes = [vp, vp, vp, i32]
     lib.corr_pass_info.argtypes = [vp, ctypes.POINTER(corr_pass_t)]
+    lib.corr_spread_work.argtypes = [vp, vp]
     lib.corr_query.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(ctypes.c_int64)]
     lib.corr_query_noalloc.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(ctypes.c_int64)]
     lib.corr_set_offsets.argtypes = [vp, vp, i32]
@@ -115,7 +117,7 @@ def load_library(path: str = LIB_PATH):
     lib.corr_last_error.restype = ctypes.c_char_p
     for name in ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
                  "corr_profile_read", "corr_pass_info", "corr_query", "corr_query_noalloc", "corr_set_offsets",
-                 "corr_eval_slices", "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune", "corr_destroy"):
+                 "corr_eval_slices", "corr_spread_work", "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune", "corr_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -180,6 +182,13 @@ def corr_pass_info(ctx) -> dict:
     r = corr_pass_t()
     _check(load_library().corr_pass_info(ctx, ctypes.byref(r)), ctx)
     return {k: getattr(r, k) for k, _ in corr_pass_t._fields_}
+
+
+def corr_spread_work(ctx) -> dict:
+    """Spreading work since the last read: bytes written, record bytes read, launches."""
+    out = np.zeros(3, dtype=np.int64)
+    _check(load_library().corr_spread_work(ctx, out.ctypes.data), ctx)
+    return {"written_bytes": int(out[0]), "record_bytes": int(out[1]), "launches": int(out[2])}
 
 
 def corr_query(ctx, quat, t, mode_radius2, out_ptr) -> int:
@@ -551,7 +560,8 @@ class Proposer:
 
 # ---- uneven batches (corr_batch_*) ---------------------------------------------
 
-BATCH_EXPORTS = ("corr_batch_create", "corr_batch_eval", "corr_batch_set_graph", "corr_batch_info", "corr_batch_destroy",
+BATCH_EXPORTS = ("corr_batch_create", "corr_batch_eval", "corr_batch_set_graph", "corr_batch_info",
+                 "corr_batch_profile", "corr_batch_profile_read", "corr_batch_spread_work", "corr_batch_destroy",
                  "corr_batch_last_error")
 
 
@@ -568,6 +578,9 @@ def _batch_lib():
         lib.corr_batch_eval.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         lib.corr_batch_set_graph.argtypes = [vp, i32]
         lib.corr_batch_info.argtypes = [vp, i32, ctypes.POINTER(corr_info_t)]
+        lib.corr_batch_profile.argtypes = [vp, i32]
+        lib.corr_batch_profile_read.argtypes = [vp, vp, vp, i32]
+        lib.corr_batch_spread_work.argtypes = [vp, vp]
         lib.corr_batch_destroy.argtypes = [vp]
         lib.corr_batch_last_error.argtypes = [vp]
         lib.corr_batch_last_error.restype = ctypes.c_char_p
@@ -617,6 +630,25 @@ def corr_batch_info(b, pair) -> dict:
     info = corr_info_t()
     _bcheck(_batch_lib().corr_batch_info(b, int(pair), ctypes.byref(info)), b)
     return {k: getattr(info, k) for k, _ in corr_info_t._fields_}
+
+
+def corr_batch_profile(b, enable):
+    _bcheck(_batch_lib().corr_batch_profile(b, int(bool(enable))), b)
+
+
+def corr_batch_profile_read(b) -> dict:
+    """Per stage name: (summed ms, launches) since the last read, over every pair."""
+    n = len(STAGES)
+    ms = np.zeros(n)
+    cnt = np.zeros(n, dtype=np.int64)
+    _bcheck(_batch_lib().corr_batch_profile_read(b, ms.ctypes.data, cnt.ctypes.data, n), b)
+    return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
+def corr_batch_spread_work(b) -> dict:
+    out = np.zeros(3, dtype=np.int64)
+    _bcheck(_batch_lib().corr_batch_spread_work(b, out.ctypes.data), b)
+    return {"written_bytes": int(out[0]), "record_bytes": int(out[1]), "launches": int(out[2])}
 
 
 def corr_batch_destroy(b):

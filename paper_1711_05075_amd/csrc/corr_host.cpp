@@ -340,6 +340,7 @@ struct Workspace {
     int* bin_start = nullptr;      // [slots][keys + 1] first sorted knot of each key
     unsigned char* tile_live = nullptr;  // [slots][m][y tiles] spreading tiles that some knot reaches
     int* plan = nullptr;           // bucket sizes and work counter of the spreading pass's live-tile plan
+    unsigned long long* work = nullptr;  // [3] spreading work since the last read (corr_spread_work)
     int* list = nullptr;           // [buckets][slots * tiles] live tiles
     int* scell = nullptr;          // [slots][nk] sorted by z-cell: packed cell
     float* skbw = nullptr;         // [slots][nk][3][w]              window weights
@@ -368,6 +369,8 @@ struct Workspace {
         bin_start = mem.alloc<int>(S * r.bins);
         tile_live = mem.alloc<unsigned char>(S * r.tiles);
         plan = mem.alloc<int>(corr::plan_words());
+        work = mem.alloc<unsigned long long>(3);
+        hip_check(hipMemsetAsync(work, 0, 3 * sizeof(unsigned long long), st), "hipMemsetAsync");
         list = mem.alloc<int>(S * r.list);
         scell = mem.alloc<int>(S * r.nk);
         skbw = mem.alloc<float>(S * r.nkw);
@@ -621,7 +624,7 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
     });
     stage(c, CORR_STAGE_SPREAD_FFT_X, "spread + fft x", [&] {
         return corr::launch_spread_fftx(g, S, occupancy(c, s), c->ws->plan, c->ws->list, c->ws->scell, c->ws->skbw,
-                                        c->ws->swts, q, s.fix_scale, c->ws->buf1, c->twm, c->stream);
+                                        c->ws->swts, q, s.fix_scale, c->ws->buf1, c->twm, c->ws->work, c->stream);
     });
     stage(c, CORR_STAGE_FFT_Y, "fft y", [&] {
         return corr::launch_fft_y(g, S, q, occupancy(c, s), c->ws->buf1, reinterpret_cast<float2*>(c->ws->buf0),
@@ -1491,6 +1494,36 @@ int corr_profile_read(corr_ctx* c, double* ms, int64_t* launches, int32_t n_stag
     });
 }
 
+namespace {
+
+// Add a workspace's spreading work record into out[3] and clear it (the
+// stream that used it has drained).
+void take_work(corr::Workspace* w, hipStream_t st, int64_t* out) {
+    if (!w || !w->work) return;
+    unsigned long long v[3] = {0, 0, 0};
+    hip_check(hipMemcpy(v, w->work, sizeof v, hipMemcpyDeviceToHost), "work record D2H");
+    for (int k = 0; k < 3; ++k) out[k] += (int64_t)v[k];
+    hip_check(hipMemsetAsync(w->work, 0, sizeof v, st), "hipMemsetAsync");
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
+}  // namespace
+
+int corr_spread_work(corr_ctx* c, int64_t* out) {
+    if (!c) {
+        g_thread_error = "corr_spread_work: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] {
+        if (!out) fail(CORR_EINVAL, "out is NULL");
+        out[0] = out[1] = out[2] = 0;
+        join_a(c);  // A's side-stream passes complete before a_done
+        hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+        if (c->own_ws) take_work(c->ws, c->stream, out);
+        take_work(c->ws_a, c->stream, out);
+    });
+}
+
 int corr_pass_info(corr_ctx* c, corr_pass_t* out) {
     if (!c) {
         g_thread_error = "corr_pass_info: NULL context";
@@ -1879,6 +1912,58 @@ int corr_batch_set_graph(corr_batch* b, int32_t enable) {
         return CORR_EINVAL;
     }
     b->graph = enable != 0;
+    return CORR_OK;
+}
+
+int corr_batch_spread_work(corr_batch* b, int64_t* out) {
+    if (!b || !out) {
+        g_thread_error = "corr_batch_spread_work: NULL batch or output";
+        return CORR_EINVAL;
+    }
+    int rc = guarded(nullptr, [&] {
+        out[0] = out[1] = out[2] = 0;
+        hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        take_work(&b->ws, b->stream, out);
+    });
+    if (rc != CORR_OK) b->err = g_thread_error;
+    return rc;
+}
+
+int corr_batch_profile(corr_batch* b, int32_t enable) {
+    if (!b) {
+        g_thread_error = "corr_batch_profile: NULL batch";
+        return CORR_EINVAL;
+    }
+    for (corr_ctx* c : b->pairs) c->profiling = enable != 0;
+    return CORR_OK;
+}
+
+int corr_batch_profile_read(corr_batch* b, double* ms, int64_t* launches, int32_t n_stages) {
+    if (!b) {
+        g_thread_error = "corr_batch_profile_read: NULL batch";
+        return CORR_EINVAL;
+    }
+    if (n_stages < 0 || (n_stages > 0 && (!ms || !launches))) {
+        b->err = "corr_batch_profile_read: bad output arrays";
+        return CORR_EINVAL;
+    }
+    std::vector<double> pm((size_t)n_stages);
+    std::vector<int64_t> pl((size_t)n_stages);
+    for (int i = 0; i < n_stages; ++i) {
+        ms[i] = 0;
+        launches[i] = 0;
+    }
+    for (corr_ctx* c : b->pairs) {
+        const int rc = corr_profile_read(c, pm.data(), pl.data(), n_stages);
+        if (rc != CORR_OK) {
+            b->err = c->err;
+            return rc;
+        }
+        for (int i = 0; i < n_stages; ++i) {
+            ms[i] += pm[i];
+            launches[i] += pl[i];
+        }
+    }
     return CORR_OK;
 }
 

@@ -84,10 +84,13 @@ hipError_t launch_scatter_plan(const Geom& g, int S, int q, const Occupancy& occ
 // Sums are exact 64-bit fixed point of 32-bit addends; fix_scale is a power of
 // two with fix_scale * max_{i,c} |wts[c][i]| <= 2^30.
 // Runs g.spread_wgs persistent workgroups over the plan's tiles; a listed tile
-// that no knot reaches only records that in occ.tile_live.
+// that no knot reaches only records that in occ.tile_live.  Adds its work to
+// d_work[3]: bytes of kept x modes written (live tiles only), bytes of sorted
+// knot records (cell, window weights, component weights) of the pass, and 1
+// launch.
 hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, int* d_plan, const int* d_list,
                               const int* d_scell, const float* d_skbw, const float* d_swts, int q, float fix_scale,
-                              float2* d_out, const float2* d_twm, hipStream_t st);
+                              float2* d_out, const float2* d_twm, unsigned long long* d_work, hipStream_t st);
 // Largest dynamic LDS any stage asks for.
 size_t max_lds_bytes(const Geom& g, int qmax);
 // a2: pruned forward y pass of S rotations x q components (live rows only).

@@ -565,62 +565,70 @@ __global__ __launch_bounds__(256) void k_scatter_plan(const int* __restrict__ ce
     tile_plan<M>(((int)blockIdx.x - nscatter) * 256 + threadIdx.x, s, bin_start, w, tile_live, plan, list, list_cap);
 }
 
-// Stage the filtered knots with filtered rank in [first, first + cap); returns
-// the total number of filtered knots.  Entered and left by the whole workgroup.
+// Stage one block of a tile's candidates, [cbeg, cbeg + cnt) of the
+// concatenated key ranges (cnt <= cap <= the workgroup size): those whose
+// window reaches the tile's rows are compacted in order (wave ballots + a
+// block scan) into the staging area with their cell, sorted position, window
+// weights along x and y, the z weight of the tile's row, and the component
+// weights of the pair starting at component cp times that z weight and the
+// fixed-point scale.  Returns how many were kept.  A block never holds more
+// than the staging area, so a tile of many candidates is spread block by
+// block and no candidate is ever scanned twice for one component pair.
+// Entered and left by the whole workgroup.
 template <int M>
-__device__ int stage_knots(const int* __restrict__ sc_, const float* __restrict__ kb_, int w, int y0, int z0,
-                           const int* rstart, const int* rpre, int nr, int first, int cap, SpreadStage st,
+__device__ int stage_block(const int* __restrict__ sc_, const float* __restrict__ kb_,
+                           const float* __restrict__ wq_, int q, int cp, float fix_scale, int w, int y0, int z0,
+                           const int* rstart, const int* rpre, int nr, int cbeg, int cnt, SpreadStage st,
                            int* wave_tot) {
     constexpr int TY = SpreadShape<M>::TY;
     const int lo = w / 2 - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ncand = rpre[nr];
-    int running = 0;
-    for (int base = 0; base < ncand; base += kSpreadThreads) {
-        const int ci = base + threadIdx.x;
-        int p = 0, packed = 0;
-        bool keep = false;
-        if (ci < ncand) {
-            int r0 = 0, r1 = nr;  // the range holding ci: rpre[r0] <= ci < rpre[r0 + 1]
-            while (r1 - r0 > 1) {
-                const int mid = (r0 + r1) >> 1;
-                if (rpre[mid] <= ci) r0 = mid;
-                else r1 = mid;
-            }
-            p = rstart[r0] + (ci - rpre[r0]);
-            packed = sc_[p];
-            const int cy = (packed >> 10) & 1023;
-            const int ry = (cy - lo - y0 + 2 * M) & (M - 1);
-            keep = ry < TY || ry > M - w;
+    int p = 0, packed = 0;
+    bool keep = false;
+    if ((int)threadIdx.x < cnt) {
+        const int ci = cbeg + (int)threadIdx.x;
+        int r0 = 0, r1 = nr;  // the range holding ci: rpre[r0] <= ci < rpre[r0 + 1]
+        while (r1 - r0 > 1) {
+            const int mid = (r0 + r1) >> 1;
+            if (rpre[mid] <= ci) r0 = mid;
+            else r1 = mid;
         }
-        const unsigned long long mask = __ballot(keep);
-        const int before = __popcll(mask & ((1ull << lane) - 1ull));
-        if (lane == 0) wave_tot[wave] = __popcll(mask);
-        __syncthreads();
-        int off = running, total = 0;
-#pragma unroll
-        for (int v = 0; v < kSpreadThreads / 64; ++v) {
-            off += v < wave ? wave_tot[v] : 0;
-            total += wave_tot[v];
-        }
-        const int rk = off + before - first;
-        if (keep && rk >= 0 && rk < cap) {
-            st.cell[rk] = packed;
-            st.pos[rk] = p;
-            const float2* kw = reinterpret_cast<const float2*>(kb_ + (int64_t)p * 3 * w);
-            float2* dx = reinterpret_cast<float2*>(st.wx + rk * w);
-            float2* dy = reinterpret_cast<float2*>(st.wy + rk * w);
-            for (int d = 0; d < w / 2; ++d) {
-                dx[d] = kw[d];
-                dy[d] = kw[w / 2 + d];
-            }
-            const int cz = (packed >> 20) & 1023;
-            st.wz[rk] = kb_[(int64_t)p * 3 * w + 2 * w + ((z0 - cz + lo + M) & (M - 1))];
-        }
-        running += total;
-        __syncthreads();
+        p = rstart[r0] + (ci - rpre[r0]);
+        packed = sc_[p];
+        const int cy = (packed >> 10) & 1023;
+        const int ry = (cy - lo - y0 + 2 * M) & (M - 1);
+        keep = ry < TY || ry > M - w;
     }
-    return running;
+    const unsigned long long mask = __ballot(keep);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_tot[wave] = __popcll(mask);
+    __syncthreads();
+    int off = 0, total = 0;
+#pragma unroll
+    for (int v = 0; v < kSpreadThreads / 64; ++v) {
+        off += v < wave ? wave_tot[v] : 0;
+        total += wave_tot[v];
+    }
+    if (keep) {
+        const int rk = off + before;
+        st.cell[rk] = packed;
+        st.pos[rk] = p;
+        const float2* kw = reinterpret_cast<const float2*>(kb_ + (int64_t)p * 3 * w);
+        float2* dx = reinterpret_cast<float2*>(st.wx + rk * w);
+        float2* dy = reinterpret_cast<float2*>(st.wy + rk * w);
+        for (int d = 0; d < w / 2; ++d) {
+            dx[d] = kw[d];
+            dy[d] = kw[w / 2 + d];
+        }
+        const int cz = (packed >> 20) & 1023;
+        const float wz = kb_[(int64_t)p * 3 * w + 2 * w + ((z0 - cz + lo + M) & (M - 1))];
+        st.wz[rk] = wz;
+        const float* wp = wq_ + (int64_t)p * q + cp;
+        const float f = wz * fix_scale;
+        st.wq[rk] = make_float2(wp[0] * f, cp + 1 < q ? wp[1] * f : 0.0f);
+    }
+    __syncthreads();
+    return total;
 }
 
 // Exact int64 -> double split (hi * 2^32 + lo), then one rounding to float.
@@ -634,7 +642,7 @@ __device__ __forceinline__ float fixed_to_float(unsigned long long u, float inv)
 // components c0 .. c1-1 (c0 even).  Entered by the whole workgroup; the LDS
 // regions are laid out by the caller.
 template <int M>
-__device__ void spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const int* __restrict__ bin_start,
+__device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const int* __restrict__ bin_start,
                             unsigned char* __restrict__ tile_live, const int* __restrict__ scell,
                             const float* __restrict__ skbw, const float* __restrict__ swts, int64_t nk, int q, int w,
                             int cap, float fix_scale, float fix_inv, float2* __restrict__ out, float2* lds,
@@ -644,7 +652,6 @@ __device__ void spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
     constexpr int TY = SS::TY, SC = SS::SC, NPTS = SS::NPTS, LS = SS::LS;
     constexpr int NT = kSpreadThreads, NW = NT / 64;
     constexpr int U = 4;         // staged knots in flight per wave
-    constexpr int CV = NPTS / NT;  // sums converted per thread
     static_assert(NPTS % NT == 0, "tile must split evenly over the workgroup");
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds);  // [2][TY][LS]
     float2* a = lds;                                                       // [TY][SC] over the sums
@@ -665,36 +672,38 @@ __device__ void spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
     const float* wq_ = swts + (int64_t)s * nk * q;
     tile_ranges<M>(bin_start + (size_t)s * (SS::KEYS + 1), w, y0, z0, rstart, rpre);
     __syncthreads();
-    const int nfilt = rpre[nr] > 0 ? stage_knots<M>(sc_, kb_, w, y0, z0, rstart, rpre, nr, 0, cap, st, wave_tot) : 0;
-    if (threadIdx.x == 0) tile_live[((size_t)s * M + z0) * (M / TY) + yt] = nfilt > 0;
-    if (nfilt == 0) return;  // the tile's spectrum is zero and is not written
-    for (int t = threadIdx.x; t < 2 * TY * LS; t += NT) acc[t] = 0ull;
-    const int rounds = (nfilt + cap - 1) / cap;
-    // component weights of the pair starting at component c for staged knot i,
-    // times the z weight and the fixed-point scale
-    auto pair_weights = [&](int i, int c) {
-        const float* wp = wq_ + (int64_t)st.pos[i] * q + c;
-        const float f = st.wz[i] * fix_scale;
-        return make_float2(wp[0] * f, c + 1 < q ? wp[1] * f : 0.0f);
+    const int ncand = rpre[nr];
+    // candidates are spread in blocks of `cap` (one staging each): a tile of one
+    // block is staged once for all its component pairs, a tile of several is
+    // staged block by block for each pair
+    const int nblk = (ncand + cap - 1) / cap;
+    auto stage = [&](int b, int cp) {
+        return stage_block<M>(sc_, kb_, wq_, q, cp, fix_scale, w, y0, z0, rstart, rpre, nr, b * cap,
+                              min(cap, ncand - b * cap), st, wave_tot);
     };
-    if (rounds == 1) {
-        for (int i = threadIdx.x; i < nfilt; i += NT) st.wq[i] = pair_weights(i, c0);
+    int kept = nblk == 1 ? stage(0, c0) : 0;  // the single block, staged with the first pair's weights
+    if (ncand == 0 || (nblk == 1 && kept == 0)) {
+        if (threadIdx.x == 0) tile_live[((size_t)s * M + z0) * (M / TY) + yt] = 0;
+        return false;  // no knot reaches the tile: its spectrum is zero and is not written
     }
+    int kept_all = 0;  // knots of the tile (counted while spreading the first pair)
+    for (int t = threadIdx.x; t < 2 * TY * LS; t += NT) acc[t] = 0ull;
     for (int cp = c0; cp < c1; cp += 2) {
-        // with every knot staged, the next pair's weights are read while this
-        // pair is spread (a thread per staged knot)
-        const bool prefetch = rounds == 1 && cp + 2 < c1 && (int)threadIdx.x < nfilt;
+        // with one block, the next pair's weights are read (a thread per staged
+        // knot) while this pair is spread
+        const bool prefetch = nblk == 1 && cp + 2 < c1 && (int)threadIdx.x < kept;
         float2 nxt = make_float2(0.f, 0.f);
         static_assert(kSpreadThreads >= 512, "one staged knot per thread");
-        for (int r = 0; r < rounds; ++r) {
-            if (rounds > 1) {
-                if (r > 0 || cp > c0)
-                    stage_knots<M>(sc_, kb_, w, y0, z0, rstart, rpre, nr, r * cap, cap, st, wave_tot);
-                for (int i = threadIdx.x; i < min(cap, nfilt - r * cap); i += NT) st.wq[i] = pair_weights(i, cp);
+        for (int b = 0; b < nblk; ++b) {
+            if (nblk > 1) kept = stage(b, cp);  // ends with a barrier
+            else __syncthreads();               // the staged weights (first pair) or the prefetched ones
+            if (cp == c0) kept_all += kept;
+            if (prefetch) {
+                const float* wp = wq_ + (int64_t)st.pos[threadIdx.x] * q + cp + 2;
+                const float f = st.wz[threadIdx.x] * fix_scale;
+                nxt = make_float2(wp[0] * f, cp + 3 < q ? wp[1] * f : 0.0f);
             }
-            if (prefetch) nxt = pair_weights(threadIdx.x, cp + 2);
-            __syncthreads();
-            const int nst = min(cap, nfilt - r * cap);
+            const int nst = kept;
             // each wave takes U staged knots at a time, a lane per window point;
             // the LDS reads of all U (at clamped, valid indices) are issued
             // together, then the atomic adds of the lanes that land in the tile
@@ -728,23 +737,36 @@ __device__ void spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
             }
             __syncthreads();
         }
+        if (cp == c0) {
+            // a tile whose candidates all miss its rows: dead, nothing written
+            if (threadIdx.x == 0) tile_live[((size_t)s * M + z0) * (M / TY) + yt] = kept_all > 0;
+            if (kept_all == 0) return false;
+        }
         if (prefetch) st.wq[threadIdx.x] = nxt;  // read from the next pair on, after the barriers below
-        // sums -> FFT input over the same memory
-        float2 cv[CV];
+        // sums -> FFT input over the same memory, fused with the first radix-8
+        // pass of the x transform: each thread converts the eight points of its
+        // first butterfly and transforms them in registers
+        {
+            constexpr int NB0 = M / 8, WORK0 = TY * NB0;
+            static_assert(WORK0 <= NT, "one first-pass butterfly per thread");
+            const int c = threadIdx.x % TY, jb = threadIdx.x / TY;
+            float2 v0[8];
+            if ((int)threadIdx.x < WORK0) {
 #pragma unroll
-        for (int k = 0; k < CV; ++k) {
-            const int t = k * NT + threadIdx.x;
-            const int e = (t / M) * LS + t % M;
-            cv[k] = make_float2(fixed_to_float(acc[e], fix_inv), fixed_to_float(acc[TY * LS + e], fix_inv));
-        }
-        __syncthreads();
+                for (int r = 0; r < 8; ++r) {
+                    const int e = c * LS + jb + r * NB0;
+                    v0[r] = make_float2(fixed_to_float(acc[e], fix_inv), fixed_to_float(acc[TY * LS + e], fix_inv));
+                }
+                dft8<-1>(v0);
+            }
+            __syncthreads();
+            if ((int)threadIdx.x < WORK0) {
 #pragma unroll
-        for (int k = 0; k < CV; ++k) {
-            const int t = k * NT + threadIdx.x;
-            a[(t / M) * SC + t % M] = cv[k];
+                for (int r = 0; r < 8; ++r) a[c * SC + jb * 8 + r] = v0[r];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        fft_cols<M, -1, TY, true, NT>(a, twl);
+        fft_passes<M, 8, -1, TY, 1, SC, NT>(a, twl);
         constexpr int PER = TY * H;
         for (int t = threadIdx.x; t < 2 * PER; t += NT) {
             const int comp = t >= PER;
@@ -762,6 +784,7 @@ __device__ void spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
             for (int t = threadIdx.x; t < 2 * TY * LS; t += NT) acc[t] = 0ull;
         }
     }
+    return true;
 }
 
 // Persistent spreading pass: each workgroup takes work items of the plan's
@@ -783,9 +806,12 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __res
                                                                 const float* __restrict__ swts, int64_t nk, int q,
                                                                 int w, int cap, float fix_scale, float fix_inv,
                                                                 float2* __restrict__ out,
-                                                                const float2* __restrict__ twm) {
+                                                                const float2* __restrict__ twm,
+                                                                unsigned long long* __restrict__ work,
+                                                                unsigned long long rec_bytes) {
     using SS = SpreadShape<M>;
     constexpr int NTY = M / SS::TY, TILES = M * NTY;
+    unsigned long long wrote = 0;  // bytes of kept x modes this workgroup wrote
     extern __shared__ float2 lds[];
     __shared__ int wave_tot[kSpreadThreads / 64];
     __shared__ int rstart[kMaxRanges], rpre[kMaxRanges + 1];
@@ -816,8 +842,18 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __res
         const int s = id / TILES, tile = id % TILES;
         const int ppp = ((q + 1) / 2 + parts[b] - 1) / parts[b];  // component pairs per part
         const int c0 = 2 * part * ppp, c1 = min(c0 + 2 * ppp, q);  // c0 < q as parts <= pairs
-        spread_tile<M>(s, tile / NTY, (tile % NTY) * SS::TY, tile % NTY, c0, c1, bin_start, tile_live, scell, skbw,
-                       swts, nk, q, w, cap, fix_scale, fix_inv, out, lds, wave_tot, rstart, rpre);
+        if (spread_tile<M>(s, tile / NTY, (tile % NTY) * SS::TY, tile % NTY, c0, c1, bin_start, tile_live, scell,
+                           skbw, swts, nk, q, w, cap, fix_scale, fix_inv, out, lds, wave_tot, rstart, rpre))
+            wrote += (unsigned long long)SS::TY * (M / 4) * sizeof(float2) * (c1 - c0);
+    }
+    // work record, summed over launches until the host reads it: bytes of kept
+    // x modes written, sorted knot records read, launches
+    if (threadIdx.x == 0) {
+        if (wrote) atomicAdd(work, wrote);
+        if (blockIdx.x == 0) {
+            atomicAdd(work + 1, rec_bytes);
+            atomicAdd(work + 2, 1ull);
+        }
     }
 }
 
@@ -1632,7 +1668,7 @@ int spread_tiles(const Geom& g) {
 
 hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, int* d_plan, const int* d_list,
                               const int* d_scell, const float* d_skbw, const float* d_swts, int q, float fix_scale,
-                              float2* d_out, const float2* d_twm, hipStream_t st) {
+                              float2* d_out, const float2* d_twm, unsigned long long* d_work, hipStream_t st) {
     if (S == 0 || occ.nk == 0) return hipSuccess;
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
@@ -1640,7 +1676,8 @@ hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, int* d
         hipLaunchKernelGGL(k_spread_fftx<M>, dim3(std::max(1, g.spread_wgs)), dim3(kSpreadThreads),
                            spread_lds_t<M>(g.w), st, occ.bin_start, occ.tile_live, d_plan, d_list, S * tiles, d_scell,
                            d_skbw, d_swts, occ.nk, q, g.w, spread_cap_t<M>(g.w), fix_scale, 1.0f / fix_scale, d_out,
-                           d_twm);
+                           d_twm, d_work,
+                           (unsigned long long)occ.nk * S * (sizeof(int) + 3 * sizeof(float) * g.w + sizeof(float) * q));
     });
 }
 

@@ -1,5 +1,5 @@
 """Measurement tooling on the CPU: the counter summary's arithmetic, its link to
-the kernel source, and the bench's algorithmic byte model."""
+the kernel source, and the bench's roofline arithmetic."""
 import csv
 import os
 
@@ -55,18 +55,20 @@ def test_bench_reads_traffic_only_for_the_current_kernel_source():
     assert rs.kernel_source_digest(src.replace("k_spread_fftx", "k_spread_fftY", 1)) != rs.kernel_source_digest(src)
 
 
-def test_stage_byte_model():
-    n, w = 128, 8
-    info = {"n": n, "kb_width": w}
-    pa = {"q": 10, "knots": 4096, "tile_rows": 8, "m": 256, "live_tiles": 883, "live_rows": 87}
-    pb = dict(pa, live_tiles=903, live_rows=100)
-    b = bench.stage_bytes(info, pa, pb)
-    spec = 8 * n * n * (n // 2)
-    rec = 4096 * (4 + 12 * w + 4 * 10)
-    tile_out = lambda p: p["live_tiles"] * 8 * (256 // 4) * 8 * 10  # noqa: E731
-    assert b["ifft_x"] == spec + 4 * n ** 3
-    assert b["ifft_y"] == 2 * spec
-    assert b["spread_fft_x"] == pytest.approx(rec + (tile_out(pa) + tile_out(pb)) / 2)
-    assert b["fft_z_product"] == pb["live_rows"] * n * (n // 2) * 8 * 10 + 2 * spec
-    # the spreading launch of the committed single-rotation workload: 37.2 MB
-    assert b["spread_fft_x"] == pytest.approx(37.15e6, rel=1e-3)
+def test_roofline_from_the_spreading_work_record():
+    # per-stage event times (ms summed over launches, launches) and the
+    # spreading kernel's own work record: bytes per launch over mean duration
+    prof = {"rotate": (1.0, 4), "spread_fft_x": (8.0, 4), "fft_y": (2.0, 4)}
+    work = {"written_bytes": 3_000_000_000, "record_bytes": 1_000_000_000, "launches": 4}
+    r = bench._roofline(prof, work, None)
+    assert r["kernel"] == "spread_fft_x" and r["launches"] == 4
+    assert r["mean_launch_ms"] == pytest.approx(2.0)
+    assert r["alg_bytes_per_launch"] == pytest.approx(1e9)
+    assert r["achieved"] == pytest.approx(1e9 / 2e-3 / 1e9)  # GB/s
+    assert r["frac"] == pytest.approx(r["achieved"] / bench.HBM_PEAK_GBS)
+    # a work record that does not cover the timed launches gives no figure
+    r = bench._roofline(prof, dict(work, launches=3), None)
+    assert r["achieved"] is None and r["frac"] is None
+    # another dominant stage: timed, but with no byte record of its own
+    r = bench._roofline(dict(prof, fft_y=(20.0, 4)), work, None)
+    assert r["kernel"] == "fft_y" and r["achieved"] is None
