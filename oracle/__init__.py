@@ -17,6 +17,12 @@ Two oracles, both written from Behandish & Ilies (CAD 2016):
   inverse FFT onto an L-periodic translation grid, keeping |m_d| < N/2.
 * ``*_sc_*`` -- the shape-complementarity score (Sec. 4.2 eq. eq_score), built
   from the two above by its definition.
+* ``lift_*`` -- the 4D lifted correlation of Sec. 2.2 (knots lifted to
+  (x, r), each carrying a half-cone, eq. eq_rhoA, eq_L2cone, eq_coneconv) and
+  Sec. 3.1 (one shape r-mirrored, Lemma 2, eq. eq_ORA, eq_convgA): its slice at
+  height h is the sum over pairs of the 4D volume W of the intersection of a
+  downward and an upward cone, in closed form; ``o2_lift_*`` is its
+  band-limited Fourier route.
 * ``obstacle``, ``o1_obstacle_points``, ``offset_balls`` -- the configuration
   obstacle as the positive set of the score (Sec. 3.1 eq. eq_obs), its
   pairwise Minkowski-sum form, and the offset slices (Sec. 3.1).
@@ -62,6 +68,12 @@ def _load():
         lib.orc_o1_points.argtypes = [p, i64, p, i64, p, p, i64, p]
         lib.orc_o1_grid.argtypes = [p, i64, p, i64, p, p, d, i32, p]
         lib.orc_o2_spectrum.argtypes = [p, i64, p, i32, d, p, p]
+        lib.orc_lift_w.restype = d
+        lib.orc_lift_w.argtypes = [d, d]
+        lib.orc_lift_what.restype = d
+        lib.orc_lift_what.argtypes = [d, d]
+        lib.orc_o1_lift_grid.argtypes = [p, i64, p, i64, p, p, d, i32, d, p]
+        lib.orc_o2_lift_spectrum.argtypes = [p, i64, p, i64, p, i32, d, d, p, p]
         lib.orc_set_threads.argtypes = [i32]
         lib.orc_get_threads.restype = i32
         _lib = lib
@@ -304,3 +316,53 @@ def offset_balls(balls, delta) -> np.ndarray:
 def o2_offset_scores(A, B, q, n, L, origin, delta) -> np.ndarray:
     """Band-limited score of the offset slice delta: A's balls offset by delta."""
     return o2_scores(offset_balls(A, delta), B, q, n, L, origin)
+
+
+# ---- 4D lifted correlation (Sec. 2.2, Sec. 3.1) -------------------------------
+
+def lift_w(d, P):
+    """4D volume of the intersection of two opposite cones with axes d apart whose
+    cross-sections' radii sum to P at every height: pi (P^2 - d^2)^2 / 24 for d < P."""
+    lib = _load()
+    d, P = np.broadcast_arrays(np.asarray(d, float), np.asarray(P, float))
+    out = np.array([lib.orc_lift_w(x, y) for x, y in zip(d.ravel(), P.ravel())])
+    return out.reshape(d.shape) if d.shape else float(out[0])
+
+
+def lift_what(k, P):
+    """3D Fourier transform of t -> lift_w(|t|, P) at |k|."""
+    lib = _load()
+    k, P = np.broadcast_arrays(np.asarray(k, float), np.asarray(P, float))
+    out = np.array([lib.orc_lift_what(x, y) for x, y in zip(k.ravel(), P.ravel())])
+    return out.reshape(k.shape) if k.shape else float(out[0])
+
+
+def o1_lift_grid(A, B, R, origin, h, n, height) -> np.ndarray:
+    """Plain slice at `height` of the lifted correlation on t = origin + h*idx,
+    [iz][iy][ix], not periodic: sum_ij c_i d_j W(|x_i - R y_j - t|; r_i + rho_j - height)."""
+    lib = _load()
+    A, B, R, o = _f64(A), _f64(B), _f64(R), _f64(origin)
+    out = np.empty((n, n, n))
+    lib.orc_o1_lift_grid(_ptr(A), len(A), _ptr(B), len(B), _ptr(R), _ptr(o), float(h), int(n), float(height),
+                         _ptr(out))
+    return out
+
+
+def o2_lift_spectrum(A, B, R, n, L, height) -> np.ndarray:
+    """Band-limited spectrum of the lifted slice at `height` (FFT order, [mz][my][mx])."""
+    lib = _load()
+    A, B, R = _f64(A), _f64(B), _f64(R)
+    re = np.empty((n, n, n))
+    im = np.empty((n, n, n))
+    lib.orc_o2_lift_spectrum(_ptr(A), len(A), _ptr(B), len(B), _ptr(R), int(n), float(L), float(height), _ptr(re),
+                             _ptr(im))
+    return re + 1j * im
+
+
+def o2_lift_scores(A, B, q, n, L, origin, height) -> np.ndarray:
+    """Band-limited lifted slice at `height` on t_n = origin + (L/n) idx, [iz][iy][ix]."""
+    G = o2_lift_spectrum(A, B, quat_to_rot(q), n, L, height)
+    k = 2.0 * np.pi * mode_numbers(n) / L
+    ph = (np.exp(1j * k * origin[2])[:, None, None] * np.exp(1j * k * origin[1])[None, :, None]
+          * np.exp(1j * k * origin[0])[None, None, :])
+    return np.real(np.fft.ifftn(G * ph / L ** 3)) * n ** 3

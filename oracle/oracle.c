@@ -29,6 +29,23 @@
  * k = 2 pi m / L for |m_d| < N/2 on an L-periodic box; the Nyquist planes are
  * left at zero.  The inverse transform to the translation grid is done in
  * Python with an FP64 FFT.
+ *
+ * lift_*: the 4D lifted correlation (Sec. 2.2 eq. eq_rhoA, eq_L2cone,
+ * eq_coneconv; Sec. 3.1 Lemma 2, eq. eq_ORA, eq_convgA).  Knot (x, r) of the
+ * fixed shape carries the half-cone {(y, s) : |y - x| <= r - s, s <= r}
+ * (trimmed far below every height used here), knot (y0, rho) of the moved
+ * shape its r-mirror, the upward cone {(y, s) : |y - y0| <= rho + s,
+ * s >= -rho}; the moved shape's cones are translated by the 4D lifted
+ * translation (t, h).  A pair's 4D intersection is the set of (y, s) with
+ * |y - x| + |y - (R y0 + t)| <= r + rho - h, whose 4D volume
+ * W(d; P) = integral over y of (P - |y - p| - |y - q|)_+ is, with
+ * P = r + rho - h and d = |p - q|,
+ *     W(d; P) = pi (P^2 - d^2)^2 / 24   for d < P, else 0
+ * (at each height s it is the lens volume of two balls whose radii sum to P,
+ * integrated over s).  The slice at height h of the lifted correlation is the
+ * sum of c_i d_j W over pairs; its 3D Fourier transform in t is
+ *     What(k; P) = 4 pi^2 (x^3 cos x - 6 x^2 sin x - 15 x cos x + 15 sin x) / (3 k^7),
+ * x = k P, which equals integral_0^P Bhat(k; u) Bhat(k; P - u) du.
  */
 #include <math.h>
 #include <omp.h>
@@ -233,6 +250,153 @@ void orc_o2_spectrum(const double *balls, int64_t nb, const double *R, int n, do
         }
     }
     free(bt); free(ef); free(cw);
+}
+
+/* ---- 4D lifted correlation ------------------------------------------------ */
+
+/* 4D volume of the intersection of a downward and an upward cone whose apex
+ * heights differ by P (radii summing to P at every common height) and whose
+ * axes are d apart. */
+double orc_lift_w(double d, double P)
+{
+    if (!(P > 0.0) || d >= P) return 0.0;
+    double u = P * P - d * d;
+    return M_PI * u * u / 24.0;
+}
+
+/* 3D Fourier transform of t -> W(|t|; P) at |k| (kernel exp(-i k.t)).  For
+ * x = k P < 2 the closed form cancels to x^7 and the Taylor series
+ * P^7 (4 pi^2 / 3) sum_n (-1)^n (2n+2)(2n+4)(2n+6) x^(2n) / (2n+7)! is summed
+ * until a term falls below 1e-18 of the sum; zero for P <= 0. */
+double orc_lift_what(double k, double P)
+{
+    if (!(P > 0.0)) return 0.0;
+    double x = k * P;
+    if (x < 2.0) {
+        double x2 = x * x, term = 1.0, sum = 0.0;
+        double fact = 5040.0; /* (2n+7)! at n = 0 */
+        for (int n = 0; n < 40; ++n) {
+            double c = (2.0 * n + 2) * (2.0 * n + 4) * (2.0 * n + 6) / fact;
+            double t = ((n & 1) ? -1.0 : 1.0) * c * term;
+            sum += t;
+            if (fabs(t) < 1e-18 * fabs(sum)) break;
+            term *= x2;
+            fact *= (2.0 * n + 8) * (2.0 * n + 9);
+        }
+        double p2 = P * P;
+        return 4.0 * M_PI * M_PI / 3.0 * p2 * p2 * p2 * P * sum;
+    }
+    double k2 = k * k, k7 = k2 * k2 * k2 * k;
+    return 4.0 * M_PI * M_PI *
+           (x * x * x * cos(x) - 6.0 * x * x * sin(x) - 15.0 * x * cos(x) + 15.0 * sin(x)) / (3.0 * k7);
+}
+
+/* Plain slice at height h of the lifted correlation on the grid
+ * t = origin + hs * (ix, iy, iz), [iz][iy][ix], not periodic:
+ * sum_ij c_i d_j W(|x_i - R y_j - t|; r_i + rho_j - h), pair by pair over
+ * the grid points of each pair's support (every skipped term is zero). */
+void orc_o1_lift_grid(const double *A, int64_t nA, const double *B, int64_t nB, const double *R,
+                      const double *origin, double hs, int n, double h, double *out)
+{
+    size_t total = (size_t)n * n * n;
+    memset(out, 0, sizeof(double) * total);
+    double *rb = (double *)malloc(sizeof(double) * 3 * (size_t)(nB > 0 ? nB : 1));
+    for (int64_t j = 0; j < nB; ++j) rotate(R, B + 5 * j, rb + 3 * j);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int iz = 0; iz < n; ++iz) {
+        double tz = origin[2] + hs * iz;
+        for (int64_t i = 0; i < nA; ++i) {
+            const double *a = A + 5 * i;
+            for (int64_t j = 0; j < nB; ++j) {
+                double P = a[3] + B[5 * j + 3] - h;
+                if (!(P > 0.0)) continue;
+                double cx = a[0] - rb[3 * j + 0], cy = a[1] - rb[3 * j + 1], cz = a[2] - rb[3 * j + 2];
+                if (fabs(tz - cz) >= P) continue;
+                int x0 = (int)ceil((cx - P - origin[0]) / hs), x1 = (int)floor((cx + P - origin[0]) / hs);
+                int y0 = (int)ceil((cy - P - origin[1]) / hs), y1 = (int)floor((cy + P - origin[1]) / hs);
+                if (x0 < 0) x0 = 0;
+                if (y0 < 0) y0 = 0;
+                if (x1 > n - 1) x1 = n - 1;
+                if (y1 > n - 1) y1 = n - 1;
+                double w = a[4] * B[5 * j + 4];
+                for (int iy = y0; iy <= y1; ++iy) {
+                    double ty = origin[1] + hs * iy;
+                    for (int ix = x0; ix <= x1; ++ix) {
+                        double tx = origin[0] + hs * ix;
+                        double dx = cx - tx, dy = cy - ty, dz = cz - tz;
+                        out[((size_t)iz * n + iy) * n + ix] += w * orc_lift_w(sqrt(dx * dx + dy * dy + dz * dz), P);
+                    }
+                }
+            }
+        }
+    }
+    free(rb);
+}
+
+/* Band-limited spectrum of the slice at height h:
+ * G(k_m) = sum_ij c_i d_j What(|k_m|; r_i + rho_j - h) exp(-i k_m . (x_i - R y_j)),
+ * k_m = 2 pi m / L, |m_d| < n/2, in FFT order re/im[mz][my][mx] (Nyquist
+ * planes zero).  This is the 4D product rho_A conj(rho_RB) fhat_D^2
+ * (eq. eq_convgA) brought back to height h, summed pair by pair: a pair's
+ * phase is the product of its three axis factors; What is tabulated per pair
+ * over the distinct |m|^2.  Threads split the z-planes of the output. */
+void orc_o2_lift_spectrum(const double *A, int64_t nA, const double *B, int64_t nB, const double *R, int n,
+                          double L, double h, double *re, double *im)
+{
+    size_t total = (size_t)n * n * n;
+    memset(re, 0, sizeof(double) * total);
+    memset(im, 0, sizeof(double) * total);
+    int half = n / 2;
+    int m2max = 3 * (half - 1) * (half - 1);
+    double dk = 2.0 * M_PI / L;
+    double *rb = (double *)malloc(sizeof(double) * 3 * (size_t)(nB > 0 ? nB : 1));
+    for (int64_t j = 0; j < nB; ++j) rotate(R, B + 5 * j, rb + 3 * j);
+#pragma omp parallel
+    {
+        double *tab = (double *)malloc(sizeof(double) * (size_t)(m2max + 1));
+        double *ef = (double *)malloc(sizeof(double) * 4 * (size_t)n);
+#pragma omp for schedule(dynamic, 1)
+        for (int iz = 0; iz < n; ++iz) {
+            int mz = iz < half ? iz : iz - n;
+            if (mz == -half) continue;
+            for (int64_t i = 0; i < nA; ++i) {
+                const double *a = A + 5 * i;
+                for (int64_t j = 0; j < nB; ++j) {
+                    double P = a[3] + B[5 * j + 3] - h;
+                    if (!(P > 0.0)) continue;
+                    double w = a[4] * B[5 * j + 4];
+                    double p[3] = {a[0] - rb[3 * j], a[1] - rb[3 * j + 1], a[2] - rb[3 * j + 2]};
+                    for (int m2 = 0; m2 <= m2max; ++m2) tab[m2] = w * orc_lift_what(dk * sqrt((double)m2), P);
+                    for (int ax = 0; ax < 2; ++ax)
+                        for (int q = 0; q < n; ++q) {
+                            double ph = dk * (q < half ? q : q - n) * p[ax];
+                            ef[(ax * n + q) * 2] = cos(ph);
+                            ef[(ax * n + q) * 2 + 1] = -sin(ph);
+                        }
+                    double phz = dk * mz * p[2];
+                    double zr = cos(phz), zi = -sin(phz);
+                    for (int iy = 0; iy < n; ++iy) {
+                        int my = iy < half ? iy : iy - n;
+                        if (my == -half) continue;
+                        const double *ey = ef + (n + iy) * 2;
+                        double yr = zr * ey[0] - zi * ey[1], yi = zr * ey[1] + zi * ey[0];
+                        size_t row = ((size_t)iz * n + iy) * n;
+                        for (int ix = 0; ix < n; ++ix) {
+                            int mx = ix < half ? ix : ix - n;
+                            if (mx == -half) continue;
+                            const double *ex = ef + ix * 2;
+                            double s = tab[mx * mx + my * my + mz * mz];
+                            re[row + ix] += s * (yr * ex[0] - yi * ex[1]);
+                            im[row + ix] += s * (yr * ex[1] + yi * ex[0]);
+                        }
+                    }
+                }
+            }
+        }
+        free(tab);
+        free(ef);
+    }
+    free(rb);
 }
 
 /* Threads of the OpenMP loops above (timing only: results do not depend on
