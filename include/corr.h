@@ -57,6 +57,21 @@ extern "C" {
                                  offset of a union of balls being the union of its
                                  balls grown by sc_offset, and the score is
                                  <a_A, a_{(R,t)B}> (the affinity's factor i cancels) */
+#define CORR_LIFTED_SCORE  4u /* score slices of the 4D lifted correlation of
+                                 Sec. 2.2 (eq. eq_rhoA, eq_L2cone, eq_coneconv) and
+                                 Sec. 3.1 (Lemma 2, eq. eq_ORA, eq_convgA): each
+                                 ball (x, r) of A lifted to a downward half-cone
+                                 {(y, s) : |y - x| <= r - s}, each ball of B to the
+                                 r-mirrored upward cone, B moved by the 4D
+                                 translation (R, t, h).  The slice at height h is
+                                   g_h(R, t) = sum_i sum_j c_i d_j W(|x_i - R y_j - t|; r_i + rho_j - h),
+                                 W(d; P) = pi (P^2 - d^2)^2 / 24 for d < P (the 4D
+                                 volume of the two cones' intersection), else 0.
+                                 Its positive set is the configuration obstacle of
+                                 the balls offset by a total of -h (Lemma 2 at
+                                 h = 0).  corr_eval gives h = 0; corr_set_offsets
+                                 sets other heights.  Not with CORR_SC_SCORE;
+                                 corr_spectrum and the queries are not available. */
 
 typedef struct {
     double x, y, z; /* centre                */
@@ -82,6 +97,12 @@ typedef struct {
     double sc_lambda;  /* with CORR_SC_SCORE: penalty factor lambda >= 0; otherwise
                           must be 0.  tol is then relative to the volume of the
                           largest grown ball.                                      */
+    double lift_range; /* with CORR_LIFTED_SCORE: slice heights h in
+                          [-lift_range, min(lift_range, (r_min(A) + r_min(B)) / 2)]
+                          are allowed; the radius expansions are planned for
+                          them (tol relative to the largest kernel value
+                          What(0; r_max(A) + r_max(B) + lift_range)).  Finite,
+                          >= 0; otherwise must be 0.                               */
 } corr_grid;
 
 typedef struct corr_ctx corr_ctx;
@@ -230,6 +251,10 @@ int corr_query_noalloc(corr_ctx* ctx, const double* quat_wxyz, const double* t_h
  * Errors: CORR_EINVAL (bad value or count), CORR_EUNSUPPORTED (with
  * CORR_SC_SCORE, whose kernel already offsets the balls), CORR_ENOMEM, CORR_EHIP.
  * After an error the previous offsets stay in force.
+ * With CORR_LIFTED_SCORE the values are slice heights h_k of the lifted
+ * correlation instead (slice k scores g_{h_k}, whose positive set is the
+ * obstacle offset by -h_k), each within the range planned at create
+ * (corr_grid.lift_range); A's component spectra are shared by all heights.
  */
 int corr_set_offsets(corr_ctx* ctx, const double* offsets, int32_t n_offsets);
 

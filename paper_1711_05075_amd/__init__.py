@@ -28,6 +28,7 @@ CORR_EHIP = -3
 CORR_EUNSUPPORTED = -4
 CORR_DETERMINISTIC = 1
 CORR_SC_SCORE = 2
+CORR_LIFTED_SCORE = 4
 CORR_TUNE_WITH_A = 1
 CORR_MAX_SLICES = 16
 
@@ -47,7 +48,7 @@ class corr_grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("box", ctypes.c_double), ("origin", ctypes.c_double * 3),
                 ("sigma", ctypes.c_double), ("kb_width", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("flags", ctypes.c_uint32), ("batch", ctypes.c_int32), ("sc_offset", ctypes.c_double),
-                ("sc_lambda", ctypes.c_double)]
+                ("sc_lambda", ctypes.c_double), ("lift_range", ctypes.c_double)]
 
 
 class corr_info_t(ctypes.Structure):
@@ -266,14 +267,18 @@ def corr_last_error(ctx=None) -> str:
     return load_library().corr_last_error(ctx).decode()
 
 
-def make_grid(n, box, origin, sigma=2.0, kb_width=8, tol=1e-6, flags=0, batch=0, sc=None) -> corr_grid:
-    """sc = (offset, lambda) scores shape complementarity (sets CORR_SC_SCORE)."""
+def make_grid(n, box, origin, sigma=2.0, kb_width=8, tol=1e-6, flags=0, batch=0, sc=None, lift=None) -> corr_grid:
+    """sc = (offset, lambda) scores shape complementarity (sets CORR_SC_SCORE);
+    lift = range of slice heights scores the lifted correlation (sets CORR_LIFTED_SCORE)."""
     g = corr_grid()
     g.n, g.box, g.sigma, g.kb_width, g.tol, g.flags, g.batch = int(n), float(box), float(sigma), int(kb_width), \
         float(tol), int(flags), int(batch)
     if sc is not None:
         g.flags |= CORR_SC_SCORE
         g.sc_offset, g.sc_lambda = float(sc[0]), float(sc[1])
+    if lift is not None:
+        g.flags |= CORR_LIFTED_SCORE
+        g.lift_range = float(lift)
     for d in range(3):
         g.origin[d] = float(origin[d])
     return g
@@ -285,13 +290,13 @@ class Correlator:
     """One (A, B) pair on one translation grid; outputs are torch CUDA tensors."""
 
     def __init__(self, A, B, n, box, origin, sigma=2.0, kb_width=8, tol=1e-6, flags=0, batch=0, device=None,
-                 sc=None):
+                 sc=None, lift=None):
         import torch
         self.torch = torch
         self.device = torch.device(device or "cuda")
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
-            self.grid = make_grid(n, box, origin, sigma, kb_width, tol, flags, batch, sc)
+            self.grid = make_grid(n, box, origin, sigma, kb_width, tol, flags, batch, sc, lift)
             self.ctx = corr_create(A, B, self.grid, self.stream.cuda_stream)
         self.n = int(n)
         self.info = corr_info(self.ctx)

@@ -238,6 +238,105 @@ Expansion build_expansion(double rlo, double rhi, double dk, int m2n, double tol
 }
 
 // ---------------------------------------------------------------------------
+// Radius expansion of the lifted kernel (CORR_LIFTED_SCORE).  A pair's kernel
+// What(k; r_i + rho_j - h) depends on both radii through their sum; it is
+// interpolated in each radius at Chebyshev points of that shape's radius
+// range,
+//     What(k; r + rho - h) ~ sum_p sum_p' l_p(r) l'_p'(rho) What(k; a_p + b_p' - h),
+// so each knot spreads its weight times the Lagrange basis l_p(r_i) (q = the
+// node count) and the node-pair table What(k; a_p + b_p' - h) joins the two
+// shapes' component spectra per slice height.  The node count is the smallest
+// (2..32) whose interpolation error in this shape's radius, over 48
+// wavenumbers up to the largest kept one, the other shape's radius range and
+// the planned heights, is within tol of the largest kernel value.
+// ---------------------------------------------------------------------------
+// 3D transform of the 4D cone-intersection volume pi (P^2 - d^2)^2 / 24 (x = kP;
+// Taylor series below x = 2, where the closed form cancels to x^7).
+double lift_what_host(double k, double P) {
+    if (!(P > 0.0)) return 0.0;
+    const double x = k * P;
+    if (x < 2.0) {
+        const double x2 = x * x;
+        double term = 1.0, sum = 0.0, fact = 5040.0;
+        for (int n = 0; n < 18; ++n) {
+            const double c = (2.0 * n + 2) * (2.0 * n + 4) * (2.0 * n + 6) / fact;
+            sum += ((n & 1) ? -c : c) * term;
+            term *= x2;
+            fact *= (2.0 * n + 8) * (2.0 * n + 9);
+        }
+        const double p2 = P * P;
+        return 4.0 * M_PI * M_PI / 3.0 * p2 * p2 * p2 * P * sum;
+    }
+    const double k2 = k * k, k7 = k2 * k2 * k2 * k;
+    return 4.0 * M_PI * M_PI * (x * x * x * std::cos(x) - 6.0 * x * x * std::sin(x) - 15.0 * x * std::cos(x) +
+                                15.0 * std::sin(x)) / (3.0 * k7);
+}
+
+Expansion build_lift_expansion(double lo, double hi, double olo, double ohi, double hlo, double hhi, double dk,
+                               int m2n, double tol) {
+    Expansion e;
+    e.rlo = lo;
+    e.rhi = hi;
+    e.rref = hi;
+    const double kmax = dk * std::sqrt((double)(m2n - 1));
+    const double scale = lift_what_host(0.0, hi + ohi - hlo);
+    double ks[48], bs[5];
+    for (int a = 0; a < 48; ++a) ks[a] = kmax * a / 47.0;
+    for (int b = 0; b < 5; ++b) bs[b] = olo + (ohi - olo) * b / 4.0;
+    const double hs[3] = {hlo, std::min(std::max(0.0, hlo), hhi), hhi};
+    if (!(hi > lo * (1.0 + 1e-12))) {
+        e.p = e.q = 1;
+        e.nodes = {hi};
+        e.basis = {1.0};
+        e.bary = {1.0};
+        double worst = 0;
+        for (double k : ks)
+            for (double b : bs)
+                for (double h : hs) worst = std::max(worst, std::fabs(lift_what_host(k, lo + b - h) - lift_what_host(k, hi + b - h)));
+        e.err = worst / scale;
+        return e;
+    }
+    std::vector<double> lrow, f;
+    for (int p = 2; p <= 32; ++p) {
+        e.p = p;
+        e.nodes.resize(p);
+        e.bary.resize(p);
+        for (int b = 0; b < p; ++b) {
+            e.nodes[b] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * std::cos(M_PI * b / (p - 1));
+            e.bary[b] = ((b % 2) ? -1.0 : 1.0) * ((b == 0 || b == p - 1) ? 0.5 : 1.0);
+        }
+        const int nt = 4 * p;
+        std::vector<std::vector<double>> L(nt, std::vector<double>(p));
+        std::vector<double> rt(nt);
+        for (int t = 0; t < nt; ++t) {
+            rt[t] = lo + (hi - lo) * (t + 0.5) / nt;
+            lagrange_row(e, rt[t], L[t].data());
+        }
+        double err = 0;
+        f.resize(p);
+        for (double k : ks)
+            for (double b : bs)
+                for (double h : hs) {
+                    for (int q = 0; q < p; ++q) f[q] = lift_what_host(k, e.nodes[q] + b - h);
+                    for (int t = 0; t < nt; ++t) {
+                        double v = 0;
+                        for (int q = 0; q < p; ++q) v += L[t][q] * f[q];
+                        err = std::max(err, std::fabs(v - lift_what_host(k, rt[t] + b - h)));
+                    }
+                }
+        e.err = err / scale;
+        if (e.err <= tol) {
+            e.q = p;
+            e.basis.assign((size_t)p * p, 0.0);
+            for (int b = 0; b < p; ++b) e.basis[(size_t)b * p + b] = 1.0;
+            return e;
+        }
+    }
+    fail(CORR_EUNSUPPORTED, "lifted kernel: 32 radius nodes reach only %.3g (tolerance %.3g); radii span [%g, %g]",
+         e.err, tol, lo, hi);
+}
+
+// ---------------------------------------------------------------------------
 // device buffers
 // ---------------------------------------------------------------------------
 struct DevMem {
@@ -275,6 +374,7 @@ struct Shape {
     double* pos = nullptr;  // [n][3]
     float* wts = nullptr;   // [q][n]
     float* vtab = nullptr;  // [q][m2n]
+    double* d_nodes = nullptr;  // [p] radius nodes of the expansion (device)
 };
 
 // One offset slice: A's balls with every radius changed by delta, and its spectrum.
@@ -436,6 +536,10 @@ struct corr_ctx {
     Geom g;
     double box = 0, origin[3] = {0, 0, 0}, sigma = 2, tol = 1e-6;
     double sc_r0 = 0, sc_lam = 0;  // shape-complementarity kernel parameters (0, 0: overlap score)
+    bool lifted = false;           // CORR_LIFTED_SCORE: slices of the lifted correlation
+    double lift_lo = 0, lift_hi = 0;  // allowed slice heights
+    float* lift_tab = nullptr;     // [q_A][q_B][m2n] node-pair kernel table of one height
+    float2* lift_ga = nullptr;     // [q_A][n][n][half] A's deconvolved component spectra
     uint32_t flags = 0;
     bool graph = false;       // replay evaluations as captured hipGraphs (corr_set_tuning)
     uint64_t shape_gen = 0;   // bumped whenever launch shapes, workspace or slices change
@@ -507,15 +611,30 @@ void validate_balls(const corr_ball* p, int64_t n, const char* name) {
     }
 }
 
-void setup_shape(corr_ctx* c, Shape& s, const corr_ball* balls, int64_t n, double dk) {
-    s.n = n;
-    double rlo = 1.0, rhi = 1.0;
+// Smallest and largest radius (1, 1 for an empty set).
+void radius_range(const corr_ball* balls, int64_t n, double& rlo, double& rhi) {
+    rlo = rhi = 1.0;
     if (n > 0) {
         rlo = rhi = balls[0].r;
         for (int64_t i = 1; i < n; ++i) {
             rlo = std::min(rlo, balls[i].r);
             rhi = std::max(rhi, balls[i].r);
         }
+    }
+}
+
+// Plan shape s's radius expansion; a lifted score also needs the other
+// shape's balls (its kernel depends on both radii).
+void setup_shape(corr_ctx* c, Shape& s, const corr_ball* balls, int64_t n, double dk,
+                 const corr_ball* other = nullptr, int64_t n_other = 0) {
+    s.n = n;
+    double rlo, rhi;
+    radius_range(balls, n, rlo, rhi);
+    if (c->lifted) {
+        double olo, ohi;
+        radius_range(other, n_other, olo, ohi);
+        s.ex = build_lift_expansion(rlo, rhi, olo, ohi, c->lift_lo, c->lift_hi, dk, c->g.m2n, c->tol);
+        return;
     }
     s.ex = build_expansion(rlo, rhi, dk, c->g.m2n, c->tol, c->sc_r0, c->sc_lam);
 }
@@ -535,8 +654,9 @@ void upload_shape(corr_ctx* c, DevMem& mem, Shape& s, const corr_ball* balls, do
             pos[3 * i + 1] = balls[i].y;
             pos[3 * i + 2] = balls[i].z;
             lagrange_row(e, std::min(std::max(balls[i].r, e.rlo), e.rhi), lrow.data());
-            // equal radii: exact volume ratio (with an offset the two terms scale differently)
-            if (e.p == 1 && e.r0 == 0.0) lrow[0] = std::pow(balls[i].r / e.rhi, 3.0);
+            // equal radii: exact volume ratio (with an offset the two terms scale
+            // differently; the lifted kernel is tabulated at the radius itself)
+            if (e.p == 1 && e.r0 == 0.0 && !c->lifted) lrow[0] = std::pow(balls[i].r / e.rhi, 3.0);
             for (int q = 0; q < e.q; ++q) {
                 double u = 0;
                 for (int b = 0; b < e.p; ++b) u += lrow[b] * e.basis[(size_t)b * e.q + q];
@@ -561,8 +681,11 @@ void upload_shape(corr_ctx* c, DevMem& mem, Shape& s, const corr_ball* balls, do
     double* d_basis = mem.alloc<double>((size_t)e.p * e.q);
     upload(d_nodes, e.nodes.data(), sizeof(double) * e.p, c->stream);
     upload(d_basis, e.basis.data(), sizeof(double) * e.p * e.q, c->stream);
-    hip_check(corr::launch_ball_table(c->g, dk, d_nodes, d_basis, e.p, e.q, e.rref, e.r0, e.lam, s.vtab, c->stream),
-              "ball table");
+    s.d_nodes = d_nodes;
+    if (!c->lifted)
+        hip_check(corr::launch_ball_table(c->g, dk, d_nodes, d_basis, e.p, e.q, e.rref, e.r0, e.lam, s.vtab,
+                                          c->stream),
+                  "ball table");
 }
 
 hipEvent_t take_event(corr_ctx* c) {
@@ -634,8 +757,32 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
 
 void stage_quats(corr_ctx* c, const double* q, int S);
 
+// The lifted score's fixed side of the slice at height h into out
+// ([q_B][n][n][half]), from A's component spectra (computed first if
+// `components`): the node-pair kernel table of that height, then
+// H[p'] = sum_p G_A[p] table[p][p'] per mode.
+void lifted_fixed_side(corr_ctx* c, double h, float2* out, bool components) {
+    const Geom& g = c->g;
+    if (components) {
+        run_spectrum_stages(c, c->A, c->ident_q, 1);
+        stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z components (A)", [&] {
+            return corr::launch_fft_z_components(g, reinterpret_cast<float2*>(c->ws->buf0), 1, c->A.ex.q,
+                                                 occupancy(c, c->A), c->deconv, c->lift_ga, c->twm, c->stream);
+        });
+    }
+    hip_check(corr::launch_lift_table(g, 2.0 * M_PI / c->box, c->A.d_nodes, c->A.ex.q, c->B.d_nodes, c->B.ex.q, h,
+                                      c->lift_tab, c->stream),
+              "lifted kernel table");
+    hip_check(corr::launch_lift_h(g, c->lift_ga, c->A.ex.q, c->lift_tab, c->B.ex.q, out, c->stream),
+              "lifted fixed side");
+}
+
 // The fixed shape's spectrum (unturned) into fa.
 void fixed_spectrum(corr_ctx* c, const Shape& a, float2* fa) {
+    if (c->lifted) {
+        lifted_fixed_side(c, 0.0, fa, true);
+        return;
+    }
     run_spectrum_stages(c, a, c->ident_q, 1);
     stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z (A)", [&] {
         return corr::launch_fft_z_spectrum(c->g, reinterpret_cast<float2*>(c->ws->buf0), 1, a.ex.q,
@@ -767,7 +914,15 @@ corr_ctx* plan_pair(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t 
              who, w);
     const double tol = gr.tol == 0 ? 1e-6 : gr.tol;
     if (!std::isfinite(tol) || !(tol > 0) || tol >= 1) fail(CORR_EINVAL, "%stol must be in (0, 1)", who);
-    if (gr.flags & ~(CORR_DETERMINISTIC | CORR_SC_SCORE)) fail(CORR_EINVAL, "%sunknown flag bits 0x%x", who, gr.flags);
+    if (gr.flags & ~(CORR_DETERMINISTIC | CORR_SC_SCORE | CORR_LIFTED_SCORE))
+        fail(CORR_EINVAL, "%sunknown flag bits 0x%x", who, gr.flags);
+    if ((gr.flags & CORR_LIFTED_SCORE) && (gr.flags & CORR_SC_SCORE))
+        fail(CORR_EINVAL, "%sCORR_LIFTED_SCORE and CORR_SC_SCORE exclude each other", who);
+    if (gr.flags & CORR_LIFTED_SCORE) {
+        if (!std::isfinite(gr.lift_range) || gr.lift_range < 0) fail(CORR_EINVAL, "%slift_range must be finite and >= 0", who);
+    } else if (gr.lift_range != 0) {
+        fail(CORR_EINVAL, "%slift_range needs CORR_LIFTED_SCORE", who);
+    }
     if (gr.flags & CORR_SC_SCORE) {
         if (!std::isfinite(gr.sc_offset) || gr.sc_offset < 0) fail(CORR_EINVAL, "%ssc_offset must be finite and >= 0", who);
         if (!std::isfinite(gr.sc_lambda) || gr.sc_lambda < 0) fail(CORR_EINVAL, "%ssc_lambda must be finite and >= 0", who);
@@ -802,9 +957,19 @@ corr_ctx* plan_pair(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t 
         hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device), "CU count");
         g.spread_wgs = 2 * std::max(cus, 1);
         const double dk = 2.0 * M_PI / gr.box;
+        if (gr.flags & CORR_LIFTED_SCORE) {
+            // heights within the planned range that leave every pair's cones
+            // meeting (r_i + rho_j - h >= half the smallest radius sum)
+            double alo, ahi, blo, bhi;
+            radius_range(A, nA, alo, ahi);
+            radius_range(B, nB, blo, bhi);
+            c->lifted = true;
+            c->lift_lo = -gr.lift_range;
+            c->lift_hi = std::min(gr.lift_range, 0.5 * (alo + blo));
+        }
 
-        setup_shape(c, c->A, A, nA, dk);
-        setup_shape(c, c->B, B, nB, dk);
+        setup_shape(c, c->A, A, nA, dk, B, nB);
+        setup_shape(c, c->B, B, nB, dk, A, nA);
         c->qmax = std::max(c->A.ex.q, c->B.ex.q);
         c->nkmax = std::max<int64_t>(std::max(nA, nB), 1);
 
@@ -831,7 +996,13 @@ corr_ctx* plan_pair(const corr_ball* A, int64_t nA, const corr_ball* B, int64_t 
         upload_shape(c, c->mem, c->A, A, dk);
         upload_shape(c, c->mem, c->B, B, dk);
         c->host_a.assign(A, A + nA);
-        c->fa = c->mem.alloc<float2>((size_t)g.n * g.n * g.half);
+        // the fixed side of a slice: F_A, or for the lifted score one table
+        // per component of B
+        c->fa = c->mem.alloc<float2>((size_t)(c->lifted ? c->B.ex.q : 1) * g.n * g.n * g.half);
+        if (c->lifted) {
+            c->lift_tab = c->mem.alloc<float>((size_t)c->A.ex.q * c->B.ex.q * g.m2n);
+            c->lift_ga = c->mem.alloc<float2>((size_t)c->A.ex.q * g.n * g.n * g.half);
+        }
         static const double ident[4] = {1, 0, 0, 0};
         c->ident_q = c->mem.alloc<double>(4);
         upload(c->ident_q, ident, sizeof ident, c->stream);
@@ -887,6 +1058,40 @@ void eval_impl(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, const std::v
         // rotations already on the device (graph replay), or staged per batch
         if (!d_quats) stage_quats(c, quat_wxyz + 4 * r0, S);
         run_spectrum_stages(c, c->B, d_quats ? d_quats + 4 * r0 : c->ws->quats, S);
+        if (c->lifted) {
+            // B's component z transforms once (into buf1, free after the y
+            // pass), then per slice: sum_p' H[p'] conj(G_B[p']), inverse z into
+            // buf0 (free after the z pass), inverse y in place, inverse x
+            float2* comps = c->ws->buf1;
+            float2* prod = reinterpret_cast<float2*>(c->ws->buf0);
+            stage(c, CORR_STAGE_FFT_Z_SPECTRUM, "fft z components (B)", [&] {
+                return corr::launch_fft_z_components(g, prod, S, c->B.ex.q, occupancy(c, c->B), nullptr, comps,
+                                                     c->twm, c->stream);
+            });
+            join_a(c);
+            for (size_t k = 0; k < fas.size(); ++k) {
+                const size_t first = (size_t)k * n_rot + r0;
+                stage(c, CORR_STAGE_FFT_Z_PRODUCT, "lifted product", [&] {
+                    return corr::launch_lift_product_ifft_z(g, comps, S, c->B.ex.q, c->phase, fas[k], prod, c->twn,
+                                                            c->stream);
+                });
+                stage(c, CORR_STAGE_IFFT_Y, "ifft y",
+                      [&] { return corr::launch_ifft_y(g, prod, S, prod, c->twn, c->stream); });
+                stage(c, CORR_STAGE_IFFT_X, "ifft x", [&] {
+                    return corr::launch_ifft_x(g, prod, S, o.scores ? o.scores + first * n3 : nullptr,
+                                               o.mask ? o.mask + first * (n3 / 32) : nullptr, o.thr, c->ws->pval,
+                                               c->ws->pidx, o.count ? c->ws->pcnt : nullptr, c->twn, c->stream);
+                });
+                if (o.peak_val || o.count)
+                    stage(c, CORR_STAGE_PEAK, "peak", [&] {
+                        return corr::launch_peak_final(c->ws->pval, c->ws->pidx, c->ws->pcnt, S, nb,
+                                                       o.peak_val ? o.peak_val + first : nullptr,
+                                                       o.peak_idx ? o.peak_idx + first : nullptr,
+                                                       o.count ? o.count + first : nullptr, c->stream);
+                    });
+            }
+            continue;
+        }
         // several slices: B's z sums once, into the second half of buf1
         // (buf1 holds q m^2 n/2 >= 2 n^2 n/2 values per slot)
         float2* zsums = c->ws->buf1 + (size_t)c->ws->slots * g.n * g.n * g.half;
@@ -1048,6 +1253,33 @@ void set_offsets(corr_ctx* c, const double* offsets, int32_t n) {
         fail(CORR_EUNSUPPORTED, "offset slices with CORR_SC_SCORE: its kernel already offsets the balls");
     if (n < 0 || n > CORR_MAX_SLICES) fail(CORR_EINVAL, "n_offsets = %d; allowed 0..%d", n, CORR_MAX_SLICES);
     if (n > 0 && !offsets) fail(CORR_EINVAL, "NULL offsets with n_offsets = %d", n);
+    if (c->lifted) {
+        // slice heights of the lifted correlation: each slice's fixed side from
+        // A's component spectra (kept since corr_create / corr_prepare_a)
+        for (int k = 0; k < n; ++k)
+            if (!std::isfinite(offsets[k]) || offsets[k] < c->lift_lo || offsets[k] > c->lift_hi)
+                fail(CORR_EINVAL, "height %d (%g) is outside the planned range [%g, %g] (corr_grid.lift_range)", k,
+                     offsets[k], c->lift_lo, c->lift_hi);
+        std::vector<Slice> ns(n);
+        DevMem nm;
+        try {
+            for (int k = 0; k < n; ++k) {
+                ns[k].delta = offsets[k];
+                ns[k].fa = nm.alloc<float2>((size_t)c->B.ex.q * c->g.n * c->g.n * c->g.half);
+                lifted_fixed_side(c, offsets[k], ns[k].fa, false);
+            }
+            hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+        } catch (...) {
+            (void)hipStreamSynchronize(c->stream);
+            nm.release();
+            throw;
+        }
+        c->slice_mem.release();
+        c->slices = std::move(ns);
+        c->slice_mem = nm;
+        c->shape_gen++;
+        return;
+    }
     double rmin = HUGE_VAL;
     for (const corr_ball& b : c->host_a) rmin = std::min(rmin, b.r);
     for (int k = 0; k < n; ++k) {
@@ -1421,6 +1653,7 @@ int corr_spectrum(corr_ctx* c, int32_t which, const double* quat_wxyz, float* ou
     }
     return guarded(c, [&] {
         if (which != 0 && which != 1) fail(CORR_EINVAL, "which must be 0 (A) or 1 (B)");
+        if (c->lifted) fail(CORR_EUNSUPPORTED, "corr_spectrum with CORR_LIFTED_SCORE: a slice has no single shape spectrum");
         join_a(c);
         if (!out_dev) fail(CORR_EINVAL, "out_dev is NULL");
         static const double ident[4] = {1, 0, 0, 0};
@@ -1612,6 +1845,7 @@ int corr_query(corr_ctx* c, const double* quat_wxyz, const double* t_host, int64
         if (n_t < 0 || n_t > INT32_MAX) fail(CORR_EINVAL, "n_t = %lld; allowed 0..2^31-1", (long long)n_t);
         if (mode_radius2 < 0) fail(CORR_EINVAL, "mode_radius2 must be >= 0");
         if (n_t > 0 && (!t_host || !out_dev)) fail(CORR_EINVAL, "NULL translations or output");
+        if (c->lifted) fail(CORR_EUNSUPPORTED, "queries with CORR_LIFTED_SCORE are not available");
         validate_quats(quat_wxyz, 1);
         for (int64_t i = 0; i < 3 * n_t; ++i)
             if (!std::isfinite(t_host[i])) fail(CORR_EINVAL, "translation %lld is not finite", (long long)(i / 3));
@@ -1750,6 +1984,7 @@ int corr_query_noalloc(corr_ctx* c, const double* quat_wxyz, const double* t_hos
         if (n_t < 0 || n_t > INT32_MAX) fail(CORR_EINVAL, "n_t = %lld; allowed 0..2^31-1", (long long)n_t);
         if (mode_radius2 < 0) fail(CORR_EINVAL, "mode_radius2 must be >= 0");
         if (n_t > 0 && (!t_host || !out_dev)) fail(CORR_EINVAL, "NULL translations or output");
+        if (c->lifted) fail(CORR_EUNSUPPORTED, "queries with CORR_LIFTED_SCORE are not available");
         validate_quats(quat_wxyz, 1);
         for (int64_t i = 0; i < 3 * n_t; ++i)
             if (!std::isfinite(t_host[i])) fail(CORR_EINVAL, "translation %lld is not finite", (long long)(i / 3));

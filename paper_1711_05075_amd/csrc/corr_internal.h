@@ -115,6 +115,23 @@ hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q,
 // launch_fft_z_product, bit for bit.
 hipError_t launch_product_ifft_z(const Geom& g, const float2* d_acc, int S, const double2* d_phase,
                                  const float2* d_fa, float2* d_out, const float2* d_twn, hipStream_t st);
+// ---- the lifted score (4D cone correlation sliced at heights h) -------------
+// d_tab [qa][qb][m2n] = What(dk sqrt(m2); a_p + b_p' - h) at the two shapes'
+// radius nodes d_na [qa], d_nb [qb] (FP64, stored as float).
+hipError_t launch_lift_table(const Geom& g, double dk, const double* d_na, int qa, const double* d_nb, int qb,
+                             double h, float* d_tab, hipStream_t st);
+// z transform of every component kept apart: d_out [S][q][n][n][half], times
+// the deconvolution if d_deconv is not NULL.
+hipError_t launch_fft_z_components(const Geom& g, const float2* d_in, int S, int q, const Occupancy& occ,
+                                   const double* d_deconv, float2* d_out, const float2* d_twm, hipStream_t st);
+// d_h [qb][n][n][half] = sum_p d_ga[p] * d_tab[p][.][|m|^2] per mode.
+hipError_t launch_lift_h(const Geom& g, const float2* d_ga, int qa, const float* d_tab, int qb, float2* d_h,
+                         hipStream_t st);
+// product sum_c d_h[c] conj(d_comps[s][c]) times the shift and deconvolution
+// factor, then inverse z: d_out [S][n][n][half].
+hipError_t launch_lift_product_ifft_z(const Geom& g, const float2* d_comps, int S, int q, const double2* d_phase,
+                                      const float2* d_h, float2* d_out, const float2* d_twn, hipStream_t st);
+
 // a5: inverse y (d_in == d_out allowed), then inverse x (half-complex to real)
 // with per-block peaks and, for the obstacle predicate score > thr, the bit
 // mask d_mask [S][n^3 / 32] (NULL: not written) and per-block counts d_pcnt

@@ -247,6 +247,46 @@ __global__ void k_ball_table(int m2n, double dk, const double* __restrict__ node
     for (int c = 0; c < q; ++c) vtab[(size_t)c * m2n + m2] = (float)(scale * acc[c]);
 }
 
+// 3D Fourier transform at |k| of the 4D volume W(|t|; P) = pi (P^2 - |t|^2)^2 / 24
+// of the intersection of two opposite cones (the lifted kernel of Sec. 3.1,
+// eq. eq_convgA, sliced at one height), whose cross-sections' radii sum to P:
+//   What(k; P) = 4 pi^2 (x^3 cos x - 6 x^2 sin x - 15 x cos x + 15 sin x) / (3 k^7),
+// x = k P; below x = 2 the closed form cancels to x^7 and its Taylor series
+// P^7 (4 pi^2 / 3) sum_n (-1)^n (2n+2)(2n+4)(2n+6) x^(2n) / (2n+7)! is summed
+// (18 terms leave < 1e-17 relative at x = 2).  Zero for P <= 0.
+__device__ double lift_what(double k, double P) {
+    if (!(P > 0.0)) return 0.0;
+    const double x = k * P;
+    if (x < 2.0) {
+        const double x2 = x * x;
+        double term = 1.0, sum = 0.0, fact = 5040.0;
+        for (int n = 0; n < 18; ++n) {
+            const double c = (2.0 * n + 2) * (2.0 * n + 4) * (2.0 * n + 6) / fact;
+            sum += ((n & 1) ? -c : c) * term;
+            term *= x2;
+            fact *= (2.0 * n + 8) * (2.0 * n + 9);
+        }
+        const double p2 = P * P;
+        return 4.0 * M_PI * M_PI / 3.0 * p2 * p2 * p2 * P * sum;
+    }
+    double sn, cs;
+    sincos(x, &sn, &cs);
+    const double k2 = k * k, k7 = k2 * k2 * k2 * k;
+    return 4.0 * M_PI * M_PI * (x * x * x * cs - 6.0 * x * x * sn - 15.0 * x * cs + 15.0 * sn) / (3.0 * k7);
+}
+
+// tab[p][p'][m2] = What(dk sqrt(m2); a_p + b_p' - h): the lifted kernel at the
+// radius nodes of both shapes for one slice height h, the bilinear expansion
+//   What(k; r_i + rho_j - h) ~ sum_{p,p'} l_p(r_i) l'_p'(rho_j) tab[p][p'](k).
+__global__ void k_lift_table(int m2n, double dk, const double* __restrict__ na, int qa,
+                             const double* __restrict__ nb, int qb, double h, float* __restrict__ tab) {
+    const int m2 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pp = blockIdx.y;  // p * qb + p'
+    if (m2 >= m2n) return;
+    const int p = pp / qb, p2 = pp % qb;
+    tab[(size_t)pp * m2n + m2] = (float)lift_what(dk * sqrt((double)m2), na[p] + nb[p2] - h);
+}
+
 // ---------------------------------------------------------------------------
 // a0 (binned form): rotate + place + window weights, and a counting sort of the
 // knots by key = z-cell * nyb + y-cell / ygroup, so that a spreading tile finds
@@ -1195,6 +1235,148 @@ __global__ __launch_bounds__(kThreads) void k_product_ifft_z(const float2* __res
     for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * N * H + t % COLS] = a[t];
 }
 
+// a2 (z) for the lifted score: the z transform of each radius component kept
+// apart, out [s][c][mz][my][mx], times the deconvolution if `deconv` is set
+// (the fixed shape's component spectra) or plain (the rotated shape's, whose
+// deconvolution is in the product's factor).  Same transforms, in the same
+// order, as z_accumulate.
+template <int M, int COLS>
+__global__ __launch_bounds__(kThreads) void k_fft_z_components(const float2* __restrict__ in, int q,
+                                                               const double* __restrict__ deconv,
+                                                               float2* __restrict__ out,
+                                                               const float2* __restrict__ twm,
+                                                               const int* __restrict__ bin_start, int64_t nk, int w) {
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H;
+    using P = RegPass<M, COLS>;
+    extern __shared__ float2 lds[];
+    __shared__ unsigned char zlive[M];
+    float2* a = lds;
+    float2* twl = a + M * COLS;
+    const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
+    auto dst = [&](int c) { return out + (((size_t)s * q + c) * N * N) * H + (size_t)iy * H + c0; };
+    if (iy == N / 2) {
+        for (int c = 0; c < q; ++c)
+            for (int t = threadIdx.x; t < N * COLS; t += kThreads)
+                dst(c)[(size_t)(t / COLS) * N * H + t % COLS] = make_float2(0.f, 0.f);
+        return;
+    }
+    load_table<M>(twl, twm);
+    for (int t = threadIdx.x; t < M; t += kThreads)
+        zlive[t] = zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, t);
+    __syncthreads();
+    for (int c = 0; c < q; ++c) {
+        const float2* src = in + (((size_t)s * q + c) * M) * N * H + (size_t)iy * H + c0;
+        float2 v[P::NBF][8];
+#pragma unroll
+        for (int u = 0; u < P::NBF; ++u) {
+            const int t = u * kThreads + (int)threadIdx.x;
+            if (P::WORK % kThreads == 0 || t < P::WORK) {
+                const int cc = t % COLS, j = t / COLS;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int z = j + r * P::NB;
+                    v[u][r] = zlive[z] ? src[(size_t)z * N * H + cc] : make_float2(0.f, 0.f);
+                }
+            }
+        }
+        fft_cols_regs<M, -1, COLS>(v, a, twl);
+        float2* d = dst(c);
+        for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
+            const int o = t / COLS, cc = t % COLS;
+            const int si = kept_source<N, M>(o);
+            float2 g = si < 0 ? make_float2(0.f, 0.f) : a[si * COLS + cc];
+            if (deconv) {
+                const float f = (float)(deconv[c0 + cc] * deconv[iy] * deconv[o]);
+                g = make_float2(g.x * f, g.y * f);
+            }
+            d[(size_t)o * N * H + cc] = g;
+        }
+        __syncthreads();  // `a` is read out before the next component's pass
+    }
+}
+
+// The fixed shape's side of one lifted slice: for every kept mode,
+//   H[p'] = sum_p G_A[p] tab[p][p'][|m|^2]
+// (G_A: its deconvolved component spectra), so that the slice's spectrum is
+// sum_p' H[p'] conj(G_RB[p']) times the product's factor.  Arrays [c][mz][my][mx].
+__global__ __launch_bounds__(kThreads) void k_lift_h(const float2* __restrict__ ga, int qa,
+                                                     const float* __restrict__ tab, int qb, int m2n, int n,
+                                                     float2* __restrict__ hh) {
+    const int half = n / 2;
+    const size_t modes = (size_t)n * n * half;
+    const size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= modes) return;
+    const int mx = (int)(i % half), iy = (int)((i / half) % n), iz = (int)(i / ((size_t)half * n));
+    const int my = iy < half ? iy : iy - n, mz = iz < half ? iz : iz - n;
+    if (iy == half || iz == half) {
+        for (int c = 0; c < qb; ++c) hh[(size_t)c * modes + i] = make_float2(0.f, 0.f);
+        return;
+    }
+    const int m2 = mx * mx + my * my + mz * mz;
+    float2 g[32];
+    for (int p = 0; p < qa; ++p) g[p] = ga[(size_t)p * modes + i];
+    for (int c = 0; c < qb; ++c) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int p = 0; p < qa; ++p) {
+            const float t = tab[((size_t)p * qb + c) * m2n + m2];
+            acc.x = fmaf(g[p].x, t, acc.x);
+            acc.y = fmaf(g[p].y, t, acc.y);
+        }
+        hh[(size_t)c * modes + i] = acc;
+    }
+}
+
+// a4 + inverse z of one lifted slice, from the rotated shape's component z
+// sums comps [s][c][mz][my][mx]:
+//   S = sum_c H[c] conj(comps[s][c]) * prod_d D(m_d) exp(i k_d o_d) / L,
+// components summed in order, then the unnormalised inverse transform along z.
+template <int M, int COLS>
+__global__ __launch_bounds__(kThreads) void k_lift_product_ifft_z(const float2* __restrict__ comps, int q,
+                                                                  const double2* __restrict__ phase,
+                                                                  const float2* __restrict__ hh,
+                                                                  float2* __restrict__ out,
+                                                                  const float2* __restrict__ twn) {
+    constexpr int N = ColShape<M>::N, H = ColShape<M>::H;
+    extern __shared__ float2 lds[];
+    float2* a = lds;
+    float2* twnl = a + N * COLS;
+    const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
+    float2* dst = out + (size_t)s * N * N * H + (size_t)iy * H + c0;
+    if (iy == N / 2) {
+        for (int t = threadIdx.x; t < N * COLS; t += kThreads)
+            dst[(size_t)(t / COLS) * N * H + t % COLS] = make_float2(0.f, 0.f);
+        return;
+    }
+    load_table<N>(twnl, twn);
+    const size_t modes = (size_t)N * N * H;
+    const float2* src = comps + (size_t)s * q * modes + (size_t)iy * H + c0;
+    const float2* hs = hh + (size_t)iy * H + c0;
+    using P = RegPass<N, COLS>;
+    float2 v[P::NBF][8];
+#pragma unroll
+    for (int u = 0; u < P::NBF; ++u) {
+        const int t = u * kThreads + (int)threadIdx.x;
+        if (P::WORK % kThreads == 0 || t < P::WORK) {
+            const int cc = t % COLS, j = t / COLS;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int o = j + r * P::NB;
+                float2 acc = make_float2(0.f, 0.f);
+                for (int c = 0; c < q; ++c) {
+                    const float2 g = src[(size_t)c * modes + (size_t)o * N * H + cc];
+                    const float2 hc = hs[(size_t)c * modes + (size_t)o * N * H + cc];
+                    // hc * conj(g)
+                    acc.x = fmaf(hc.x, g.x, fmaf(hc.y, g.y, acc.x));
+                    acc.y = fmaf(hc.y, g.x, fmaf(-hc.x, g.y, acc.y));
+                }
+                v[u][r] = cmul(acc, shift_factor(phase, N, c0 + cc, iy, o));
+            }
+        }
+    }
+    fft_cols_regs<N, 1, COLS>(v, a, twnl);
+    for (int t = threadIdx.x; t < N * COLS; t += kThreads) dst[(size_t)(t / COLS) * N * H + t % COLS] = a[t];
+}
+
 // a5: inverse y over [s][z][my][mx] -> [s][z][y][mx].  A workgroup reads all of
 // its columns before it writes them back, so in == out (in place) is allowed.
 template <int M, int COLS>
@@ -1735,6 +1917,50 @@ hipError_t launch_product_ifft_z(const Geom& g, const float2* d_acc, int S, cons
             constexpr int COLS = decltype(cc)::value;
             hipLaunchKernelGGL((k_product_ifft_z<M, COLS>), dim3(C::H / COLS, C::N, S), dim3(kThreads),
                                sizeof(float2) * ((size_t)C::N * COLS + C::N), st, d_acc, d_phase, d_fa, d_out, d_twn);
+        });
+    });
+}
+
+hipError_t launch_lift_table(const Geom& g, double dk, const double* d_na, int qa, const double* d_nb, int qb,
+                             double h, float* d_tab, hipStream_t st) {
+    hipLaunchKernelGGL(k_lift_table, dim3((g.m2n + 127) / 128, qa * qb), dim3(128), 0, st, g.m2n, dk, d_na, qa, d_nb,
+                       qb, h, d_tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_z_components(const Geom& g, const float2* d_in, int S, int q, const Occupancy& occ,
+                                   const double* d_deconv, float2* d_out, const float2* d_twm, hipStream_t st) {
+    if (S == 0) return hipSuccess;
+    return with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        using C = ColShape<M>;
+        return with_cols<typename C::Z>(g.cols_z, [&](auto cc) {
+            constexpr int COLS = decltype(cc)::value;
+            hipLaunchKernelGGL((k_fft_z_components<M, COLS>), dim3(C::H / COLS, C::N, S), dim3(kThreads),
+                               sizeof(float2) * ((size_t)M * COLS + M), st, d_in, q, d_deconv, d_out, d_twm,
+                               occ.bin_start, occ.nk, g.w);
+        });
+    });
+}
+
+hipError_t launch_lift_h(const Geom& g, const float2* d_ga, int qa, const float* d_tab, int qb, float2* d_h,
+                         hipStream_t st) {
+    const size_t modes = (size_t)g.n * g.n * g.half;
+    hipLaunchKernelGGL(k_lift_h, dim3((unsigned)((modes + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, d_ga, qa,
+                       d_tab, qb, g.m2n, g.n, d_h);
+    return hipGetLastError();
+}
+
+hipError_t launch_lift_product_ifft_z(const Geom& g, const float2* d_comps, int S, int q, const double2* d_phase,
+                                      const float2* d_h, float2* d_out, const float2* d_twn, hipStream_t st) {
+    return with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        using C = ColShape<M>;
+        return with_cols<typename C::IY>(g.cols_iy, [&](auto cc) {
+            constexpr int COLS = decltype(cc)::value;
+            hipLaunchKernelGGL((k_lift_product_ifft_z<M, COLS>), dim3(C::H / COLS, C::N, S), dim3(kThreads),
+                               sizeof(float2) * ((size_t)C::N * COLS + C::N), st, d_comps, q, d_phase, d_h, d_out,
+                               d_twn);
         });
     });
 }

@@ -82,6 +82,9 @@ GOOD = np.array([[0.0, 0.0, 0.0, 0.05, 1.0], [0.1, 0.0, 0.0, 0.04, 1.0]])
     (dict(sc=(0.01, -2.0)), pkg.CORR_EINVAL),
     (dict(sc=(float("nan"), 2.0)), pkg.CORR_EINVAL),
     (dict(sc=(0.01, float("inf"))), pkg.CORR_EINVAL),
+    (dict(lift=-0.01), pkg.CORR_EINVAL),
+    (dict(lift=float("nan")), pkg.CORR_EINVAL),
+    (dict(lift=0.01, sc=(0.01, 1.0)), pkg.CORR_EINVAL),
 ])
 def test_create_rejects_bad_grids(lib, bad, code):
     rc, out = _create(GOOD, GOOD, _grid(**bad))
@@ -168,6 +171,13 @@ def test_batch_rejects_bad_arguments(lib):
     assert "pair 0" in pkg._batch_lib().corr_batch_last_error(None).decode()
     assert blib.corr_batch_eval(None, None, None, None, None, None, None) == pkg.CORR_EINVAL
     assert blib.corr_batch_destroy(None) == pkg.CORR_OK
+
+
+def test_lift_range_needs_its_flag(lib):
+    g = _grid()
+    g.lift_range = 0.01
+    rc, out = _create(GOOD, GOOD, g)
+    assert rc == pkg.CORR_EINVAL and not out.value
 
 
 def test_complementarity_parameters_need_their_flag(lib):
