@@ -23,6 +23,9 @@ Two oracles, both written from Behandish & Ilies (CAD 2016):
   height h is the sum over pairs of the 4D volume W of the intersection of a
   downward and an upward cone, in closed form; ``o2_lift_*`` is its
   band-limited Fourier route.
+* ``raster_*`` -- the uniform-grid baseline of Sec. 5.2 / Sec. 6.2: both
+  unions sampled on the translation lattice, and the number of samples where
+  they meet, counted directly for each translation.
 * ``obstacle``, ``o1_obstacle_points``, ``offset_balls`` -- the configuration
   obstacle as the positive set of the score (Sec. 3.1 eq. eq_obs), its
   pairwise Minkowski-sum form, and the offset slices (Sec. 3.1).
@@ -74,6 +77,8 @@ def _load():
         lib.orc_lift_what.argtypes = [d, d]
         lib.orc_o1_lift_grid.argtypes = [p, i64, p, i64, p, p, d, i32, d, p]
         lib.orc_o2_lift_spectrum.argtypes = [p, i64, p, i64, p, i32, d, d, p, p]
+        lib.orc_raster_bitmaps.argtypes = [p, i64, p, i64, p, p, d, i32, p, p]
+        lib.orc_raster_counts.argtypes = [p, p, i32, p, i64, p]
         lib.orc_set_threads.argtypes = [i32]
         lib.orc_get_threads.restype = i32
         _lib = lib
@@ -366,3 +371,33 @@ def o2_lift_scores(A, B, q, n, L, origin, height) -> np.ndarray:
     ph = (np.exp(1j * k * origin[2])[:, None, None] * np.exp(1j * k * origin[1])[None, :, None]
           * np.exp(1j * k * origin[0])[None, None, :])
     return np.real(np.fft.ifftn(G * ph / L ** 3)) * n ** 3
+
+
+# ---- rasterization baseline (Sec. 5.2, Sec. 6.2) ---------------------------------
+
+def raster_bitmaps(A, B, R, origin, h, n):
+    """Sample grids [z][y][x] (uint8): A at origin + h u, R B at h v (v signed, FFT order)."""
+    lib = _load()
+    A, B, R, o = _f64(A), _f64(B), _f64(R), _f64(origin)
+    a = np.zeros((n, n, n), np.uint8)
+    b = np.zeros((n, n, n), np.uint8)
+    lib.orc_raster_bitmaps(_ptr(A), len(A), _ptr(B), len(B), _ptr(R), _ptr(o), float(h), int(n), _ptr(a), _ptr(b))
+    return a, b
+
+
+def raster_counts(a, b, idx) -> np.ndarray:
+    """sum_u a(u) b(u - t) (periodic) at translation indices idx [k][3] = (tx, ty, tz)."""
+    lib = _load()
+    n = a.shape[0]
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).reshape(-1, 3))
+    out = np.empty(len(idx), np.int64)
+    lib.orc_raster_counts(_ptr(np.ascontiguousarray(a)), _ptr(np.ascontiguousarray(b)), int(n), _ptr(idx), len(idx),
+                          _ptr(out))
+    return out
+
+
+def raster_counts_grid(A, B, q, n, L, origin) -> np.ndarray:
+    """Counts at every translation index, [tz][ty][tx] (O(n^6): small n only)."""
+    a, b = raster_bitmaps(A, B, quat_to_rot(q), origin, L / n, n)
+    t = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)[:, ::-1]
+    return raster_counts(a, b, t).reshape(n, n, n)

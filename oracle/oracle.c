@@ -46,6 +46,15 @@
  * sum of c_i d_j W over pairs; its 3D Fourier transform in t is
  *     What(k; P) = 4 pi^2 (x^3 cos x - 6 x^2 sin x - 15 x cos x + 15 sin x) / (3 k^7),
  * x = k P, which equals integral_0^P Bhat(k; u) Bhat(k; P - u) du.
+ *
+ * raster_*: the uniform-grid baseline of Sec. 5.2 / Sec. 6.2 (rasterize each
+ * union, correlate the two grids).  The fixed shape is sampled at
+ * origin + h u, the moved shape (turned by R) at h v, u, v in [0, n)^3 (v
+ * read periodically as -n/2 .. n/2-1), a sample being 1 when it lies in some
+ * ball (|p - c|^2 <= r^2 in FP64).  The count at translation index t is
+ * sum_u a(u) b(u - t) with periodic indices: the number of grid samples
+ * where the fixed shape meets the moved one translated by origin + h t; its
+ * volume estimate is h^3 times the count.
  */
 #include <math.h>
 #include <omp.h>
@@ -397,6 +406,71 @@ void orc_o2_lift_spectrum(const double *A, int64_t nA, const double *B, int64_t 
         free(ef);
     }
     free(rb);
+}
+
+/* ---- rasterization baseline ------------------------------------------------ */
+
+static int inside_any(const double *p, const double *c, const double *r2, int64_t nb)
+{
+    for (int64_t i = 0; i < nb; ++i) {
+        double dx = p[0] - c[3 * i], dy = p[1] - c[3 * i + 1], dz = p[2] - c[3 * i + 2];
+        if (dx * dx + dy * dy + dz * dz <= r2[i]) return 1;
+    }
+    return 0;
+}
+
+/* The two sample grids, [z][y][x] bytes: a(u) of A at origin + h u, b(v) of
+ * R B at h v with v the signed index of FFT order (v - n for v >= n/2). */
+void orc_raster_bitmaps(const double *A, int64_t nA, const double *B, int64_t nB, const double *R,
+                        const double *origin, double h, int n, unsigned char *a, unsigned char *b)
+{
+    double *ca = (double *)malloc(sizeof(double) * 3 * (size_t)(nA > 0 ? nA : 1));
+    double *ra = (double *)malloc(sizeof(double) * (size_t)(nA > 0 ? nA : 1));
+    double *cb = (double *)malloc(sizeof(double) * 3 * (size_t)(nB > 0 ? nB : 1));
+    double *rb = (double *)malloc(sizeof(double) * (size_t)(nB > 0 ? nB : 1));
+    for (int64_t i = 0; i < nA; ++i) {
+        ca[3 * i] = A[5 * i];
+        ca[3 * i + 1] = A[5 * i + 1];
+        ca[3 * i + 2] = A[5 * i + 2];
+        ra[i] = A[5 * i + 3] * A[5 * i + 3];
+    }
+    for (int64_t j = 0; j < nB; ++j) {
+        rotate(R, B + 5 * j, cb + 3 * j);
+        rb[j] = B[5 * j + 3] * B[5 * j + 3];
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < n; ++x) {
+                size_t i = ((size_t)z * n + y) * n + x;
+                double pa[3] = {origin[0] + h * x, origin[1] + h * y, origin[2] + h * z};
+                double pb[3] = {h * (x < n / 2 ? x : x - n), h * (y < n / 2 ? y : y - n), h * (z < n / 2 ? z : z - n)};
+                a[i] = (unsigned char)inside_any(pa, ca, ra, nA);
+                b[i] = (unsigned char)inside_any(pb, cb, rb, nB);
+            }
+    free(ca); free(ra); free(cb); free(rb);
+}
+
+/* counts[k] = sum_u a(u) b(u - t_k) (periodic indices) at the translation
+ * indices t_k = (tx, ty, tz) of idx[3k..3k+2]. */
+void orc_raster_counts(const unsigned char *a, const unsigned char *b, int n, const int *idx, int64_t nt,
+                       int64_t *counts)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nt; ++k) {
+        int tx = idx[3 * k], ty = idx[3 * k + 1], tz = idx[3 * k + 2];
+        int64_t c = 0;
+        for (int z = 0; z < n; ++z) {
+            int bz = ((z - tz) % n + n) % n;
+            for (int y = 0; y < n; ++y) {
+                int by = ((y - ty) % n + n) % n;
+                const unsigned char *ar = a + ((size_t)z * n + y) * n;
+                const unsigned char *br = b + ((size_t)bz * n + by) * n;
+                for (int x = 0; x < n; ++x) c += ar[x] & br[((x - tx) % n + n) % n];
+            }
+        }
+        counts[k] = c;
+    }
 }
 
 /* Threads of the OpenMP loops above (timing only: results do not depend on
