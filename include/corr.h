@@ -181,7 +181,9 @@ int corr_info(const corr_ctx* ctx, corr_info_t* out);
 #define CORR_STAGE_GRAPH         10  /* a whole evaluation replayed as one hipGraph
                                         (corr_tuning.graph); its stages are not timed
                                         one by one                                      */
-#define CORR_N_STAGES            11
+#define CORR_STAGE_RASTER        11  /* the rasterization baseline (corr_raster_eval),
+                                        one rotation                                    */
+#define CORR_N_STAGES            12
 
 /* Turn per-stage timing on (enable != 0) or off.  While on, every stage launch
  * on the context's stream is bracketed by a pair of HIP events. */
@@ -228,6 +230,24 @@ int corr_query(corr_ctx* ctx, const double* quat_wxyz, const double* t_host, int
  */
 int corr_query_noalloc(corr_ctx* ctx, const double* quat_wxyz, const double* t_host, int64_t n_t,
                        int32_t mode_radius2, float* out_dev, int64_t* n_modes);
+
+/*
+ * The uniform-rasterization baseline (Sec. 5.2 and Sec. 6.2: the grid method
+ * the nonequispaced route is compared with).  Both unions are sampled on the
+ * context's translation grid: A at origin + h u and B, turned by rotation r, at
+ * h v (u, v in [0, n)^3, v read as the signed index of FFT order), a sample
+ * being 1 when it lies in some ball (|p - c|^2 <= r^2, FP64).  The two sample
+ * grids are correlated by FFT (FP64: one packed forward transform, the
+ * pointwise product, one inverse transform), so that
+ *   counts_dev[r][tz][ty][tx] = sum_u a(u) b(u - t)   (periodic indices)
+ * is the exact number of samples where A meets B moved by origin + h t; h^3
+ * times it estimates vol(A & (R B + t)), the overlap of the two unions (a ball
+ * overlap inside a shape counts once).  counts_dev: device int32
+ * [n_rot][n][n][n]; quat_wxyz host [n_rot][4].  Independent of the score kind
+ * set at create.  Works on buffers grown on demand (n^3 x 16 bytes).
+ * Asynchronous.
+ */
+int corr_raster_eval(corr_ctx* ctx, const double* quat_wxyz, int64_t n_rot, int32_t* counts_dev);
 
 /* ---- configuration obstacles and offset slices --------------------------- */
 

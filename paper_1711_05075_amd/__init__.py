@@ -34,14 +34,14 @@ CORR_MAX_SLICES = 16
 
 EXPORTS = ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
            "corr_profile_read", "corr_pass_info", "corr_query", "corr_query_noalloc", "corr_set_offsets",
-           "corr_eval_slices", "corr_spread_work", "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune",
+           "corr_eval_slices", "corr_spread_work", "corr_raster_eval", "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune",
            "corr_destroy", "corr_last_error",
            "corr_batch_create",
            "corr_batch_eval", "corr_batch_set_graph",
            "corr_batch_info", "corr_batch_profile", "corr_batch_profile_read", "corr_batch_spread_work",
            "corr_batch_destroy", "corr_batch_last_error")
 STAGES = ("rotate", "bin", "spread_fft_x", "fft_y", "fft_z_spectrum", "fft_z_product", "ifft_y", "ifft_x", "peak",
-          "query", "graph")
+          "query", "graph", "raster")
 
 
 class corr_grid(ctypes.Structure):
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH):
     lib.corr_profile_read.argtypes = [vp, vp, vp, i32]
     lib.corr_pass_info.argtypes = [vp, ctypes.POINTER(corr_pass_t)]
     lib.corr_spread_work.argtypes = [vp, vp]
+    lib.corr_raster_eval.argtypes = [vp, vp, i64, vp]
     lib.corr_query.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(ctypes.c_int64)]
     lib.corr_query_noalloc.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(ctypes.c_int64)]
     lib.corr_set_offsets.argtypes = [vp, vp, i32]
@@ -118,7 +119,7 @@ def load_library(path: str = LIB_PATH):
     lib.corr_last_error.restype = ctypes.c_char_p
     for name in ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_info", "corr_profile",
                  "corr_profile_read", "corr_pass_info", "corr_query", "corr_query_noalloc", "corr_set_offsets",
-                 "corr_eval_slices", "corr_spread_work", "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune", "corr_destroy"):
+                 "corr_eval_slices", "corr_spread_work", "corr_raster_eval", "corr_get_tuning", "corr_set_tuning", "corr_tuning_choices", "corr_autotune", "corr_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -183,6 +184,12 @@ def corr_pass_info(ctx) -> dict:
     r = corr_pass_t()
     _check(load_library().corr_pass_info(ctx, ctypes.byref(r)), ctx)
     return {k: getattr(r, k) for k, _ in corr_pass_t._fields_}
+
+
+def corr_raster_eval(ctx, quats, counts_ptr):
+    """Voxel-overlap counts of the rasterization baseline into counts_ptr (int32 [n_rot][n][n][n])."""
+    q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
+    _check(load_library().corr_raster_eval(ctx, q.ctypes.data if len(q) else None, len(q), counts_ptr or None), ctx)
 
 
 def corr_spread_work(ctx) -> dict:
@@ -381,6 +388,15 @@ class Correlator:
         with torch.cuda.device(self.device):
             nm = corr_query(self.ctx, quat, t, mode_radius2, out.data_ptr() if len(t) else None)
         return out, nm
+
+    def raster(self, quats):
+        """Counts of the rasterization baseline, int32 [rotations][n][n][n]."""
+        torch = self.torch
+        q = np.asarray(quats, dtype=np.float64).reshape(-1, 4)
+        out = torch.empty((len(q), self.n, self.n, self.n), dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            corr_raster_eval(self.ctx, q, out.data_ptr())
+        return out
 
     def spectrum(self, which, quat=None):
         torch = self.torch

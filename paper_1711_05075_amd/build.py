@@ -25,7 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 # the correlation kernels contract no multiply-add on their own: their fused
 # operations are written out, so results are bitwise the same for every launch
 # shape the autotuner may pick
-PER_FILE = {"corr_kernels.hip": ["-ffp-contract=off"]}
+PER_FILE = {"corr_kernels.hip": ["-ffp-contract=off"], "raster_kernels.hip": ["-ffp-contract=off"]}
 
 
 def _hipcc() -> str:
@@ -47,8 +47,8 @@ def build_library(verbose: bool = False) -> str:
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs, cmds = [], []
-    for src, lang in (("corr_kernels.hip", "hip"), ("corr_host.cpp", "hip"), ("prop_kernels.hip", "hip"),
-                      ("prop_host.cpp", "hip")):
+    for src, lang in (("corr_kernels.hip", "hip"), ("raster_kernels.hip", "hip"), ("corr_host.cpp", "hip"),
+                      ("prop_kernels.hip", "hip"), ("prop_host.cpp", "hip")):
         obj = os.path.join(bdir, src + ".o")
         cmds.append([hipcc, "-x", lang, "--offload-arch=" + ARCH, *COMMON, *DEVICE_FLAGS, *PER_FILE.get(src, []),
                      "-c", os.path.join(CSRC, src), "-o", obj])

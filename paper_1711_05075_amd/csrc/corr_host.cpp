@@ -375,6 +375,7 @@ struct Shape {
     float* wts = nullptr;   // [q][n]
     float* vtab = nullptr;  // [q][m2n]
     double* d_nodes = nullptr;  // [p] radius nodes of the expansion (device)
+    double* rad = nullptr;      // [n] radii (device; the rasterization baseline)
 };
 
 // One offset slice: A's balls with every radius changed by delta, and its spectrum.
@@ -576,6 +577,7 @@ struct corr_ctx {
         size_t cap = 0;
     };
     Grown q_modes, q_part, q_P, q_t, q_quat, q_tpart;
+    Grown r_grid, r_tw, r_quat;  // rasterization baseline: sample grid, FP64 twiddles, rotations
     double* q_host = nullptr;  // pinned staging of the rotation and translations
     size_t q_host_cap = 0;
     hipEvent_t q_done = nullptr;  // the last copy out of q_host
@@ -643,6 +645,7 @@ void upload_shape(corr_ctx* c, DevMem& mem, Shape& s, const corr_ball* balls, do
     const Expansion& e = s.ex;
     const int64_t n = s.n;
     s.pos = mem.alloc<double>((size_t)3 * std::max<int64_t>(n, 1));
+    s.rad = mem.alloc<double>((size_t)std::max<int64_t>(n, 1));
     s.wts = mem.alloc<float>((size_t)e.q * std::max<int64_t>(n, 1));
     s.vtab = mem.alloc<float>((size_t)e.q * c->g.m2n);
     if (n > 0) {
@@ -664,6 +667,9 @@ void upload_shape(corr_ctx* c, DevMem& mem, Shape& s, const corr_ball* balls, do
             }
         }
         upload(s.pos, pos.data(), sizeof(double) * pos.size(), c->stream);
+        std::vector<double> rad((size_t)n);
+        for (int64_t i = 0; i < n; ++i) rad[i] = balls[i].r;
+        upload(s.rad, rad.data(), sizeof(double) * rad.size(), c->stream);
         upload(s.wts, w.data(), sizeof(float) * w.size(), c->stream);
         // fixed-point scale: one knot adds w_ic times window values <= 1 to a
         // sum, so with 2^30 / max |w_ic| every addend fits an int32 (converted
@@ -2026,6 +2032,39 @@ int corr_query_noalloc(corr_ctx* c, const double* quat_wxyz, const double* t_hos
         hip_check(corr::launch_query(g, qp, d_modes, nm, dq, B.pos, B.wts, B.n, B.ex.q, B.vtab, c->box, part, c->fa, P,
                                      dt, n_t, tpart, out_dev, c->stream),
                   "query");
+    });
+}
+
+int corr_raster_eval(corr_ctx* c, const double* quat_wxyz, int64_t n_rot, int32_t* counts_dev) {
+    if (!c) {
+        g_thread_error = "corr_raster_eval: NULL context";
+        return CORR_EINVAL;
+    }
+    return guarded(c, [&] {
+        if (n_rot < 0) fail(CORR_EINVAL, "n_rot = %lld", (long long)n_rot);
+        if (n_rot == 0) return;
+        if (!counts_dev) fail(CORR_EINVAL, "counts_dev is NULL");
+        validate_quats(quat_wxyz, n_rot);
+        join_a(c);
+        const Geom& g = c->g;
+        const size_t n3 = (size_t)g.n * g.n * g.n;
+        auto* grid = static_cast<double2*>(grow(c, c->r_grid, sizeof(double2) * n3));
+        auto* dq = static_cast<double*>(grow(c, c->r_quat, sizeof(double) * 4 * (size_t)n_rot));
+        if (!c->r_tw.p) {
+            std::vector<double2> tw(g.n);
+            for (int j = 0; j < g.n; ++j)
+                tw[j] = make_double2(std::cos(2.0 * M_PI * j / g.n), -std::sin(2.0 * M_PI * j / g.n));
+            auto* d = static_cast<double2*>(grow(c, c->r_tw, sizeof(double2) * g.n));
+            upload(d, tw.data(), sizeof(double2) * g.n, c->stream);
+        }
+        upload(dq, quat_wxyz, sizeof(double) * 4 * (size_t)n_rot, c->stream);
+        const double h = c->box / g.n;
+        for (int64_t r = 0; r < n_rot; ++r)
+            stage(c, CORR_STAGE_RASTER, "raster", [&] {
+                return corr::launch_raster_counts(g.n, h, c->origin, c->A.pos, c->A.rad, c->A.n, c->B.pos, c->B.rad,
+                                                  c->B.n, dq + 4 * r, static_cast<const double2*>(c->r_tw.p), grid,
+                                                  counts_dev + r * n3, c->stream);
+            });
     });
 }
 

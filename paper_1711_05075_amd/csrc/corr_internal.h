@@ -148,6 +148,17 @@ hipError_t launch_ifft_x(const Geom& g, const float2* d_in, int S, float* d_scor
 hipError_t launch_peak_final(const float* d_pval, const int* d_pidx, const int* d_pcnt, int S, int nblocks,
                              float* d_peak_val, int64_t* d_peak_idx, int64_t* d_count, hipStream_t st);
 
+// ---- uniform-rasterization baseline (raster_kernels.hip) ------------------
+// Voxel-overlap counts of one rotation: both shapes sampled on the n^3 grid
+// (A at origin + h u, B turned by d_quat at h v, v signed), the grids
+// correlated by an FP64 FFT in d_grid (n^3 double2, overwritten), and
+// d_counts [n^3] (int32, [tz][ty][tx]) = sum_u a(u) b(u - t), exact.
+// d_tw [n] = exp(-2 pi i j / n) in FP64.
+hipError_t launch_raster_counts(int n, double h, const double origin[3], const double* d_pos_a, const double* d_rad_a,
+                                int64_t na, const double* d_pos_b, const double* d_rad_b, int64_t nb,
+                                const double* d_quat, const double2* d_tw, double2* d_grid, int32_t* d_counts,
+                                hipStream_t st);
+
 // ---- single-configuration query -------------------------------------------
 // d_modes: nm packed modes (mx + 512) | (my + 512) << 10 | (mz + 512) << 20 of the
 // half space.  Scratch: d_part float2 [chunks][nm], d_P float2 [nm], d_tpart
