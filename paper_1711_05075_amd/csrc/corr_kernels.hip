@@ -710,6 +710,7 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
     const int* sc_ = scell + (int64_t)s * nk;
     const float* kb_ = skbw + (int64_t)s * nk * 3 * w;
     const float* wq_ = swts + (int64_t)s * nk * q;
+    if (c0 >= c1) return false;  // no component to spread (never staged: weights would be read past q)
     tile_ranges<M>(bin_start + (size_t)s * (SS::KEYS + 1), w, y0, z0, rstart, rpre);
     __syncthreads();
     const int ncand = rpre[nr];
@@ -865,7 +866,11 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __res
         for (int b = kPlanBuckets - 1; b >= 0; --b) {
             first[b] = run;
             size[b] = plan[b];
-            parts[b] = cut && b >= kSplitBucket ? min(kSplitParts, (q + 1) / 2) : 1;
+            // every part gets at least one component pair: with ppp pairs per
+            // part, only ceil(pairs / ppp) parts are needed (6 pairs in at most
+            // 5 parts are 3 parts of 2)
+            const int pairs = (q + 1) / 2, ppp = (pairs + min(kSplitParts, pairs) - 1) / min(kSplitParts, pairs);
+            parts[b] = cut && b >= kSplitBucket ? (pairs + ppp - 1) / ppp : 1;
             run += size[b] * parts[b];
         }
         total = run;
@@ -881,7 +886,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __res
         const int id = list[(size_t)b * list_cap + e];
         const int s = id / TILES, tile = id % TILES;
         const int ppp = ((q + 1) / 2 + parts[b] - 1) / parts[b];  // component pairs per part
-        const int c0 = 2 * part * ppp, c1 = min(c0 + 2 * ppp, q);  // c0 < q as parts <= pairs
+        const int c0 = 2 * part * ppp, c1 = min(c0 + 2 * ppp, q);  // c0 < q: no part is empty
         if (spread_tile<M>(s, tile / NTY, (tile % NTY) * SS::TY, tile % NTY, c0, c1, bin_start, tile_live, scell,
                            skbw, swts, nk, q, w, cap, fix_scale, fix_inv, out, lds, wave_tot, rstart, rpre))
             wrote += (unsigned long long)SS::TY * (M / 4) * sizeof(float2) * (c1 - c0);
