@@ -487,16 +487,17 @@ def _cpu_oracles(cases, s_of, sample, torch, plain=None):
     return cpu, per_pair
 
 
-def measure_uneven(args, torch, pkg, cpu=True):
+def measure_uneven(args, torch, pkg, cpu=True, kb_width=None):
     """The uneven batch: 64 pairs, ball counts log-uniform in [500, 50000],
     grids of 32^3, 64^3 or 128^3, 32 rotations each, in one corr_batch_eval
     call (scores and peaks), timed launch by launch and as one replayed
     hipGraph; per-stage event times and the spreading kernel's work record
     from one more call; the oracles on a bounded sample."""
     dev = torch.device("cuda:0")
+    w = kb_width or args.kb_width
     t_setup = time.perf_counter()
     cases = synth.uneven_batch_case()
-    b = pkg.Batch([(A, B, g.n, g.box, g.origin) for A, B, q, g in cases], device=dev)
+    b = pkg.Batch([(A, B, g.n, g.box, g.origin) for A, B, q, g in cases], device=dev, kb_width=w)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     quats = [q for A, B, q, g in cases]
@@ -540,7 +541,8 @@ def measure_uneven(args, torch, pkg, cpu=True):
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "uneven batch: 64 pairs of Gaussian-mixture ball shapes, ball counts log-uniform "
                                   "in [500, 50000], translation grids 32^3/64^3/128^3 per pair, 32 rotations each, "
-                                  "sigma 2, KB width 8, one corr_batch_eval call (scores and peaks)",
+                                  "sigma 2, KB width %d, one corr_batch_eval call (scores and peaks)" % w,
+                      "kb_width": w,
                       "pairs": len(cases), "pairs_per_n": {str(n): ns.count(n) for n in (32, 64, 128)},
                       "correlations": nrot, "rot_trans_per_step": total_rt,
                       "balls": int(sum(len(A) + len(B) for A, B, q, g in cases))},
@@ -695,6 +697,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kb-width", type=int, default=6,
+                    help="Kaiser-Bessel window width of the uneven batch (its configuration leaves it open; 6 keeps "
+                         "the error against FP64 near 5e-6, 8 near 1e-6, both within 1e-4)")
     ap.add_argument("--no-extras", action="store_true",
                     help="report the uneven batch only (no single-rotation, batched or proposal keys)")
     ap.add_argument("--no-proposal", action="store_true", help="leave the proposal workflow out of the extras")
@@ -760,6 +765,10 @@ def main():
         return
     t0 = time.perf_counter()
     out = measure_uneven(args, torch, pkg, cpu=not args.no_cpu_baseline)
+    if not args.no_extras and args.kb_width != 8:
+        # the same batch at the default window width, for comparison
+        w8 = measure_uneven(args, torch, pkg, cpu=False, kb_width=8)
+        out["uneven_kb_width_8"] = {k: w8[k] for k in ("value", "unit", "ms_per_step", "roofline")}
     if not args.no_extras:
         single = measure_single(args, torch, pkg)
         out["single_rotation"] = {k: single[k] for k in single if k not in (

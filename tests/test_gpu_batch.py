@@ -68,16 +68,18 @@ def test_small_uneven_batch_scores(pkg, slots):
     b.close()
 
 
-def test_full_uneven_batch_largest_pairs_elementwise():
+@pytest.mark.parametrize("w", [8, 6])
+def test_full_uneven_batch_largest_pairs_elementwise(w):
     import paper_1711_05075_amd as pkg
     # the full uneven batch in the launch configuration the benchmark times
     # (64 pairs, ball counts log-uniform in [500, 50000], grids of 32^3, 64^3
     # or 128^3, 32 rotations each, rotations per pass chosen per pair), scores
     # of the largest pair of each grid size compared element by element with
-    # the FP64 oracle at rotations 0 and 31, and the peaks of the smallest
+    # the FP64 oracle at rotations 0 and 31, and the peaks of the smallest; at
+    # the default window width and at the width the benchmark runs it with
     cases = synth.uneven_batch_case()
-    _say("case: 64-pair uneven batch, 32 rotations each (2048 correlations), scores kept")
-    b = pkg.Batch([(A, B, g.n, g.box, g.origin) for A, B, q, g in cases])
+    _say("case: 64-pair uneven batch, 32 rotations each (2048 correlations), KB width %d, scores kept" % w)
+    b = pkg.Batch([(A, B, g.n, g.box, g.origin) for A, B, q, g in cases], kb_width=w)
     scores, pv, pi, offs = b.eval([q for A, B, q, g in cases], scores=True)
     torch.cuda.synchronize()
     pv, pi = pv.cpu().numpy(), pi.cpu().numpy()
