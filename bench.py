@@ -520,6 +520,17 @@ def measure_uneven(args, torch, pkg, cpu=True, kb_width=None):
     b.set_graph(True)
     rows["graph"] = _timed(torch, step, args.warmup, args.steps)
     b.set_graph(False)
+    tuned = None
+    if not args.no_autotune:
+        # the library's batch autotuner (launch shapes of every pair), then timed
+        # launch by launch and as a graph under the kept tuning
+        t0 = time.perf_counter()
+        tuned = b.autotune(quats, (s, pv, pi), reps=1)
+        tuned["seconds"] = time.perf_counter() - t0
+        rows["autotuned"] = _timed(torch, step, args.warmup, args.steps)
+        b.set_graph(True)
+        rows["autotuned graph"] = _timed(torch, step, args.warmup, args.steps)
+        b.set_graph(False)
     for k, ms in rows.items():
         print("uneven batch, %s: %.3f ms" % (k, ms), file=sys.stderr, flush=True)
     best = min(rows, key=rows.get)
@@ -546,7 +557,7 @@ def measure_uneven(args, torch, pkg, cpu=True, kb_width=None):
                       "pairs": len(cases), "pairs_per_n": {str(n): ns.count(n) for n in (32, 64, 128)},
                       "correlations": nrot, "rot_trans_per_step": total_rt,
                       "balls": int(sum(len(A) + len(B) for A, B, q, g in cases))},
-           "modes_ms": rows, "best_mode": best, "setup_s": t_setup,
+           "modes_ms": rows, "best_mode": best, "setup_s": t_setup, "autotuned": tuned,
            "rotations_per_pass_by_n": {k: sorted(v) for k, v in slots.items()},
            "stages_ms_per_step": {k: v[0] for k, v in prof.items() if v[1]},
            "stage_launches_per_step": {k: v[1] for k, v in prof.items() if v[1]},

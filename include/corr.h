@@ -441,6 +441,22 @@ int corr_batch_set_graph(corr_batch* b, int32_t enable);
 
 int corr_batch_info(const corr_batch* b, int32_t pair, corr_info_t* out);
 
+/*
+ * Autotuner of a batch: runs corr_batch_eval (these arguments) under candidate
+ * launch shapes applied to every pair and keeps the fastest, by coordinate
+ * descent: spread_wgs (one, one and a half or two per CU), then each column
+ * pass's width by rank among each pair's own choices (0 the pair's default, 1
+ * and 2 the others of corr_tuning_choices where its grid has them).  Rotations
+ * per pass stay as planned at create.  Each candidate is timed by HIP events
+ * as the least of `reps` (1..100) runs after an untimed one.  No tuning
+ * changes a bit of the outputs, which hold the last evaluation.  Synchronous.
+ * out5 (host int32 [5], or NULL): spread_wgs and the four ranks kept.  After
+ * an error the pairs' previous tunings are restored.
+ */
+int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* rot_offsets, float* scores_dev,
+                        const int64_t* score_offsets, float* peak_val_dev, int64_t* peak_idx_dev, int32_t reps,
+                        int32_t* out5);
+
 /* corr_profile / corr_profile_read over every pair of the batch (the read
  * sums the pairs' stage times and launch counts), and corr_spread_work of the
  * batch's shared workspace. */

@@ -39,7 +39,7 @@ EXPORTS = ("corr_create", "corr_prepare_a", "corr_eval", "corr_spectrum", "corr_
            "corr_batch_create",
            "corr_batch_eval", "corr_batch_set_graph",
            "corr_batch_info", "corr_batch_profile", "corr_batch_profile_read", "corr_batch_spread_work",
-           "corr_batch_destroy", "corr_batch_last_error")
+           "corr_batch_autotune", "corr_batch_destroy", "corr_batch_last_error")
 STAGES = ("rotate", "bin", "spread_fft_x", "fft_y", "fft_z_spectrum", "fft_z_product", "ifft_y", "ifft_x", "peak",
           "query", "graph", "raster")
 
@@ -582,8 +582,8 @@ class Proposer:
 # ---- uneven batches (corr_batch_*) ---------------------------------------------
 
 BATCH_EXPORTS = ("corr_batch_create", "corr_batch_eval", "corr_batch_set_graph", "corr_batch_info",
-                 "corr_batch_profile", "corr_batch_profile_read", "corr_batch_spread_work", "corr_batch_destroy",
-                 "corr_batch_last_error")
+                 "corr_batch_profile", "corr_batch_profile_read", "corr_batch_spread_work", "corr_batch_autotune",
+                 "corr_batch_destroy", "corr_batch_last_error")
 
 
 class corr_pair(ctypes.Structure):
@@ -602,6 +602,7 @@ def _batch_lib():
         lib.corr_batch_profile.argtypes = [vp, i32]
         lib.corr_batch_profile_read.argtypes = [vp, vp, vp, i32]
         lib.corr_batch_spread_work.argtypes = [vp, vp]
+        lib.corr_batch_autotune.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp]
         lib.corr_batch_destroy.argtypes = [vp]
         lib.corr_batch_last_error.argtypes = [vp]
         lib.corr_batch_last_error.restype = ctypes.c_char_p
@@ -721,6 +722,23 @@ class Batch:
                 out.append(s[o:o + c * n ** 3].view(c, n, n, n))
                 o += c * n ** 3
         return out, pv, pi, offs
+
+    def autotune(self, quats_per_pair, out, reps=2):
+        """Run corr_batch_autotune on these rotations with the caller's output
+        tensors out = (packed scores or None, peak_val, peak_idx); returns the
+        kept choice {spread_wgs, rank of each column pass's width}."""
+        counts = [len(q) for q in quats_per_pair]
+        offs = np.ascontiguousarray(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64))
+        q = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64).reshape(-1, 4)
+                                                 for x in quats_per_pair]))
+        s, pv, pi = out
+        res = np.zeros(5, dtype=np.int32)
+        with self.torch.cuda.device(self.device):
+            _bcheck(_batch_lib().corr_batch_autotune(self.b, q.ctypes.data, offs.ctypes.data,
+                                                     s.data_ptr() if s is not None else None, None, pv.data_ptr(),
+                                                     pi.data_ptr(), int(reps), res.ctypes.data), self.b)
+        return {"spread_wgs": int(res[0]), "rank_cols_y": int(res[1]), "rank_cols_z": int(res[2]),
+                "rank_cols_iy": int(res[3]), "rank_pairs_ix": int(res[4])}
 
     def info(self, pair):
         return corr_batch_info(self.b, pair)

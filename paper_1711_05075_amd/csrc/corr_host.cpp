@@ -2241,6 +2241,120 @@ int corr_batch_profile_read(corr_batch* b, double* ms, int64_t* launches, int32_
     return CORR_OK;
 }
 
+int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* rot_offsets, float* scores_dev,
+                        const int64_t* score_offsets, float* peak_val_dev, int64_t* peak_idx_dev, int32_t reps,
+                        int32_t* out5) {
+    if (!b) {
+        g_thread_error = "corr_batch_autotune: NULL batch";
+        return CORR_EINVAL;
+    }
+    if (reps < 1 || reps > 100) {
+        b->err = "corr_batch_autotune: reps must be in 1..100";
+        return CORR_EINVAL;
+    }
+    // a candidate: spread_wgs and, per column pass, the rank of the width among
+    // each pair's choices (0 its default, 1 and 2 the others where they exist)
+    struct Cand {
+        int wgs;
+        int rank[4];
+    };
+    std::vector<corr_tuning> start;
+    for (corr_ctx* c : b->pairs) start.push_back(get_tuning(c));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = guarded(nullptr, [&] {
+        hip_check(hipEventCreate(&e0), "hipEventCreate");
+        hip_check(hipEventCreate(&e1), "hipEventCreate");
+    });
+    if (rc != CORR_OK) {
+        b->err = g_thread_error;
+        return rc;
+    }
+    auto apply = [&](const Cand& k) {
+        for (size_t i = 0; i < b->pairs.size(); ++i) {
+            corr_ctx* c = b->pairs[i];
+            corr_tuning t = start[i];
+            t.spread_wgs = k.wgs;
+            int32_t corr_tuning::*fields[4] = {&corr_tuning::cols_y, &corr_tuning::cols_z, &corr_tuning::cols_iy,
+                                               &corr_tuning::pairs_ix};
+            for (int p = 0; p < 4; ++p) {
+                int ch[3];
+                const int n = corr::col_choices(c->g.m, p, ch);
+                t.*fields[p] = ch[k.rank[p] < n ? k.rank[p] : 0];
+            }
+            set_tuning(c, t);
+        }
+    };
+    float best_ms = INFINITY;
+    Cand cur{start.empty() ? 1 : start[0].spread_wgs, {0, 0, 0, 0}};
+    auto timed = [&](const Cand& k) -> float {
+        apply(k);
+        auto unit = [&] {
+            const int r = corr_batch_eval(b, quat_wxyz, rot_offsets, scores_dev, score_offsets, peak_val_dev,
+                                          peak_idx_dev);
+            if (r != CORR_OK) throw CorrError{r, b->err};
+        };
+        unit();  // untimed: first touch, graph capture
+        float best = INFINITY;
+        for (int r = 0; r < reps; ++r) {
+            hip_check(hipEventRecord(e0, b->stream), "hipEventRecord");
+            unit();
+            hip_check(hipEventRecord(e1, b->stream), "hipEventRecord");
+            hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            best = std::min(best, ms);
+        }
+        return best;
+    };
+    rc = guarded(nullptr, [&] {
+        const int cus = b->pairs.empty() ? 1 : cu_count(b->pairs[0]);
+        best_ms = timed(cur);
+        for (int v : {cus, cus + cus / 2, 2 * cus}) {
+            if (v == cur.wgs) continue;
+            Cand k = cur;
+            k.wgs = v;
+            const float ms = timed(k);
+            if (ms < best_ms) {
+                best_ms = ms;
+                cur = k;
+            }
+        }
+        for (int p = 0; p < 4; ++p)
+            for (int r = 1; r < 3; ++r) {
+                Cand k = cur;
+                k.rank[p] = r;
+                const float ms = timed(k);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    cur = k;
+                }
+            }
+        apply(cur);
+        // the outputs hold an evaluation under the kept tuning
+        const int r = corr_batch_eval(b, quat_wxyz, rot_offsets, scores_dev, score_offsets, peak_val_dev, peak_idx_dev);
+        if (r != CORR_OK) throw CorrError{r, b->err};
+        hip_check(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    });
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != CORR_OK) {
+        (void)hipStreamSynchronize(b->stream);
+        for (size_t i = 0; i < b->pairs.size(); ++i) {
+            try {
+                set_tuning(b->pairs[i], start[i]);
+            } catch (...) {
+            }
+        }
+        b->err = g_thread_error;
+        return rc;
+    }
+    if (out5) {
+        out5[0] = cur.wgs;
+        for (int p = 0; p < 4; ++p) out5[1 + p] = cur.rank[p];
+    }
+    return CORR_OK;
+}
+
 int corr_batch_info(const corr_batch* b, int32_t pair, corr_info_t* out) {
     if (!b || pair < 0 || pair >= (int32_t)b->pairs.size()) {
         g_thread_error = "corr_batch_info: bad batch or pair index";

@@ -247,6 +247,45 @@ def test_batch_graph_replays_match_the_eager_batch():
     b.close()
 
 
+def test_batch_autotune_keeps_every_bit():
+    # the batch autotuner tries every spreading workgroup count and every width
+    # rank of every column pass on all pairs; whatever it keeps, and every
+    # candidate it ran (the outputs hold the last), the results stay bitwise
+    from paper_1711_05075_amd import Batch
+    pairs, quats = [], []
+    for p, (n, na, nb) in enumerate(((32, 700, 300), (64, 1500, 900), (128, 400, 500), (32, 2500, 1200))):
+        A = synth.mixture_balls(na, 1200 + p)
+        B = synth.mixture_balls(nb, 2200 + p)
+        g = synth.grid_for(A, B, n)
+        pairs.append((A, B, n, g.box, g.origin))
+        quats.append(synth.random_quaternions(3 + p, 3200 + p))
+    _say("case: batch autotuner, 4 pairs (n = 32, 64, 128, 32), 3..6 rotations")
+    b = Batch(pairs)
+    ref = b.eval(quats, scores=True)
+    torch.cuda.synchronize()
+    ref_s = [x.clone() for x in ref[0]]
+    ref_pv, ref_pi = ref[1].clone(), ref[2].clone()
+    total = sum(len(q) * n ** 3 for q, n in zip(quats, b.ns))
+    dev = torch.device("cuda:0")
+    s = torch.empty(total, dtype=torch.float32, device=dev)
+    pv = torch.empty(len(np.concatenate(quats)), dtype=torch.float32, device=dev)
+    pi = torch.empty_like(pv, dtype=torch.int64)
+    kept = b.autotune(quats, (s, pv, pi), reps=1)
+    torch.cuda.synchronize()
+    _say("  kept %s" % kept)
+    off = 0
+    for x, q, n in zip(ref_s, quats, b.ns):
+        assert torch.equal(s[off:off + len(q) * n ** 3].view(len(q), n, n, n), x)
+        off += len(q) * n ** 3
+    assert torch.equal(pv, ref_pv) and torch.equal(pi, ref_pi)
+    # and a plain evaluation under the kept tuning
+    got = b.eval(quats, scores=True)
+    torch.cuda.synchronize()
+    for x, y in zip(got[0], ref_s):
+        assert torch.equal(x, y)
+    b.close()
+
+
 def test_side_stream_spectrum_of_a_is_joined_everywhere():
     # corr_prepare_a runs on a side stream; every later call must see its result
     import paper_1711_05075_amd as pkg
