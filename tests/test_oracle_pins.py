@@ -433,6 +433,40 @@ def test_sc_four_terms_equal_the_signed_union():
     assert G.min() < 0 < G.max()
 
 
+def test_sc_cross_terms_are_two_functions():
+    # Sec. 4.2 writes the expanded score with one cross term taken twice
+    # (-2 lam). With S (+) B0 read as every ball grown by r0, the cross terms
+    # are g(A+, B) and g(A, B+): equal for one ball each of equal radius, but
+    # not in general. Concentric balls, closed form: the overlap is the smaller ball.
+    a, b, r0, lam = 0.1, 0.2, 0.02, 2.0
+    A = np.array([[0.0, 0.0, 0.0, a, 1.0]])
+    B = np.array([[0.0, 0.0, 0.0, b, 1.0]])
+    t0 = np.zeros((1, 3))
+    gA = oracle.o1_points(oracle.sc_grown(A, r0), B, np.eye(3), t0)[0]
+    gB = oracle.o1_points(A, oracle.sc_grown(B, r0), np.eye(3), t0)[0]
+    vol = lambda r: 4.0 * np.pi / 3.0 * r ** 3
+    assert gA == pytest.approx(vol(a + r0), rel=1e-12)
+    assert gB == pytest.approx(vol(a), rel=1e-12)
+    G = oracle.o1_sc_grid(A, B, np.eye(3), (0.0, 0.0, 0.0), 1.0, 1, r0, lam)[0, 0, 0]
+    # the four-term score at t = 0 by hand: V(a+r0, b+r0) = vol(a+r0), ...
+    assert G == pytest.approx(vol(a + r0) - lam * vol(a + r0) - lam * vol(a) + lam * lam * vol(a), rel=1e-12)
+    merged = vol(a + r0) - 2 * lam * gA + lam * lam * vol(a)
+    assert abs(merged - G) > 0.5 * abs(G)
+    # one ball each of equal radius: the two cross terms agree by symmetry
+    t = np.array([[0.05, 0.0, 0.0], [0.13, 0.04, -0.02]])
+    Ae = np.array([[0.0, 0.0, 0.0, 0.1, 1.0]])
+    e1 = oracle.o1_points(oracle.sc_grown(Ae, r0), Ae, np.eye(3), t)
+    e2 = oracle.o1_points(Ae, oracle.sc_grown(Ae, r0), np.eye(3), t)
+    np.testing.assert_allclose(e1, e2, rtol=1e-12)
+    # a mixture pair at n = 16: the cross terms differ by 0.41 of their peak
+    Am, Bm = synth.mixture_balls(60, 4200), synth.mixture_balls(45, 4300)
+    g = synth.grid_for(Am, Bm, 16, pad=0.04)
+    R = oracle.quat_to_rot(synth.random_quaternions(1, 4400)[0])
+    cA = oracle.o1_grid(oracle.sc_grown(Am, r0), Bm, R, g.origin, g.h, g.n)
+    cB = oracle.o1_grid(Am, oracle.sc_grown(Bm, r0), R, g.origin, g.h, g.n)
+    assert np.abs(cA - cB).max() > 0.05 * cA.max()
+
+
 def test_sc_zero_offset_is_scaled_plain_score():
     # r0 -> 0: a_S = (1 - lam) f_S, so G = (1 - lam)^2 g (O1 and O2)
     A, B, q, g, plain = synth.tiny_case()
