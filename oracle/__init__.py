@@ -43,12 +43,17 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIBRARY names another build of oracle.c (an instrumented one, say);
+# it is loaded as it is, never rebuilt
+_LIB_OVERRIDE = os.environ.get("ORACLE_LIBRARY")
+_LIB = _LIB_OVERRIDE or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
 def build(force: bool = False) -> str:
     """Compile oracle.c with gcc (FP64, no fast-math)."""
+    if _LIB_OVERRIDE:
+        return _LIB
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",

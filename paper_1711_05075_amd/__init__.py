@@ -19,7 +19,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libcorr.so")
+# CORR_LIBRARY names another build of the same library (an instrumented one, say)
+LIB_PATH = os.environ.get("CORR_LIBRARY") or os.path.join(_PKG, "libcorr.so")
 
 CORR_OK = 0
 CORR_EINVAL = -1
