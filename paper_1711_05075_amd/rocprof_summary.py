@@ -1,7 +1,11 @@
 """Short text summaries of rocprofv3 output.
 
   python -m paper_1711_05075_amd.rocprof_summary stats <kernel_stats.csv> <out.txt> "<title>" "<command>"
+      [<kernel_trace.csv> <kernel regex> <K>]
       per-kernel call counts and durations from a --kernel-trace --stats run;
+      with a kernel trace, also the mean duration of every dispatch of the
+      kernels matching the regex (all their instantiations together) and of
+      the last K of them, the launches a program timed itself at its end;
 
   python -m paper_1711_05075_amd.rocprof_summary traffic <kernel regex> <fetch.csv> <write.csv>
       <copy_fetch.csv> <copy_write.csv> <copy bytes> <out.txt> "<commands>"
@@ -36,7 +40,18 @@ def _short(name):
     return re.sub(r"^void ", "", name).split("(")[0].split("::")[-1]
 
 
-def stats(src, dst, title, cmd):
+def family(trace, regex, last):
+    """Mean duration (us) of all dispatches of the kernels matching regex in a
+    kernel-trace CSV, and of the last `last` of them by start time."""
+    d = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+               for r in csv.DictReader(open(trace)) if re.search(regex, r["Kernel_Name"]))
+    if len(d) < last:
+        raise SystemExit("only %d dispatches of /%s/ in %s" % (len(d), regex, trace))
+    tail = d[len(d) - last:]
+    return len(d), sum(x for _, x in d) / len(d) / 1e3, sum(x for _, x in tail) / last / 1e3
+
+
+def stats(src, dst, title, cmd, trace=None, regex=None, last=None):
     rows = list(csv.DictReader(open(src)))
     lines = ["# " + title, "#", "# command (one MI355X, repository root):", "#   " + cmd,
              "# durations in microseconds, from rocprofv3 --kernel-trace --stats", "",
@@ -44,6 +59,12 @@ def stats(src, dst, title, cmd):
     for r in rows:
         lines.append("%-26s %6s %12.1f %10.1f %7.2f" % (_short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e3,
                                                          float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    if trace:
+        last = int(last)
+        n, avg, tail = family(trace, regex, last)
+        lines += ["", "# kernels matching /%s/, every instantiation together (kernel trace):" % regex,
+                  "family_dispatches: %d" % n, "family_avg_us: %.1f" % avg,
+                  "family_last_%d_avg_us: %.1f" % (last, tail)]
     open(dst, "w").write("\n".join(lines) + "\n")
 
 
@@ -86,7 +107,7 @@ def traffic(regex, fetch, write, cfetch, cwrite, copy_bytes, dst, cmds):
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
-        stats(*sys.argv[2:6])
+        stats(*sys.argv[2:9])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:10])
     else:
