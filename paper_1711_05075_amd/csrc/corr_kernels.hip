@@ -458,6 +458,14 @@ struct SpreadShape {
 };
 constexpr int kMaxRanges = 24;  // two key ranges per z-cell of a window of <= 12 cells
 constexpr int kSpreadThreads = 512;
+// Widest window spread from staged window origins (see spread_staged_w8);
+// tiles that span every row of the plane (TY = M) keep the knot's cell, since
+// their rows wrap inside the tile.
+constexpr int kWinMax = 8;
+template <int M>
+__device__ __forceinline__ bool use_win(int w) {
+    return SpreadShape<M>::TY < M && w <= kWinMax;
+}
 
 // z row z0 is live iff some knot's z-cell lies in z0-w/2 .. z0+w/2-1 on the
 // periodic axis; bs are the rotation's key starts (z-cell c owns the keys
@@ -651,7 +659,17 @@ __device__ int stage_block(const int* __restrict__ sc_, const float* __restrict_
     }
     if (keep) {
         const int rk = off + before;
-        st.cell[rk] = packed;
+        if (use_win<M>(w)) {
+            // window origin relative to the tile: first row by (signed), first
+            // column bx; point (dy, dx) adds at row by + dy, column bx + dx
+            const int cy = (packed >> 10) & 1023, cx = packed & 1023;
+            const int ry = (cy - lo - y0 + 2 * M) & (M - 1);
+            const int by = ry < SpreadShape<M>::TY ? ry : ry - M;
+            const int bx = (cx - lo + M) & (M - 1);
+            st.cell[rk] = ((by * SpreadShape<M>::LS + bx) & 0xffff) | (by << 16);
+        } else {
+            st.cell[rk] = packed;
+        }
         st.pos[rk] = p;
         const float2* kw = reinterpret_cast<const float2*>(kb_ + (int64_t)p * 3 * w);
         float2* dx = reinterpret_cast<float2*>(st.wx + rk * w);
@@ -678,6 +696,144 @@ __device__ __forceinline__ float fixed_to_float(unsigned long long u, float inv)
     return (float)(d * (double)inv);
 }
 
+// The staged knots of one block, spread for one component pair into the two
+// planes of fixed-point sums.  Each wave takes U staged knots at a time (every
+// NW-th), a lane per window point, w^2 points per knot: the LDS reads of all U
+// are issued together, then the atomic adds of the lanes that land in the
+// tile.  Used where w^2 fills whole waves (w = 8) or nearly (w = 10).  The sums
+// are exact integers, so the order of the adds does not matter.
+template <int M>
+__device__ __forceinline__ void spread_staged_rows(const SpreadStage& st, int nst, int w, int y0,
+                                                   unsigned long long* __restrict__ acc) {
+    using SS = SpreadShape<M>;
+    constexpr int TY = SS::TY, LS = SS::LS, NW = kSpreadThreads / 64, U = 4;
+    const int lo = w / 2 - 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int dmul = (65536 + w - 1) / w;  // t / w for t < w*w by a multiply
+    for (int i0 = wave; i0 < nst; i0 += U * NW) {
+        for (int t0 = 0; t0 < w * w; t0 += 64) {
+            const int t = t0 + lane;
+            const int ddy = min((t * dmul) >> 16, w - 1), ddx = t - ((t * dmul) >> 16) * w;
+            int packed[U];
+            float wyx[U];
+            float2 c2[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = min(i0 + u * NW, nst - 1);
+                packed[u] = st.cell[i];
+                wyx[u] = st.wy[i * w + ddy] * st.wx[i * w + ddx];
+                c2[u] = st.wq[i];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int cx = packed[u] & 1023, cy = (packed[u] >> 10) & 1023;
+                const int l = (cy - lo - y0 + ddy + 2 * M) & (M - 1);
+                if (i0 + u * NW < nst && t < w * w && l < TY) {
+                    const int off = l * LS + ((cx - lo + ddx + M) & (M - 1));
+                    // |addend| <= 2^30: a 32-bit conversion, sign-extended
+                    atomicAdd(acc + off, (unsigned long long)(long long)__float2int_rn(c2[u].x * wyx[u]));
+                    atomicAdd(acc + TY * LS + off,
+                              (unsigned long long)(long long)__float2int_rn(c2[u].y * wyx[u]));
+                }
+            }
+        }
+    }
+}
+
+// Windows of w <= kWinMax on tiles of fewer rows than the plane use a staged
+// window origin instead of the knot's cell: its first row by relative to the tile (-(w-1) .. TY-1) and its first
+// column bx (0 .. M-1), packed as (by * LS + bx) in the low 16 bits (two's
+// complement) and by in the high 16.  Window point (dy, dx) then adds at LDS
+// word (by * LS + bx) + (dy * LS + dx), with no wrap: a line's columns
+// M .. M+w-2 (inside its padding, LS - M = 8 >= w - 1) collect the points past
+// the periodic edge and are folded back onto columns 0 .. w-2 before the
+// transform.
+__device__ __forceinline__ int win_row(int word) { return word >> 16; }
+__device__ __forceinline__ int win_off(int word) { return (int)(short)(word & 0xffff); }
+
+// w = 8: a knot's 64 window points fill a wave instruction, a lane per point
+// (row lane / 8, column lane % 8).  Each wave takes U staged knots at a time
+// (every NW-th); their LDS reads are issued together, then the atomic adds of
+// the lanes whose row lies in the tile.
+template <int M>
+__device__ __forceinline__ void spread_staged_w8(const SpreadStage& st, int nst,
+                                                 unsigned long long* __restrict__ acc) {
+    using SS = SpreadShape<M>;
+    constexpr int TY = SS::TY, LS = SS::LS, NW = kSpreadThreads / 64, U = 4, W = 8;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ddy = lane >> 3, ddx = lane & 7, loff = ddy * LS + ddx;
+    for (int i0 = wave; i0 < nst; i0 += U * NW) {
+        int word[U];
+        float wyx[U];
+        float2 c2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = min(i0 + u * NW, nst - 1);
+            word[u] = st.cell[i];
+            wyx[u] = st.wy[i * W + ddy] * st.wx[i * W + ddx];
+            c2[u] = st.wq[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i0 + u * NW < nst && (unsigned)(win_row(word[u]) + ddy) < (unsigned)TY) {
+                const int off = win_off(word[u]) + loff;
+                // |addend| <= 2^30: a 32-bit conversion, sign-extended
+                atomicAdd(acc + off, (unsigned long long)(long long)__float2int_rn(c2[u].x * wyx[u]));
+                atomicAdd(acc + TY * LS + off, (unsigned long long)(long long)__float2int_rn(c2[u].y * wyx[u]));
+            }
+        }
+    }
+}
+
+// w = 6: a wave instruction takes three knots' half windows, 3 rows x 6
+// columns each (54 of 64 lanes): lane l serves knot l / 18 of a triple, row
+// (l % 18) / 6 (and that + 3 in the second instruction), column l % 6.  A
+// knot's weights are read once for both halves.  Each wave takes U triples at
+// a time (every NW-th).
+template <int M>
+__device__ __forceinline__ void spread_staged_w6(const SpreadStage& st, int nst,
+                                                 unsigned long long* __restrict__ acc) {
+    using SS = SpreadShape<M>;
+    constexpr int TY = SS::TY, LS = SS::LS, NW = kSpreadThreads / 64, U = 2, W = 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = lane / 18, r = lane - slot * 18, ddy = r / W, ddx = r - ddy * W;
+    const int loff = ddy * LS + ddx;
+    const int ntrip = (nst + 2) / 3;
+    for (int t0 = wave; t0 < ntrip; t0 += U * NW) {
+        int word[U];
+        bool ok[U];
+        float wy0[U], wy1[U], wx[U];
+        float2 c2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = (t0 + u * NW) * 3 + slot;
+            ok[u] = slot < 3 && i < nst;
+            const int ic = min(i, nst - 1);  // a valid index for the reads
+            word[u] = st.cell[ic];
+            wy0[u] = st.wy[ic * W + ddy];
+            wy1[u] = st.wy[ic * W + ddy + 3];
+            wx[u] = st.wx[ic * W + ddx];
+            c2[u] = st.wq[ic];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            const int row = win_row(word[u]) + ddy, off = win_off(word[u]) + loff;
+            if ((unsigned)row < (unsigned)TY) {
+                const float f = wy0[u] * wx[u];
+                atomicAdd(acc + off, (unsigned long long)(long long)__float2int_rn(c2[u].x * f));
+                atomicAdd(acc + TY * LS + off, (unsigned long long)(long long)__float2int_rn(c2[u].y * f));
+            }
+            if ((unsigned)(row + 3) < (unsigned)TY) {
+                const float f = wy1[u] * wx[u];
+                atomicAdd(acc + off + 3 * LS, (unsigned long long)(long long)__float2int_rn(c2[u].x * f));
+                atomicAdd(acc + TY * LS + off + 3 * LS,
+                          (unsigned long long)(long long)__float2int_rn(c2[u].y * f));
+            }
+        }
+    }
+}
+
 // One spreading tile (z row z0, y rows y0 .. y0+TY-1 of rotation s), for the
 // components c0 .. c1-1 (c0 even).  Entered by the whole workgroup; the LDS
 // regions are laid out by the caller.
@@ -690,8 +846,7 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
     constexpr int H = M / 4;  // half of the n = M/2 kept modes along x
     using SS = SpreadShape<M>;
     constexpr int TY = SS::TY, SC = SS::SC, NPTS = SS::NPTS, LS = SS::LS;
-    constexpr int NT = kSpreadThreads, NW = NT / 64;
-    constexpr int U = 4;         // staged knots in flight per wave
+    constexpr int NT = kSpreadThreads;
     static_assert(NPTS % NT == 0, "tile must split evenly over the workgroup");
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds);  // [2][TY][LS]
     float2* a = lds;                                                       // [TY][SC] over the sums
@@ -703,9 +858,6 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
     st.wz = reinterpret_cast<float*>(st.pos + cap);
     st.wx = st.wz + cap;
     st.wy = st.wx + cap * w;
-    const int lo = w / 2 - 1;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int dmul = (65536 + w - 1) / w;  // t / w for t < w*w by a multiply
     const int nr = 2 * w;
     const int* sc_ = scell + (int64_t)s * nk;
     const float* kb_ = skbw + (int64_t)s * nk * 3 * w;
@@ -744,38 +896,9 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
                 const float f = st.wz[threadIdx.x] * fix_scale;
                 nxt = make_float2(wp[0] * f, cp + 3 < q ? wp[1] * f : 0.0f);
             }
-            const int nst = kept;
-            // each wave takes U staged knots at a time, a lane per window point;
-            // the LDS reads of all U (at clamped, valid indices) are issued
-            // together, then the atomic adds of the lanes that land in the tile
-            for (int i0 = wave; i0 < nst; i0 += U * NW) {
-                for (int t0 = 0; t0 < w * w; t0 += 64) {
-                    const int t = t0 + lane;
-                    const int ddy = min((t * dmul) >> 16, w - 1), ddx = t - ((t * dmul) >> 16) * w;
-                    int packed[U];
-                    float wyx[U];
-                    float2 c2[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int i = min(i0 + u * NW, nst - 1);
-                        packed[u] = st.cell[i];
-                        wyx[u] = st.wy[i * w + ddy] * st.wx[i * w + ddx];
-                        c2[u] = st.wq[i];
-                    }
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int cx = packed[u] & 1023, cy = (packed[u] >> 10) & 1023;
-                        const int l = (cy - lo - y0 + ddy + 2 * M) & (M - 1);
-                        if (i0 + u * NW < nst && t < w * w && l < TY) {
-                            const int off = l * LS + ((cx - lo + ddx + M) & (M - 1));
-                            // |addend| <= 2^30: a 32-bit conversion, sign-extended
-                            atomicAdd(acc + off, (unsigned long long)(long long)__float2int_rn(c2[u].x * wyx[u]));
-                            atomicAdd(acc + TY * LS + off,
-                                      (unsigned long long)(long long)__float2int_rn(c2[u].y * wyx[u]));
-                        }
-                    }
-                }
-            }
+            if (use_win<M>(w) && w == 6) spread_staged_w6<M>(st, kept, acc);
+            else if (use_win<M>(w) && w == 8) spread_staged_w8<M>(st, kept, acc);
+            else spread_staged_rows<M>(st, kept, w, y0, acc);
             __syncthreads();
         }
         if (cp == c0) {
@@ -784,6 +907,15 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
             if (kept_all == 0) return false;
         }
         if (prefetch) st.wq[threadIdx.x] = nxt;  // read from the next pair on, after the barriers below
+        if (use_win<M>(w)) {
+            // points past the periodic edge, in columns M .. M+w-2, back onto 0 .. w-2
+            const int wm = w - 1;
+            for (int t = threadIdx.x; t < 2 * TY * wm; t += NT) {
+                const int line = t / wm, col = t - line * wm;
+                acc[line * LS + col] += acc[line * LS + M + col];
+            }
+            __syncthreads();
+        }
         // sums -> FFT input over the same memory, fused with the first radix-8
         // pass of the x transform: each thread converts the eight points of its
         // first butterfly and transforms them in registers
@@ -839,7 +971,7 @@ constexpr int kSplitBucket = 5;  // candidate sets of 256 knots or more
 constexpr int kSplitParts = 5;   // items per cut tile (at most the component pairs)
 
 template <int M>
-__global__ __launch_bounds__(kSpreadThreads) void k_spread_fftx(const int* __restrict__ bin_start,
+__global__ __launch_bounds__(kSpreadThreads, 4) void k_spread_fftx(const int* __restrict__ bin_start,
                                                                 unsigned char* __restrict__ tile_live,
                                                                 int* __restrict__ plan, const int* __restrict__ list,
                                                                 int list_cap, const int* __restrict__ scell,
