@@ -682,15 +682,16 @@ class Batch:
     """Uneven batch of pairs on torch device memory; peaks for every rotation and,
     optionally, the packed scores of every pair."""
 
-    def __init__(self, pairs, slots=0, device=None, kb_width=8):
-        """pairs: list of (A, B, n, box, origin); kb_width: window width of every pair."""
+    def __init__(self, pairs, slots=0, device=None, kb_width=8, tol=1e-6):
+        """pairs: list of (A, B, n, box, origin); kb_width and tol (radius expansion):
+        the same for every pair."""
         import torch
         self.torch = torch
         self.device = torch.device(device or "cuda")
         self.ns = [int(p[2]) for p in pairs]
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
-            self.b = corr_batch_create([(A, B, make_grid(n, box, origin, kb_width=kb_width))
+            self.b = corr_batch_create([(A, B, make_grid(n, box, origin, kb_width=kb_width, tol=tol))
                                         for A, B, n, box, origin in pairs], slots, self.stream.cuda_stream)
 
     def set_graph(self, enable):

@@ -616,23 +616,28 @@ __global__ __launch_bounds__(256) void k_scatter_plan(const int* __restrict__ ce
 // Stage one block of a tile's candidates, [cbeg, cbeg + cnt) of the
 // concatenated key ranges (cnt <= cap <= the workgroup size): those whose
 // window reaches the tile's rows are compacted in order (wave ballots + a
-// block scan) into the staging area with their cell, sorted position, window
-// weights along x and y, the z weight of the tile's row, and the component
-// weights of the pair starting at component cp times that z weight and the
-// fixed-point scale.  Returns how many were kept.  A block never holds more
-// than the staging area, so a tile of many candidates is spread block by
-// block and no candidate is ever scanned twice for one component pair.
-// Entered and left by the whole workgroup.
-template <int M>
+// block scan) into the staging area with their cell (or window origin), sorted
+// position, window weights along x and y, the z weight of the tile's row, and
+// the component weights of the pair starting at component cp times that z
+// weight and the fixed-point scale.  Returns how many were kept.  Every load
+// of a candidate is issued at once, before it is known to be kept: the z
+// weight's index follows from the key range the candidate came from (range j
+// holds z-cell z0 - w/2 + j/2, whose window weight at row z0 is entry
+// w - 1 - j/2), so a block costs one round trip to memory.  A block never
+// holds more than the staging area, so a tile of many candidates is spread
+// block by block and no candidate is ever scanned twice for one component
+// pair.  Entered and left by the whole workgroup.
+template <int M, int W>
 __device__ int stage_block(const int* __restrict__ sc_, const float* __restrict__ kb_,
-                           const float* __restrict__ wq_, int q, int cp, float fix_scale, int w, int y0, int z0,
+                           const float* __restrict__ wq_, int q, int cp, float fix_scale, int y0,
                            const int* rstart, const int* rpre, int nr, int cbeg, int cnt, SpreadStage st,
                            int* wave_tot) {
-    constexpr int TY = SpreadShape<M>::TY;
-    const int lo = w / 2 - 1;
+    constexpr int TY = SpreadShape<M>::TY, LO = W / 2 - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int p = 0, packed = 0;
     bool keep = false;
+    float2 kx[W / 2], ky[W / 2], wq2 = make_float2(0.f, 0.f);
+    float wz = 0.f;
     if ((int)threadIdx.x < cnt) {
         const int ci = cbeg + (int)threadIdx.x;
         int r0 = 0, r1 = nr;  // the range holding ci: rpre[r0] <= ci < rpre[r0 + 1]
@@ -643,9 +648,18 @@ __device__ int stage_block(const int* __restrict__ sc_, const float* __restrict_
         }
         p = rstart[r0] + (ci - rpre[r0]);
         packed = sc_[p];
+        const float2* kw = reinterpret_cast<const float2*>(kb_ + (int64_t)p * 3 * W);
+#pragma unroll
+        for (int d = 0; d < W / 2; ++d) {
+            kx[d] = kw[d];
+            ky[d] = kw[W / 2 + d];
+        }
+        wz = kb_[(int64_t)p * 3 * W + 2 * W + (W - 1 - (r0 >> 1))];
+        const float* wp = wq_ + (int64_t)p * q + cp;
+        wq2 = make_float2(wp[0], cp + 1 < q ? wp[1] : 0.0f);
         const int cy = (packed >> 10) & 1023;
-        const int ry = (cy - lo - y0 + 2 * M) & (M - 1);
-        keep = ry < TY || ry > M - w;
+        const int ry = (cy - LO - y0 + 2 * M) & (M - 1);
+        keep = ry < TY || ry > M - W;
     }
     const unsigned long long mask = __ballot(keep);
     const int before = __popcll(mask & ((1ull << lane) - 1ull));
@@ -659,31 +673,28 @@ __device__ int stage_block(const int* __restrict__ sc_, const float* __restrict_
     }
     if (keep) {
         const int rk = off + before;
-        if (use_win<M>(w)) {
+        if (use_win<M>(W)) {
             // window origin relative to the tile: first row by (signed), first
             // column bx; point (dy, dx) adds at row by + dy, column bx + dx
             const int cy = (packed >> 10) & 1023, cx = packed & 1023;
-            const int ry = (cy - lo - y0 + 2 * M) & (M - 1);
-            const int by = ry < SpreadShape<M>::TY ? ry : ry - M;
-            const int bx = (cx - lo + M) & (M - 1);
+            const int ry = (cy - LO - y0 + 2 * M) & (M - 1);
+            const int by = ry < TY ? ry : ry - M;
+            const int bx = (cx - LO + M) & (M - 1);
             st.cell[rk] = ((by * SpreadShape<M>::LS + bx) & 0xffff) | (by << 16);
         } else {
             st.cell[rk] = packed;
         }
         st.pos[rk] = p;
-        const float2* kw = reinterpret_cast<const float2*>(kb_ + (int64_t)p * 3 * w);
-        float2* dx = reinterpret_cast<float2*>(st.wx + rk * w);
-        float2* dy = reinterpret_cast<float2*>(st.wy + rk * w);
-        for (int d = 0; d < w / 2; ++d) {
-            dx[d] = kw[d];
-            dy[d] = kw[w / 2 + d];
+        float2* dx = reinterpret_cast<float2*>(st.wx + rk * W);
+        float2* dy = reinterpret_cast<float2*>(st.wy + rk * W);
+#pragma unroll
+        for (int d = 0; d < W / 2; ++d) {
+            dx[d] = kx[d];
+            dy[d] = ky[d];
         }
-        const int cz = (packed >> 20) & 1023;
-        const float wz = kb_[(int64_t)p * 3 * w + 2 * w + ((z0 - cz + lo + M) & (M - 1))];
         st.wz[rk] = wz;
-        const float* wp = wq_ + (int64_t)p * q + cp;
         const float f = wz * fix_scale;
-        st.wq[rk] = make_float2(wp[0] * f, cp + 1 < q ? wp[1] * f : 0.0f);
+        st.wq[rk] = make_float2(wq2.x * f, wq2.y * f);
     }
     __syncthreads();
     return total;
@@ -871,8 +882,15 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
     // staged block by block for each pair
     const int nblk = (ncand + cap - 1) / cap;
     auto stage = [&](int b, int cp) {
-        return stage_block<M>(sc_, kb_, wq_, q, cp, fix_scale, w, y0, z0, rstart, rpre, nr, b * cap,
-                              min(cap, ncand - b * cap), st, wave_tot);
+        const int c0b = b * cap, cnt = min(cap, ncand - b * cap);
+        switch (w) {  // the width as a constant: the loaded weights stay in registers
+        case 6: return stage_block<M, 6>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st, wave_tot);
+        case 8: return stage_block<M, 8>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st, wave_tot);
+        case 10: return stage_block<M, 10>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st,
+                                           wave_tot);
+        default: return stage_block<M, 12>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st,
+                                           wave_tot);
+        }
     };
     int kept = nblk == 1 ? stage(0, c0) : 0;  // the single block, staged with the first pair's weights
     if (ncand == 0 || (nblk == 1 && kept == 0)) {
