@@ -61,8 +61,10 @@ hipError_t launch_ball_table(const Geom& g, double dk, const double* d_nodes, co
 
 // ---- pipeline stages -----------------------------------------------------
 // Knots are sorted by key = z-cell * (m / ygroup) + y-cell / ygroup, with
-// y-groups of ygroup(m) cells chosen so that there are at most 8192 keys.
-constexpr int bin_ygroup(int m) { return m * m / 8192 > 1 ? m * m / 8192 : 1; }
+// y-groups of ygroup(m) cells chosen so that there are at most 16384 keys
+// (m = 256: groups of 4 cells, so that a tile of 8 rows and a window of 6
+// reads about 16 candidate cells for the 13 that reach it).
+constexpr int bin_ygroup(int m) { return m * m / 16384 > 1 ? m * m / 16384 : 1; }
 constexpr int bin_keys(int m) { return m * (m / bin_ygroup(m)); }
 // a0, binned: rotate, place, window weights, and each knot's rank among the
 // knots of its key from atomic counters (d_counts [S][keys], zero on entry);

@@ -396,10 +396,10 @@ __global__ __launch_bounds__(kBinBlock) void k_bin_scan(int* __restrict__ counts
     const int s = blockIdx.x;
     int* cs = counts + (size_t)s * keys;
     int* bs = bin_start + (size_t)s * (keys + 1);
-    switch (keys / kBinBlock) {  // keys is 1024, 4096 or 8192
+    switch (keys / kBinBlock) {  // keys is 1024, 4096 or 16384
         case 4: scan_counts<4>(cs, bs, wsum); break;
         case 16: scan_counts<16>(cs, bs, wsum); break;
-        default: scan_counts<32>(cs, bs, wsum); break;
+        default: scan_counts<64>(cs, bs, wsum); break;
     }
     if (threadIdx.x == 0) bs[keys] = (int)nk;
 }
