@@ -422,9 +422,10 @@ struct WsReq {
         for (int k = 0; k < 10; ++k) fit = std::min(fit, (size_t)slots * have[k] / std::max<size_t>(need[k], 1));
         return (int)std::max<size_t>(fit, 1);
     }
+    // device bytes of one slot: the arrays of Workspace below, element by element
     size_t slot_bytes() const {
-        return 4 * buf0 + 8 * buf1 + 4 * (3 * nk + nkw + nkq) + 12 * nkw + 4 * (counts + bins) + 12 * blocks + tiles +
-               4 * list + 32;
+        return 4 * buf0 + 8 * buf1 + 16 * nk /*rec*/ + 8 * nk /*rank, scell*/ + 4 * nkw /*skbw*/ + 4 * nkq /*swts*/ +
+               4 * (counts + bins) + 12 * blocks + tiles + 4 * list + 32 /*quats*/;
     }
 };
 
@@ -434,8 +435,7 @@ struct Workspace {
     DevMem mem;
     float* buf0 = nullptr;         // [slots][q][m][n][half] complex (after y; reused after inverse z)
     float2* buf1 = nullptr;        // [slots][q][m^2][half] (after spread + x; reused after product)
-    int* cell = nullptr;           // [slots][nk] packed cell of each knot
-    float* kbw = nullptr;          // [slots][nk][3][w] window weights
+    int4* rec = nullptr;           // [slots][nk] packed cell of each knot and its offsets from it (FP32 bits)
     int* rank = nullptr;           // [slots][nk] rank among the knots of its sort key
     int* counts = nullptr;         // [slots][keys] knots per sort key; zero between passes
     int* bin_start = nullptr;      // [slots][keys + 1] first sorted knot of each key
@@ -461,8 +461,7 @@ struct Workspace {
         const size_t SQ = (size_t)std::max(nslots, qslots);
         buf0 = mem.alloc<float>(S * r.buf0);
         buf1 = mem.alloc<float2>(S * r.buf1);
-        cell = mem.alloc<int>(S * r.nk);
-        kbw = mem.alloc<float>(S * r.nkw);
+        rec = mem.alloc<int4>(S * r.nk);
         rank = mem.alloc<int>(S * r.nk);
         counts = mem.alloc<int>(S * r.counts);
         // the sort's counters start at zero; every scan clears them again
@@ -744,11 +743,11 @@ void run_spectrum_stages(corr_ctx* c, const Shape& s, const double* d_quats, int
     c->last_nk = s.n;
     c->last_ws = c->ws;
     stage(c, CORR_STAGE_ROTATE, "rotate", [&] {
-        return corr::launch_rotate_bin(g, d_quats, S, s.pos, s.n, c->ws->cell, c->ws->kbw, c->ws->rank, c->ws->counts,
+        return corr::launch_rotate_bin(g, d_quats, S, s.pos, s.n, c->ws->rec, c->ws->rank, c->ws->counts,
                                        c->ws->bin_start, c->ws->plan, c->stream);
     });
     stage(c, CORR_STAGE_BIN, "bin", [&] {
-        return corr::launch_scatter_plan(g, S, q, occupancy(c, s), c->ws->cell, c->ws->kbw, s.wts, c->ws->rank,
+        return corr::launch_scatter_plan(g, S, q, occupancy(c, s), c->ws->rec, s.wts, c->ws->rank,
                                          c->ws->scell, c->ws->skbw, c->ws->swts, c->ws->plan, c->ws->list, c->stream);
     });
     stage(c, CORR_STAGE_SPREAD_FFT_X, "spread + fft x", [&] {

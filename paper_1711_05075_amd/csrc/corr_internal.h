@@ -66,21 +66,21 @@ hipError_t launch_ball_table(const Geom& g, double dk, const double* d_nodes, co
 // reads about 16 candidate cells for the 13 that reach it).
 constexpr int bin_ygroup(int m) { return m * m / 16384 > 1 ? m * m / 16384 : 1; }
 constexpr int bin_keys(int m) { return m * (m / bin_ygroup(m)); }
-// a0, binned: rotate, place, window weights, and each knot's rank among the
-// knots of its key from atomic counters (d_counts [S][keys], zero on entry);
-// then the scan of the counts into d_bin_start [S][keys + 1], which clears
-// them.  Also clears the live-tile plan's counters d_plan.
+// a0, binned: rotate, place (d_rec [S][nk]: packed cell and the FP32 offsets
+// from it), and each knot's rank among the knots of its key from atomic
+// counters (d_counts [S][keys], zero on entry); then the scan of the counts
+// into d_bin_start [S][keys + 1], which clears them.  Also clears the
+// live-tile plan's counters d_plan.
 hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const double* d_pos, int64_t nk,
-                             int* d_cell, float* d_kbw, int* d_rank, int* d_counts, int* d_bin_start, int* d_plan,
-                             hipStream_t st);
-// The scatter of every knot's record (cell, window weights, q component
-// weights) into sorted order, and the live-tile plan: tiles that no knot's
-// window can reach are marked dead in occ.tile_live and the others are listed
-// in d_list by the size of their candidate sets (d_plan: bucket sizes and the
-// spreading pass's work counter).
-hipError_t launch_scatter_plan(const Geom& g, int S, int q, const Occupancy& occ, const int* d_cell,
-                               const float* d_kbw, const float* d_wts, const int* d_rank, int* d_scell, float* d_skbw,
-                               float* d_swts, int* d_plan, int* d_list, hipStream_t st);
+                             int4* d_rec, int* d_rank, int* d_counts, int* d_bin_start, int* d_plan, hipStream_t st);
+// The scatter of every knot into sorted order (its cell, its window weights
+// along x, y and z evaluated from its offsets, its q component weights), and
+// the live-tile plan: tiles that no knot's window can reach are marked dead in
+// occ.tile_live and the others are listed in d_list by the size of their
+// candidate sets (d_plan: bucket sizes and the spreading pass's work counter).
+hipError_t launch_scatter_plan(const Geom& g, int S, int q, const Occupancy& occ, const int4* d_rec,
+                               const float* d_wts, const int* d_rank, int* d_scell, float* d_skbw, float* d_swts,
+                               int* d_plan, int* d_list, hipStream_t st);
 // a1 + a2 (x): gather-spreading of the sorted knots fused with the x transform;
 // writes [S][q][z][y][mx] without a spreading grid in HBM.
 // Sums are exact 64-bit fixed point of 32-bit addends; fix_scale is a power of

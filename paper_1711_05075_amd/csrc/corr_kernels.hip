@@ -342,12 +342,13 @@ __device__ __forceinline__ void scan_counts(int* __restrict__ cs, int* __restric
     for (int k = 0; k < PER / 4; ++k) reinterpret_cast<int4*>(cs + b0)[k] = make_int4(0, 0, 0, 0);
 }
 
-// Rotate + place + window weights + counts per key.  Workgroup (0, 0) also
-// clears the tile plan's counters.
+// Rotate + place + counts per key: each knot's record is its packed cell and
+// its offsets from that cell along x, y and z (FP32, in [0, 1)), from which the
+// scatter evaluates the window weights.  Workgroup (0, 0) also clears the tile
+// plan's counters.
 __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restrict__ quats,
                                                           const double* __restrict__ pos, int64_t nk, double inv_hf,
-                                                          int m, int w, float beta, float inv_i0beta, int yshift,
-                                                          int nyb, int* __restrict__ cell, float* __restrict__ kbw,
+                                                          int m, int yshift, int nyb, int4* __restrict__ rec,
                                                           int* __restrict__ rank, int* __restrict__ counts,
                                                           int* __restrict__ plan, int nplan) {
     const int64_t j = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
@@ -364,10 +365,8 @@ __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restri
         double px = pos[3 * j], py = pos[3 * j + 1], pz = pos[3 * j + 2];
         double u[3] = {(R[0] * px + R[1] * py + R[2] * pz) * inv_hf, (R[3] * px + R[4] * py + R[5] * pz) * inv_hf,
                        (R[6] * px + R[7] * py + R[8] * pz) * inv_hf};
-        const float tw = 2.0f / (float)w;
-        const int lo = w / 2 - 1;
         int c[3];
-        float* kw = kbw + ((int64_t)s * nk + j) * 3 * w;
+        float f3[3];
         for (int d = 0; d < 3; ++d) {
             double fl = floor(u[d]);
             float f = (float)(u[d] - fl);
@@ -378,9 +377,10 @@ __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restri
                 f = 0.0f;
                 c[d] = (c[d] + 1) % m;
             }
-            for (int i = 0; i < w; ++i) kw[d * w + i] = kb_window(f - (float)(i - lo), tw, beta, inv_i0beta);
+            f3[d] = f;
         }
-        cell[(int64_t)s * nk + j] = c[0] | (c[1] << 10) | (c[2] << 20);
+        rec[(int64_t)s * nk + j] = make_int4(c[0] | (c[1] << 10) | (c[2] << 20), __float_as_int(f3[0]),
+                                             __float_as_int(f3[1]), __float_as_int(f3[2]));
         const int key = c[2] * nyb + (c[1] >> yshift);
         rank[(int64_t)s * nk + j] = atomicAdd(&counts[(size_t)s * keys + key], 1);
     }
@@ -405,20 +405,27 @@ __global__ __launch_bounds__(kBinBlock) void k_bin_scan(int* __restrict__ counts
 }
 
 // Scatter knot j of rotation s into sorted position: its packed cell, its
-// window weights and its q component weights.
-__device__ __forceinline__ void bin_scatter(int64_t j, int s, const int* __restrict__ cell,
-                                            const float* __restrict__ kbw, const float* __restrict__ wts,
-                                            const int* __restrict__ rank, const int* __restrict__ bin_start,
-                                            int64_t nk, int keys, int yshift, int nyb, int w, int q,
+// window weights along x, y and z (evaluated here from its offsets, w per
+// axis) and its q component weights.
+__device__ __forceinline__ void bin_scatter(int64_t j, int s, const int4* __restrict__ rec,
+                                            const float* __restrict__ wts, const int* __restrict__ rank,
+                                            const int* __restrict__ bin_start, int64_t nk, int keys, int yshift,
+                                            int nyb, int w, float beta, float inv_i0beta, int q,
                                             int* __restrict__ scell, float* __restrict__ skbw,
                                             float* __restrict__ swts) {
-    const int packed = cell[(int64_t)s * nk + j];
+    const int4 r = rec[(int64_t)s * nk + j];
+    const int packed = r.x;
     const int key = ((packed >> 20) & 1023) * nyb + (((packed >> 10) & 1023) >> yshift);
     const int64_t p = (int64_t)s * nk + bin_start[(size_t)s * (keys + 1) + key] + rank[(int64_t)s * nk + j];
     scell[p] = packed;
-    const float2* src = reinterpret_cast<const float2*>(kbw + ((int64_t)s * nk + j) * 3 * w);
+    const float tw = 2.0f / (float)w;
+    const int lo = w / 2 - 1;
+    const float f3[3] = {__int_as_float(r.y), __int_as_float(r.z), __int_as_float(r.w)};
     float2* dst = reinterpret_cast<float2*>(skbw + p * 3 * w);
-    for (int i = 0; i < 3 * w / 2; ++i) dst[i] = src[i];
+    for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < w; i += 2)
+            dst[(d * w + i) / 2] = make_float2(kb_window(f3[d] - (float)(i - lo), tw, beta, inv_i0beta),
+                                               kb_window(f3[d] - (float)(i + 1 - lo), tw, beta, inv_i0beta));
     for (int c = 0; c < q; ++c) swts[p * q + c] = wts[(size_t)c * nk + j];
 }
 
@@ -595,10 +602,11 @@ __device__ __forceinline__ void tile_plan(int tile, int s, const int* __restrict
 // The scatter of the sorted records (workgroups x < nscatter) and the live-tile
 // plan (the others) of one spreading pass, both reading the key starts.
 template <int M>
-__global__ __launch_bounds__(256) void k_scatter_plan(const int* __restrict__ cell, const float* __restrict__ kbw,
+__global__ __launch_bounds__(256) void k_scatter_plan(const int4* __restrict__ rec,
                                                       const float* __restrict__ wts, const int* __restrict__ rank,
                                                       const int* __restrict__ bin_start, int64_t nk, int yshift,
-                                                      int nyb, int w, int q, int* __restrict__ scell,
+                                                      int nyb, int w, float beta, float inv_i0beta, int q,
+                                                      int* __restrict__ scell,
                                                       float* __restrict__ skbw, float* __restrict__ swts,
                                                       int nscatter, unsigned char* __restrict__ tile_live,
                                                       int* __restrict__ plan, int* __restrict__ list, int list_cap) {
@@ -606,8 +614,8 @@ __global__ __launch_bounds__(256) void k_scatter_plan(const int* __restrict__ ce
     if ((int)blockIdx.x < nscatter) {
         const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
         if (j < nk)
-            bin_scatter(j, s, cell, kbw, wts, rank, bin_start, nk, SpreadShape<M>::KEYS, yshift, nyb, w, q, scell,
-                        skbw, swts);
+            bin_scatter(j, s, rec, wts, rank, bin_start, nk, SpreadShape<M>::KEYS, yshift, nyb, w, beta, inv_i0beta,
+                        q, scell, skbw, swts);
         return;
     }
     tile_plan<M>(((int)blockIdx.x - nscatter) * 256 + threadIdx.x, s, bin_start, w, tile_live, plan, list, list_cap);
@@ -1949,13 +1957,11 @@ int bin_blocks(int64_t nk) { return (int)((nk + kBinBlock - 1) / kBinBlock); }
 }  // namespace
 
 hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const double* d_pos, int64_t nk,
-                             int* d_cell, float* d_kbw, int* d_rank, int* d_counts, int* d_bin_start, int* d_plan,
-                             hipStream_t st) {
+                             int4* d_rec, int* d_rank, int* d_counts, int* d_bin_start, int* d_plan, hipStream_t st) {
     if (nk == 0 || S == 0) return hipSuccess;
     const int G = bin_ygroup(g.m);
     hipLaunchKernelGGL(k_rotate_bin, dim3(bin_blocks(nk), S), dim3(kBinBlock), 0, st, d_quats, d_pos, nk, g.inv_hf,
-                       g.m, g.w, g.beta, g.inv_i0beta, log2i(G), g.m / G, d_cell, d_kbw, d_rank, d_counts, d_plan,
-                       plan_words());
+                       g.m, log2i(G), g.m / G, d_rec, d_rank, d_counts, d_plan, plan_words());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_scan, dim3(S), dim3(kBinBlock), 0, st, d_counts, bin_keys(g.m), nk, d_bin_start);
@@ -1964,18 +1970,18 @@ hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const 
 
 int plan_words() { return kPlanBuckets + 1; }
 
-hipError_t launch_scatter_plan(const Geom& g, int S, int q, const Occupancy& occ, const int* d_cell,
-                               const float* d_kbw, const float* d_wts, const int* d_rank, int* d_scell, float* d_skbw,
-                               float* d_swts, int* d_plan, int* d_list, hipStream_t st) {
+hipError_t launch_scatter_plan(const Geom& g, int S, int q, const Occupancy& occ, const int4* d_rec,
+                               const float* d_wts, const int* d_rank, int* d_scell, float* d_skbw, float* d_swts,
+                               int* d_plan, int* d_list, hipStream_t st) {
     if (occ.nk == 0 || S == 0) return hipSuccess;
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         constexpr int tiles = M * (M / SpreadShape<M>::TY);
         const int G = bin_ygroup(M);
         const int nscatter = bin_blocks(occ.nk);
-        hipLaunchKernelGGL(k_scatter_plan<M>, dim3(nscatter + (tiles + 255) / 256, S), dim3(256), 0, st, d_cell, d_kbw,
-                           d_wts, d_rank, occ.bin_start, occ.nk, log2i(G), M / G, g.w, q, d_scell, d_skbw, d_swts,
-                           nscatter, occ.tile_live, d_plan, d_list, S * tiles);
+        hipLaunchKernelGGL(k_scatter_plan<M>, dim3(nscatter + (tiles + 255) / 256, S), dim3(256), 0, st, d_rec,
+                           d_wts, d_rank, occ.bin_start, occ.nk, log2i(G), M / G, g.w, g.beta, g.inv_i0beta, q,
+                           d_scell, d_skbw, d_swts, nscatter, occ.tile_live, d_plan, d_list, S * tiles);
     });
 }
 
