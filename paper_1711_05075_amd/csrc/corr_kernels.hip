@@ -31,6 +31,31 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Workgroups go to the XCDs in turn (linear id mod kXcds), each XCD with an L2
+// of its own.  xcd_block gives a workgroup its logical block (x fastest) so
+// that the gridDim.x blocks of one (y, z) -- neighbouring column blocks, which
+// read the two halves of the same 128-byte lines -- run one after another on
+// one XCD and share its L2, while successive (y, z) go to the XCDs in turn,
+// which keeps the XCDs evenly loaded.  A bijection of the grid onto itself
+// (a tail of fewer than kXcds whole rows keeps the plain order): every
+// block's work is unchanged.
+constexpr int kXcds = 8;
+struct Blk {
+    int x, y, z;
+};
+__device__ __forceinline__ Blk xcd_block() {
+    const int gx = (int)gridDim.x, gy = (int)gridDim.y;
+    const int total = gx * gy * (int)gridDim.z;
+    const int lin = (int)blockIdx.x + gx * ((int)blockIdx.y + gy * (int)blockIdx.z);
+    const int span = kXcds * gx, main = total - total % span;
+    int lam = lin;
+    if (lin < main) {
+        const int xcd = lin % kXcds, r = lin / kXcds;  // r-th workgroup of this XCD
+        lam = ((r / gx) * kXcds + xcd) * gx + r % gx;
+    }
+    return {lam % gx, (lam / gx) % gy, lam / (gx * gy)};
+}
+
 // This file is built without floating-point contraction: every fused
 // multiply-add is written out (fmaf), so the arithmetic and its rounding are
 // fixed by the source and do not depend on how a kernel is instantiated
@@ -1148,16 +1173,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ i
     __shared__ unsigned char live[NT];
     float2* a = lds;
     float2* twl = a + M * COLS;
-    const int s = blockIdx.z / q;
+    // plain block order: here the XCD-grouped order of the z passes measured
+    // slower (the rows of one slab and z row are then read by one XCD at a time)
+    const Blk b = {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z};
+    const int s = b.z / q;
     const int* bs = bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1);
-    const int c0 = blockIdx.x * COLS;
+    const int c0 = b.x * COLS;
     load_table<M>(twl, twm);
-    for (int z = blockIdx.y * YZB; z < blockIdx.y * YZB + YZB; ++z) {
+    for (int z = b.y * YZB; z < b.y * YZB + YZB; ++z) {
         if (!zrow_live<M>(bs, nk, w, z)) continue;
         __syncthreads();  // the previous row's output has been read out of `a`
         for (int t = threadIdx.x; t < NT; t += kThreads) live[t] = tile_live[((size_t)s * M + z) * NT + t];
         __syncthreads();
-        const size_t plane = (size_t)blockIdx.z * M + z;  // slab * M + z
+        const size_t plane = (size_t)b.z * M + z;  // slab * M + z
         const float2* src = in + plane * M * H + c0;
         using P = RegPass<M, COLS>;
         float2 v[P::NBF][8];
@@ -1277,7 +1305,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __res
     __shared__ unsigned char zlive[M];
     float2* a = lds;
     float2* twl = a + M * COLS;
-    const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
+    const Blk b = xcd_block();
+    const int c0 = b.x * COLS, iy = b.y, s = b.z;
     float2* dst = spec + (size_t)s * N * N * H + (size_t)iy * H + c0;
     if (iy == N / 2) {
         for (int t = threadIdx.x; t < N * COLS; t += kThreads)
@@ -1330,7 +1359,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
     float2* a = lds;
     float2* twl = a + M * COLS;
     float2* twnl = twl + M;
-    const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
+    const Blk b = xcd_block();
+    const int c0 = b.x * COLS, iy = b.y, s = b.z;
     float2* dst = out + (size_t)s * N * N * H + (size_t)iy * H + c0;
     if (iy == N / 2) {
         for (int t = threadIdx.x; t < N * COLS; t += kThreads)
@@ -1369,7 +1399,8 @@ __global__ __launch_bounds__(kThreads) void k_product_ifft_z(const float2* __res
     extern __shared__ float2 lds[];
     float2* a = lds;
     float2* twnl = a + N * COLS;
-    const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
+    const Blk b = xcd_block();
+    const int c0 = b.x * COLS, iy = b.y, s = b.z;
     float2* dst = out + (size_t)s * N * N * H + (size_t)iy * H + c0;
     if (iy == N / 2) {
         for (int t = threadIdx.x; t < N * COLS; t += kThreads)
@@ -1415,7 +1446,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_components(const float2* __r
     __shared__ unsigned char zlive[M];
     float2* a = lds;
     float2* twl = a + M * COLS;
-    const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
+    const Blk b = xcd_block();
+    const int c0 = b.x * COLS, iy = b.y, s = b.z;
     auto dst = [&](int c) { return out + (((size_t)s * q + c) * N * N) * H + (size_t)iy * H + c0; };
     if (iy == N / 2) {
         for (int c = 0; c < q; ++c)
@@ -1503,7 +1535,8 @@ __global__ __launch_bounds__(kThreads) void k_lift_product_ifft_z(const float2* 
     extern __shared__ float2 lds[];
     float2* a = lds;
     float2* twnl = a + N * COLS;
-    const int c0 = blockIdx.x * COLS, iy = blockIdx.y, s = blockIdx.z;
+    const Blk b = xcd_block();
+    const int c0 = b.x * COLS, iy = b.y, s = b.z;
     float2* dst = out + (size_t)s * N * N * H + (size_t)iy * H + c0;
     if (iy == N / 2) {
         for (int t = threadIdx.x; t < N * COLS; t += kThreads)
