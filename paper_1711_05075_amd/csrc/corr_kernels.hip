@@ -958,28 +958,28 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
             if (kept_all == 0) return false;
         }
         if (prefetch) st.wq[threadIdx.x] = nxt;  // read from the next pair on, after the barriers below
-        if (use_win<M>(w)) {
-            // points past the periodic edge, in columns M .. M+w-2, back onto 0 .. w-2
-            const int wm = w - 1;
-            for (int t = threadIdx.x; t < 2 * TY * wm; t += NT) {
-                const int line = t / wm, col = t - line * wm;
-                acc[line * LS + col] += acc[line * LS + M + col];
-            }
-            __syncthreads();
-        }
         // sums -> FFT input over the same memory, fused with the first radix-8
         // pass of the x transform: each thread converts the eight points of its
-        // first butterfly and transforms them in registers
+        // first butterfly and transforms them in registers.  With window
+        // origins, the points past the periodic edge (columns M .. M+w-2) are
+        // added back onto columns 0 .. w-2 here, as integers.
         {
             constexpr int NB0 = M / 8, WORK0 = TY * NB0;
             static_assert(WORK0 <= NT, "one first-pass butterfly per thread");
+            static_assert(!(SS::TY < M) || NB0 >= kWinMax - 1, "edge columns within the first butterflies");
             const int c = threadIdx.x % TY, jb = threadIdx.x / TY;
+            const bool fold = use_win<M>(w) && jb < w - 1;
             float2 v0[8];
             if ((int)threadIdx.x < WORK0) {
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const int e = c * LS + jb + r * NB0;
-                    v0[r] = make_float2(fixed_to_float(acc[e], fix_inv), fixed_to_float(acc[TY * LS + e], fix_inv));
+                    unsigned long long re = acc[e], im = acc[TY * LS + e];
+                    if (r == 0 && fold) {
+                        re += acc[c * LS + M + jb];
+                        im += acc[TY * LS + c * LS + M + jb];
+                    }
+                    v0[r] = make_float2(fixed_to_float(re, fix_inv), fixed_to_float(im, fix_inv));
                 }
                 dft8<-1>(v0);
             }
