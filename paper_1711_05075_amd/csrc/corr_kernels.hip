@@ -1159,54 +1159,67 @@ __device__ __forceinline__ void fft_cols_regs(float2 (&v)[NBF][8], float2* a, co
 }
 
 // a2: y pass over [slab][z][y][mx] -> [slab][z][my][mx], M points pruned to N,
-// slab = rotation * q + component.  A workgroup takes YZB z rows of one slab
-// and column block; dead z rows are skipped (their output is never read) and
-// rows of dead y tiles are zero.
+// slab = rotation * q + component.  A workgroup takes YZB z rows of one
+// rotation and column block, every component of them; dead z rows are skipped
+// (their output is never read) and rows of dead y tiles are zero.
 template <int M, int COLS>
 __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ in, float2* __restrict__ out,
-                                                    const float2* __restrict__ twm, int q,
+                                                    const float2* __restrict__ twm, int q, int cg,
                                                     const int* __restrict__ bin_start,
                                                     const unsigned char* __restrict__ tile_live, int64_t nk, int w) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, YZB = ColShape<M>::YZB;
     constexpr int TY = SpreadShape<M>::TY, NT = M / TY;
+    using P = RegPass<M, COLS>;
     extern __shared__ float2 lds[];
     __shared__ unsigned char live[NT];
     float2* a = lds;
     float2* twl = a + M * COLS;
-    // plain block order: here the XCD-grouped order of the z passes measured
-    // slower (the rows of one slab and z row are then read by one XCD at a time)
-    const Blk b = {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z};
-    const int s = b.z / q;
+    // one workgroup per (column block, z row, rotation, group of cg
+    // components): the group's components of the row are transformed in turn,
+    // the next one's columns read into registers while the current one is
+    // transformed
+    const int ng = (q + cg - 1) / cg;
+    const int s = blockIdx.z / ng, cbeg = (blockIdx.z % ng) * cg, cend = min(q, cbeg + cg);
     const int* bs = bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1);
-    const int c0 = b.x * COLS;
+    const int c0 = blockIdx.x * COLS;
     load_table<M>(twl, twm);
-    for (int z = b.y * YZB; z < b.y * YZB + YZB; ++z) {
+    for (int z = blockIdx.y * YZB; z < blockIdx.y * YZB + YZB; ++z) {
         if (!zrow_live<M>(bs, nk, w, z)) continue;
         __syncthreads();  // the previous row's output has been read out of `a`
         for (int t = threadIdx.x; t < NT; t += kThreads) live[t] = tile_live[((size_t)s * M + z) * NT + t];
         __syncthreads();
-        const size_t plane = (size_t)b.z * M + z;  // slab * M + z
-        const float2* src = in + plane * M * H + c0;
-        using P = RegPass<M, COLS>;
-        float2 v[P::NBF][8];
+        float2 nxt[P::NBF][8];
+        auto fetch = [&](int c) {
+            const float2* src = in + ((size_t)(s * q + c) * M + z) * M * H + c0;
 #pragma unroll
-        for (int u = 0; u < P::NBF; ++u) {
-            const int t = u * kThreads + (int)threadIdx.x;
-            if (P::WORK % kThreads == 0 || t < P::WORK) {
-                const int c = t % COLS, j = t / COLS;
+            for (int u = 0; u < P::NBF; ++u) {
+                const int t = u * kThreads + (int)threadIdx.x;
+                if (P::WORK % kThreads == 0 || t < P::WORK) {
+                    const int cc = t % COLS, j = t / COLS;
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const int y = j + r * P::NB;
-                    v[u][r] = live[y / TY] ? src[(size_t)y * H + c] : make_float2(0.f, 0.f);
+                    for (int r = 0; r < 8; ++r) {
+                        const int y = j + r * P::NB;
+                        nxt[u][r] = live[y / TY] ? src[(size_t)y * H + cc] : make_float2(0.f, 0.f);
+                    }
                 }
             }
-        }
-        fft_cols_regs<M, -1, COLS>(v, a, twl);
-        float2* dst = out + plane * N * H + c0;
-        for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
-            const int o = t / COLS, c = t % COLS;
-            const int si = kept_source<N, M>(o);
-            dst[(size_t)o * H + c] = si < 0 ? make_float2(0.f, 0.f) : a[si * COLS + c];
+        };
+        fetch(cbeg);
+        for (int c = cbeg; c < cend; ++c) {
+            float2 v[P::NBF][8];
+#pragma unroll
+            for (int u = 0; u < P::NBF; ++u)
+#pragma unroll
+                for (int r = 0; r < 8; ++r) v[u][r] = nxt[u][r];
+            if (c + 1 < cend) fetch(c + 1);
+            fft_cols_regs<M, -1, COLS>(v, a, twl);
+            float2* dst = out + ((size_t)(s * q + c) * M + z) * N * H + c0;
+            for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
+                const int o = t / COLS, cc = t % COLS;
+                const int si = kept_source<N, M>(o);
+                dst[(size_t)o * H + cc] = si < 0 ? make_float2(0.f, 0.f) : a[si * COLS + cc];
+            }
+            __syncthreads();  // `a` read out before the next component's transform
         }
     }
 }
@@ -2057,6 +2070,9 @@ hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, int* d
     });
 }
 
+// Fewest workgroups a y-pass grid is given when a row's components are split.
+constexpr long kYMinBlocks = 16384;
+
 hipError_t launch_fft_y(const Geom& g, int S, int q, const Occupancy& occ, const float2* d_in, float2* d_out,
                         const float2* d_twm, hipStream_t st) {
     if (S == 0 || q == 0) return hipSuccess;
@@ -2065,9 +2081,15 @@ hipError_t launch_fft_y(const Geom& g, int S, int q, const Occupancy& occ, const
         using C = ColShape<M>;
         return with_cols<typename C::Y>(g.cols_y, [&](auto cc) {
             constexpr int COLS = decltype(cc)::value;
-            hipLaunchKernelGGL((k_fft_y<M, COLS>), dim3(C::H / COLS, M / C::YZB, S * q), dim3(kThreads),
-                               sizeof(float2) * ((size_t)M * COLS + M), st, d_in, d_out, d_twm, q, occ.bin_start,
-                               occ.tile_live, occ.nk, g.w);
+            // components per workgroup: all of a row's, unless the grid would
+            // then hold fewer than kYMinBlocks workgroups (one rotation of a
+            // shape with many components needs them split to fill the chip)
+            const long rows = (long)(C::H / COLS) * (M / C::YZB) * S;
+            int cg = q;
+            while (cg > 1 && rows * ((q + cg - 1) / cg) < kYMinBlocks) cg = (cg + 1) / 2;
+            hipLaunchKernelGGL((k_fft_y<M, COLS>), dim3(C::H / COLS, M / C::YZB, S * ((q + cg - 1) / cg)),
+                               dim3(kThreads), sizeof(float2) * ((size_t)M * COLS + M), st, d_in, d_out, d_twm, q,
+                               cg, occ.bin_start, occ.tile_live, occ.nk, g.w);
         });
     });
 }
