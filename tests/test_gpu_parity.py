@@ -148,6 +148,23 @@ def test_other_window_widths(w):
     c.close()
 
 
+@pytest.mark.parametrize("w", [6, 8, 12])
+def test_window_widths_on_whole_plane_tiles(w):
+    # at n = 16 a spreading tile spans every row of its plane, so windows wrap
+    # inside the tile and the knot loop keeps each knot's cell instead of a
+    # staged window origin
+    A = synth.mixture_balls(300, 1300 + w)
+    B = synth.mixture_balls(200, 2300 + w)
+    g = synth.grid_for(A, B, 16)
+    q = synth.random_quaternions(3, 3300 + w)
+    _say("case: 300+200 mixture balls, n=16, KB width %d, 3 rotations" % w)
+    c = _corr(A, B, g, kb_width=w)
+    s, _, _ = c.eval(q, peaks=False)
+    torch.cuda.synchronize()
+    _check_scores("n=16 w=%d" % w, s.double().cpu().numpy(), _o2(A, B, q, g))
+    c.close()
+
+
 def test_window_width_4_is_rejected():
     from paper_1711_05075_amd import CorrError, CORR_EUNSUPPORTED
     A, B, q, g, _ = synth.tiny_case()
