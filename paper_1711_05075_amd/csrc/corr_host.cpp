@@ -1026,8 +1026,8 @@ corr::WsReq ws_req(const corr_ctx* c) {
     r.nk = (size_t)c->nkmax;
     r.nkw = (size_t)c->nkmax * 3 * g.w;
     r.nkq = (size_t)c->nkmax * c->qmax;
-    r.counts = (size_t)corr::bin_keys(g.m);
-    r.bins = (size_t)corr::bin_keys(g.m) + 1;
+    r.counts = (size_t)corr::bin_keys_max(g.m);
+    r.bins = (size_t)corr::bin_keys_max(g.m) + 1;
     r.blocks = (size_t)corr::ifft_x_blocks_max(g);  // any inverse-x width
     r.tiles = (size_t)g.m * corr::spread_tiles(g);
     r.list = (size_t)corr::plan_buckets() * r.tiles;
@@ -1407,6 +1407,7 @@ corr_tuning get_tuning(const corr_ctx* c) {
     t.cols_iy = c->g.cols_iy ? c->g.cols_iy : (corr::col_choices(c->g.m, 2, def), def[0]);
     t.pairs_ix = c->g.pairs_ix ? c->g.pairs_ix : (corr::col_choices(c->g.m, 3, def), def[0]);
     t.graph = c->graph ? 1 : 0;
+    t.bin_group = corr::bin_group(c->g);
     return t;
 }
 
@@ -1428,14 +1429,22 @@ void set_tuning(corr_ctx* c, const corr_tuning& t) {
         fail(CORR_EINVAL, "spread_wgs = %d; allowed 1..%d (two per CU)", t.spread_wgs, 2 * cus);
     if (t.slots < 1 || t.slots > 256) fail(CORR_EINVAL, "slots = %d; allowed 1..256", t.slots);
     if (t.graph != 0 && t.graph != 1) fail(CORR_EINVAL, "graph must be 0 or 1");
+    {
+        int bg[3];
+        const int k = corr::bin_choices(c->g.m, bg);
+        bool ok = false;
+        for (int i = 0; i < k; ++i) ok = ok || bg[i] == t.bin_group;
+        if (!ok) fail(CORR_EINVAL, "bin_group = %d is not one of this grid's groups (corr_tuning_choices)", t.bin_group);
+    }
     if (t.slots != c->ws->slots) {
         if (!c->own_ws) fail(CORR_EUNSUPPORTED, "the pairs of a batch share their workspace: slots are fixed");
         replace_workspace(c, t.slots);
     }
     Geom& g = c->g;
     if (g.cols_y != t.cols_y || g.cols_z != t.cols_z || g.cols_iy != t.cols_iy || g.pairs_ix != t.pairs_ix ||
-        g.spread_wgs != t.spread_wgs)
+        g.spread_wgs != t.spread_wgs || corr::bin_group(g) != t.bin_group)
         c->shape_gen++;
+    g.bin_group = t.bin_group;
     g.cols_y = t.cols_y;
     g.cols_z = t.cols_z;
     g.cols_iy = t.cols_iy;
@@ -1516,6 +1525,9 @@ corr_tuning autotune(corr_ctx* c, const double* q, int64_t n_rot, float* scores,
             const int k = corr::col_choices(c->g.m, p, ch);
             try_field(fields[p], std::vector<int>(ch, ch + k));
         }
+        int bg[3];
+        const int kb = corr::bin_choices(c->g.m, bg);
+        try_field(&corr_tuning::bin_group, std::vector<int>(bg, bg + kb));
         set_tuning(c, cur);
     } catch (...) {
         (void)hipStreamSynchronize(c->stream);
@@ -1563,9 +1575,11 @@ int corr_tuning_choices(const corr_ctx* c, int32_t pass, int32_t* out3, int32_t*
         return CORR_EINVAL;
     }
     int ch[3];
-    const int k = (pass >= 0 && pass < 4) ? corr::col_choices(c->g.m, pass, ch) : 0;
+    const int k = (pass >= 0 && pass < 4) ? corr::col_choices(c->g.m, pass, ch)
+                  : pass == 4             ? corr::bin_choices(c->g.m, ch)
+                                          : 0;
     if (k == 0) {
-        g_thread_error = "corr_tuning_choices: pass must be 0..3";
+        g_thread_error = "corr_tuning_choices: pass must be 0..4";
         return CORR_EINVAL;
     }
     for (int i = 0; i < k; ++i) out3[i] = ch[i];
@@ -2242,7 +2256,7 @@ int corr_batch_profile_read(corr_batch* b, double* ms, int64_t* launches, int32_
 
 int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* rot_offsets, float* scores_dev,
                         const int64_t* score_offsets, float* peak_val_dev, int64_t* peak_idx_dev, int32_t reps,
-                        int32_t* out5) {
+                        int32_t* out6) {
     if (!b) {
         g_thread_error = "corr_batch_autotune: NULL batch";
         return CORR_EINVAL;
@@ -2251,11 +2265,12 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
         b->err = "corr_batch_autotune: reps must be in 1..100";
         return CORR_EINVAL;
     }
-    // a candidate: spread_wgs and, per column pass, the rank of the width among
-    // each pair's choices (0 its default, 1 and 2 the others where they exist)
+    // a candidate: spread_wgs and, per column pass and for the bin group, the
+    // rank of the value among each pair's choices (0 its default, 1 and 2 the
+    // others where they exist)
     struct Cand {
         int wgs;
-        int rank[4];
+        int rank[5];
     };
     std::vector<corr_tuning> start;
     for (corr_ctx* c : b->pairs) start.push_back(get_tuning(c));
@@ -2280,11 +2295,14 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
                 const int n = corr::col_choices(c->g.m, p, ch);
                 t.*fields[p] = ch[k.rank[p] < n ? k.rank[p] : 0];
             }
+            int bg[3];
+            const int nb = corr::bin_choices(c->g.m, bg);
+            t.bin_group = bg[k.rank[4] < nb ? k.rank[4] : 0];
             set_tuning(c, t);
         }
     };
     float best_ms = INFINITY;
-    Cand cur{start.empty() ? 1 : start[0].spread_wgs, {0, 0, 0, 0}};
+    Cand cur{start.empty() ? 1 : start[0].spread_wgs, {0, 0, 0, 0, 0}};
     auto timed = [&](const Cand& k) -> float {
         apply(k);
         auto unit = [&] {
@@ -2318,7 +2336,7 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
                 cur = k;
             }
         }
-        for (int p = 0; p < 4; ++p)
+        for (int p = 0; p < 5; ++p)
             for (int r = 1; r < 3; ++r) {
                 Cand k = cur;
                 k.rank[p] = r;
@@ -2347,9 +2365,9 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
         b->err = g_thread_error;
         return rc;
     }
-    if (out5) {
-        out5[0] = cur.wgs;
-        for (int p = 0; p < 4; ++p) out5[1 + p] = cur.rank[p];
+    if (out6) {
+        out6[0] = cur.wgs;
+        for (int p = 0; p < 5; ++p) out6[1 + p] = cur.rank[p];
     }
     return CORR_OK;
 }

@@ -24,6 +24,9 @@ struct Geom {
     // the default, half of it or twice it, see col_choices): forward y, z
     // passes, inverse y and slice products, inverse x (line pairs)
     int cols_y = 0, cols_z = 0, cols_iy = 0, pairs_ix = 0;
+    // y-group of the sort keys (the bins of spreading), in cells: 0 for
+    // bin_ygroup(m), else one of bin_choices(m)
+    int bin_group = 0;
 };
 
 // Widths a column pass may take at spreading-grid size m: out[0] is the
@@ -61,11 +64,22 @@ hipError_t launch_ball_table(const Geom& g, double dk, const double* d_nodes, co
 
 // ---- pipeline stages -----------------------------------------------------
 // Knots are sorted by key = z-cell * (m / ygroup) + y-cell / ygroup, with
-// y-groups of ygroup(m) cells chosen so that there are at most 16384 keys
-// (m = 256: groups of 4 cells, so that a tile of 8 rows and a window of 6
-// reads about 16 candidate cells for the 13 that reach it).
+// y-groups of ygroup(m) cells by default, chosen so that there are at most
+// 16384 keys (m = 256: groups of 4 cells, so that a tile of 8 rows and a
+// window of 6 reads about 16 candidate cells for the 13 that reach it).  The
+// tuning may take half or twice that group where the key count stays within
+// [1024, 32768] (bin_choices); a rotation's key starts always have room for
+// the finest choice.
 constexpr int bin_ygroup(int m) { return m * m / 16384 > 1 ? m * m / 16384 : 1; }
-constexpr int bin_keys(int m) { return m * (m / bin_ygroup(m)); }
+constexpr int bin_ygroup_min(int m) {
+    return bin_ygroup(m) > 1 && m * m / (bin_ygroup(m) / 2) <= 32768 ? bin_ygroup(m) / 2 : bin_ygroup(m);
+}
+constexpr int bin_keys_max(int m) { return m * (m / bin_ygroup_min(m)); }
+// Groups a grid of spreading size m may take: out[0] the default, then half
+// and twice it where allowed.  Returns the count (1..3).
+int bin_choices(int m, int out[3]);
+// The group a geometry uses.
+inline int bin_group(const Geom& g) { return g.bin_group > 0 ? g.bin_group : bin_ygroup(g.m); }
 // a0, binned: rotate, place (d_rec [S][nk]: packed cell and the FP32 offsets
 // from it), and each knot's rank among the knots of its key from atomic
 // counters (d_counts [S][keys], zero on entry); then the scan of the counts

@@ -373,12 +373,12 @@ __device__ __forceinline__ void scan_counts(int* __restrict__ cs, int* __restric
 // plan's counters.
 __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restrict__ quats,
                                                           const double* __restrict__ pos, int64_t nk, double inv_hf,
-                                                          int m, int yshift, int nyb, int4* __restrict__ rec,
-                                                          int* __restrict__ rank, int* __restrict__ counts,
-                                                          int* __restrict__ plan, int nplan) {
+                                                          int m, int yshift, int nyb, int kstride,
+                                                          int4* __restrict__ rec, int* __restrict__ rank,
+                                                          int* __restrict__ counts, int* __restrict__ plan,
+                                                          int nplan) {
     const int64_t j = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
     const int s = blockIdx.y;
-    const int keys = m * nyb;
     if (blockIdx.x == 0 && s == 0 && (int)threadIdx.x < nplan) plan[threadIdx.x] = 0;
     if (j < nk) {
         const double* q = quats + 4 * s;
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restri
         rec[(int64_t)s * nk + j] = make_int4(c[0] | (c[1] << 10) | (c[2] << 20), __float_as_int(f3[0]),
                                              __float_as_int(f3[1]), __float_as_int(f3[2]));
         const int key = c[2] * nyb + (c[1] >> yshift);
-        rank[(int64_t)s * nk + j] = atomicAdd(&counts[(size_t)s * keys + key], 1);
+        rank[(int64_t)s * nk + j] = atomicAdd(&counts[(size_t)s * kstride + key], 1);
     }
 }
 
@@ -415,16 +415,19 @@ __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restri
 // keys / kBinBlock consecutive keys per thread); clears the counts.  Reading
 // the counts in a kernel of its own makes every workgroup's atomic increments
 // visible without device-wide fences.
-__global__ __launch_bounds__(kBinBlock) void k_bin_scan(int* __restrict__ counts, int keys, int64_t nk,
-                                                        int* __restrict__ bin_start) {
+__global__ __launch_bounds__(kBinBlock) void k_bin_scan(int* __restrict__ counts, int keys, int kstride,
+                                                        int64_t nk, int* __restrict__ bin_start) {
     __shared__ int wsum[kBinBlock / 64];
     const int s = blockIdx.x;
-    int* cs = counts + (size_t)s * keys;
-    int* bs = bin_start + (size_t)s * (keys + 1);
-    switch (keys / kBinBlock) {  // keys is 1024, 4096 or 16384
+    int* cs = counts + (size_t)s * kstride;
+    int* bs = bin_start + (size_t)s * (kstride + 1);
+    switch (keys / kBinBlock) {  // keys is a power of two, 1024 .. 32768
         case 4: scan_counts<4>(cs, bs, wsum); break;
+        case 8: scan_counts<8>(cs, bs, wsum); break;
         case 16: scan_counts<16>(cs, bs, wsum); break;
-        default: scan_counts<64>(cs, bs, wsum); break;
+        case 32: scan_counts<32>(cs, bs, wsum); break;
+        case 64: scan_counts<64>(cs, bs, wsum); break;
+        default: scan_counts<128>(cs, bs, wsum); break;
     }
     if (threadIdx.x == 0) bs[keys] = (int)nk;
 }
@@ -483,7 +486,8 @@ struct SpreadShape {
     // lines padded by 8 words so that consecutive lines of a window use the
     // two different halves of the LDS banks; the FFT input overlays them
     static constexpr int LS = M + 8;
-    static constexpr int G = bin_ygroup(M), NYB = M / G, KEYS = M * NYB;
+    // key starts of a rotation: KEYS + 1 ints, room for the finest y-groups
+    static constexpr int KEYS = bin_keys_max(M);
     // the sums (and FFT input) and the twiddle table; the staged knots follow
     static constexpr size_t FIXED = 16 * (size_t)TY * LS + 8 * (size_t)M;
     static_assert(8 * (size_t)TY * SC <= 16 * (size_t)TY * LS, "FFT input must fit over the sums");
@@ -500,11 +504,11 @@ __device__ __forceinline__ bool use_win(int w) {
 }
 
 // z row z0 is live iff some knot's z-cell lies in z0-w/2 .. z0+w/2-1 on the
-// periodic axis; bs are the rotation's key starts (z-cell c owns the keys
-// c*NYB .. c*NYB+NYB-1).
+// periodic axis; bs are the rotation's key starts (with y-groups of 2^ygs
+// cells, z-cell c owns the keys c*NYB .. c*NYB+NYB-1, NYB = M >> ygs).
 template <int M>
-__device__ __forceinline__ bool zrow_live(const int* __restrict__ bs, int64_t nk, int w, int z0) {
-    constexpr int NYB = SpreadShape<M>::NYB;
+__device__ __forceinline__ bool zrow_live(const int* __restrict__ bs, int64_t nk, int w, int z0, int ygs) {
+    const int NYB = M >> ygs;
     if (nk == 0) return false;
     const int zlo = z0 - w / 2, zhi = z0 + w / 2 - 1;
     if (zlo < 0) return bs[M * NYB] - bs[(zlo + M) * NYB] + bs[(zhi + 1) * NYB] - bs[0] > 0;
@@ -529,10 +533,11 @@ struct SpreadStage {
 // windows reach rows y0 .. y0+TY-1, the piece j%2 (the groups wrap around the
 // periodic axis at most once).
 template <int M>
-__device__ __forceinline__ void tile_range(const int* __restrict__ bs, int w, int y0, int z0, int j, int& start,
-                                           int& len) {
+__device__ __forceinline__ void tile_range(const int* __restrict__ bs, int w, int y0, int z0, int j, int ygs,
+                                           int& start, int& len) {
     using SS = SpreadShape<M>;
-    constexpr int TY = SS::TY, G = SS::G, NYB = SS::NYB;
+    constexpr int TY = SS::TY;
+    const int G = 1 << ygs, NYB = M >> ygs;
     const int zc = (z0 - w / 2 + (j >> 1) + M) & (M - 1);
     const int ylo = y0 - w / 2, yhi = y0 + TY + w / 2 - 2;
     int ga[2] = {0, 0}, gb[2] = {NYB - 1, -1};  // inclusive group ranges; gb < ga is empty
@@ -560,11 +565,11 @@ __device__ __forceinline__ void tile_range(const int* __restrict__ bs, int w, in
 // All key ranges of a tile, by wave 0: rstart[r], and the prefix sums
 // rpre[0..2w] of their lengths.
 template <int M>
-__device__ void tile_ranges(const int* __restrict__ bs, int w, int y0, int z0, int* rstart, int* rpre) {
+__device__ void tile_ranges(const int* __restrict__ bs, int w, int y0, int z0, int ygs, int* rstart, int* rpre) {
     const int lane = threadIdx.x & 63;
     if (threadIdx.x >= 64) return;
     int start = 0, len = 0;
-    if (lane < 2 * w) tile_range<M>(bs, w, y0, z0, lane, start, len);
+    if (lane < 2 * w) tile_range<M>(bs, w, y0, z0, lane, ygs, start, len);
     int incl = len;
 #pragma unroll
     for (int d = 1; d < 32; d <<= 1) {
@@ -591,7 +596,7 @@ __device__ void tile_ranges(const int* __restrict__ bs, int w, int y0, int z0, i
 constexpr int kPlanBuckets = plan_buckets();
 
 template <int M>
-__device__ __forceinline__ void tile_plan(int tile, int s, const int* __restrict__ bin_start, int w,
+__device__ __forceinline__ void tile_plan(int tile, int s, const int* __restrict__ bin_start, int w, int ygs,
                                           unsigned char* __restrict__ tile_live, int* __restrict__ plan,
                                           int* __restrict__ list, int list_cap) {
     using SS = SpreadShape<M>;
@@ -604,7 +609,7 @@ __device__ __forceinline__ void tile_plan(int tile, int s, const int* __restrict
         int ncand = 0;
         for (int j = 0; j < 2 * w; ++j) {
             int st0, len;
-            tile_range<M>(bs, w, y0, z0, j, st0, len);
+            tile_range<M>(bs, w, y0, z0, j, ygs, st0, len);
             ncand += len;
         }
         if (ncand == 0) tile_live[(size_t)s * TILES + tile] = 0;
@@ -643,7 +648,8 @@ __global__ __launch_bounds__(256) void k_scatter_plan(const int4* __restrict__ r
                         q, scell, skbw, swts);
         return;
     }
-    tile_plan<M>(((int)blockIdx.x - nscatter) * 256 + threadIdx.x, s, bin_start, w, tile_live, plan, list, list_cap);
+    tile_plan<M>(((int)blockIdx.x - nscatter) * 256 + threadIdx.x, s, bin_start, w, yshift, tile_live, plan, list,
+                 list_cap);
 }
 
 // Stage one block of a tile's candidates, [cbeg, cbeg + cnt) of the
@@ -886,7 +892,7 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
                             unsigned char* __restrict__ tile_live, const int* __restrict__ scell,
                             const float* __restrict__ skbw, const float* __restrict__ swts, int64_t nk, int q, int w,
                             int cap, float fix_scale, float fix_inv, float2* __restrict__ out, float2* lds,
-                            int* wave_tot, int* rstart, int* rpre) {
+                            int* wave_tot, int* rstart, int* rpre, int ygs) {
     constexpr int H = M / 4;  // half of the n = M/2 kept modes along x
     using SS = SpreadShape<M>;
     constexpr int TY = SS::TY, SC = SS::SC, NPTS = SS::NPTS, LS = SS::LS;
@@ -907,7 +913,7 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
     const float* kb_ = skbw + (int64_t)s * nk * 3 * w;
     const float* wq_ = swts + (int64_t)s * nk * q;
     if (c0 >= c1) return false;  // no component to spread (never staged: weights would be read past q)
-    tile_ranges<M>(bin_start + (size_t)s * (SS::KEYS + 1), w, y0, z0, rstart, rpre);
+    tile_ranges<M>(bin_start + (size_t)s * (SS::KEYS + 1), w, y0, z0, ygs, rstart, rpre);
     __syncthreads();
     const int ncand = rpre[nr];
     // candidates are spread in blocks of `cap` (one staging each): a tile of one
@@ -1032,7 +1038,7 @@ __global__ __launch_bounds__(kSpreadThreads, 4) void k_spread_fftx(const int* __
                                                                 float2* __restrict__ out,
                                                                 const float2* __restrict__ twm,
                                                                 unsigned long long* __restrict__ work,
-                                                                unsigned long long rec_bytes) {
+                                                                unsigned long long rec_bytes, int ygs) {
     using SS = SpreadShape<M>;
     constexpr int NTY = M / SS::TY, TILES = M * NTY;
     unsigned long long wrote = 0;  // bytes of kept x modes this workgroup wrote
@@ -1071,7 +1077,7 @@ __global__ __launch_bounds__(kSpreadThreads, 4) void k_spread_fftx(const int* __
         const int ppp = ((q + 1) / 2 + parts[b] - 1) / parts[b];  // component pairs per part
         const int c0 = 2 * part * ppp, c1 = min(c0 + 2 * ppp, q);  // c0 < q: no part is empty
         if (spread_tile<M>(s, tile / NTY, (tile % NTY) * SS::TY, tile % NTY, c0, c1, bin_start, tile_live, scell,
-                           skbw, swts, nk, q, w, cap, fix_scale, fix_inv, out, lds, wave_tot, rstart, rpre))
+                           skbw, swts, nk, q, w, cap, fix_scale, fix_inv, out, lds, wave_tot, rstart, rpre, ygs))
             wrote += (unsigned long long)SS::TY * (M / 4) * sizeof(float2) * (c1 - c0);
     }
     // work record, summed over launches until the host reads it: bytes of kept
@@ -1166,7 +1172,8 @@ template <int M, int COLS>
 __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ in, float2* __restrict__ out,
                                                     const float2* __restrict__ twm, int q, int cg,
                                                     const int* __restrict__ bin_start,
-                                                    const unsigned char* __restrict__ tile_live, int64_t nk, int w) {
+                                                    const unsigned char* __restrict__ tile_live, int64_t nk, int w,
+                                                    int ygs) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, YZB = ColShape<M>::YZB;
     constexpr int TY = SpreadShape<M>::TY, NT = M / TY;
     using P = RegPass<M, COLS>;
@@ -1184,7 +1191,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ i
     const int c0 = blockIdx.x * COLS;
     load_table<M>(twl, twm);
     for (int z = blockIdx.y * YZB; z < blockIdx.y * YZB + YZB; ++z) {
-        if (!zrow_live<M>(bs, nk, w, z)) continue;
+        if (!zrow_live<M>(bs, nk, w, z, ygs)) continue;
         __syncthreads();  // the previous row's output has been read out of `a`
         for (int t = threadIdx.x; t < NT; t += kThreads) live[t] = tile_live[((size_t)s * M + z) * NT + t];
         __syncthreads();
@@ -1312,7 +1319,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __res
                                                              const float* __restrict__ vtab, int m2n,
                                                              const double* __restrict__ deconv,
                                                              float2* __restrict__ spec, const float2* __restrict__ twm,
-                                                             const int* __restrict__ bin_start, int64_t nk, int w) {
+                                                             const int* __restrict__ bin_start, int64_t nk, int w, int ygs) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, PER = ZAcc<M, COLS>::PER;
     extern __shared__ float2 lds[];
     __shared__ unsigned char zlive[M];
@@ -1327,7 +1334,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_spectrum(const float2* __res
         return;
     }
     load_table<M>(twl, twm);
-    for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, t);
+    for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, t, ygs);
     __syncthreads();
     float2 acc[PER];
     z_accumulate<M, COLS>(in, s, q, iy, c0, vtab, m2n, a, twl, zlive, acc);
@@ -1365,7 +1372,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
                                                             const float2* __restrict__ fa, float2* __restrict__ out,
                                                             const float2* __restrict__ twm,
                                                             const float2* __restrict__ twn,
-                                                            const int* __restrict__ bin_start, int64_t nk, int w) {
+                                                            const int* __restrict__ bin_start, int64_t nk, int w, int ygs) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, PER = ZAcc<M, COLS>::PER;
     extern __shared__ float2 lds[];
     __shared__ unsigned char zlive[M];
@@ -1382,7 +1389,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_product(const float2* __rest
     }
     load_table<M>(twl, twm);
     load_table<N>(twnl, twn);
-    for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, t);
+    for (int t = threadIdx.x; t < M; t += kThreads) zlive[t] = zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, t, ygs);
     __syncthreads();
     float2 acc[PER];
     z_accumulate<M, COLS>(in, s, q, iy, c0, vtab, m2n, a, twl, zlive, acc);
@@ -1452,7 +1459,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_components(const float2* __r
                                                                const double* __restrict__ deconv,
                                                                float2* __restrict__ out,
                                                                const float2* __restrict__ twm,
-                                                               const int* __restrict__ bin_start, int64_t nk, int w) {
+                                                               const int* __restrict__ bin_start, int64_t nk, int w, int ygs) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H;
     using P = RegPass<M, COLS>;
     extern __shared__ float2 lds[];
@@ -1470,7 +1477,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_components(const float2* __r
     }
     load_table<M>(twl, twm);
     for (int t = threadIdx.x; t < M; t += kThreads)
-        zlive[t] = zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, t);
+        zlive[t] = zrow_live<M>(bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1), nk, w, t, ygs);
     __syncthreads();
     for (int c = 0; c < q; ++c) {
         const float2* src = in + (((size_t)s * q + c) * M) * N * H + (size_t)iy * H + c0;
@@ -2005,12 +2012,13 @@ int bin_blocks(int64_t nk) { return (int)((nk + kBinBlock - 1) / kBinBlock); }
 hipError_t launch_rotate_bin(const Geom& g, const double* d_quats, int S, const double* d_pos, int64_t nk,
                              int4* d_rec, int* d_rank, int* d_counts, int* d_bin_start, int* d_plan, hipStream_t st) {
     if (nk == 0 || S == 0) return hipSuccess;
-    const int G = bin_ygroup(g.m);
+    const int G = bin_group(g);
     hipLaunchKernelGGL(k_rotate_bin, dim3(bin_blocks(nk), S), dim3(kBinBlock), 0, st, d_quats, d_pos, nk, g.inv_hf,
-                       g.m, log2i(G), g.m / G, d_rec, d_rank, d_counts, d_plan, plan_words());
+                       g.m, log2i(G), g.m / G, bin_keys_max(g.m), d_rec, d_rank, d_counts, d_plan, plan_words());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_scan, dim3(S), dim3(kBinBlock), 0, st, d_counts, bin_keys(g.m), nk, d_bin_start);
+    hipLaunchKernelGGL(k_bin_scan, dim3(S), dim3(kBinBlock), 0, st, d_counts, g.m * (g.m / G), bin_keys_max(g.m), nk,
+                       d_bin_start);
     return hipGetLastError();
 }
 
@@ -2023,7 +2031,7 @@ hipError_t launch_scatter_plan(const Geom& g, int S, int q, const Occupancy& occ
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         constexpr int tiles = M * (M / SpreadShape<M>::TY);
-        const int G = bin_ygroup(M);
+        const int G = bin_group(g);
         const int nscatter = bin_blocks(occ.nk);
         hipLaunchKernelGGL(k_scatter_plan<M>, dim3(nscatter + (tiles + 255) / 256, S), dim3(256), 0, st, d_rec,
                            d_wts, d_rank, occ.bin_start, occ.nk, log2i(G), M / G, g.w, g.beta, g.inv_i0beta, q,
@@ -2066,7 +2074,8 @@ hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, int* d
                            spread_lds_t<M>(g.w), st, occ.bin_start, occ.tile_live, d_plan, d_list, S * tiles, d_scell,
                            d_skbw, d_swts, occ.nk, q, g.w, spread_cap_t<M>(g.w), fix_scale, 1.0f / fix_scale, d_out,
                            d_twm, d_work,
-                           (unsigned long long)occ.nk * S * (sizeof(int) + 3 * sizeof(float) * g.w + sizeof(float) * q));
+                           (unsigned long long)occ.nk * S * (sizeof(int) + 3 * sizeof(float) * g.w + sizeof(float) * q),
+                           log2i(bin_group(g)));
     });
 }
 
@@ -2089,7 +2098,7 @@ hipError_t launch_fft_y(const Geom& g, int S, int q, const Occupancy& occ, const
             while (cg > 1 && rows * ((q + cg - 1) / cg) < kYMinBlocks) cg = (cg + 1) / 2;
             hipLaunchKernelGGL((k_fft_y<M, COLS>), dim3(C::H / COLS, M / C::YZB, S * ((q + cg - 1) / cg)),
                                dim3(kThreads), sizeof(float2) * ((size_t)M * COLS + M), st, d_in, d_out, d_twm, q,
-                               cg, occ.bin_start, occ.tile_live, occ.nk, g.w);
+                               cg, occ.bin_start, occ.tile_live, occ.nk, g.w, log2i(bin_group(g)));
         });
     });
 }
@@ -2104,7 +2113,7 @@ hipError_t launch_fft_z_spectrum(const Geom& g, const float2* d_in, int S, int q
             constexpr int COLS = decltype(cc)::value;
             hipLaunchKernelGGL((k_fft_z_spectrum<M, COLS>), dim3(C::H / COLS, C::N, S), dim3(kThreads),
                                sizeof(float2) * ((size_t)M * COLS + M), st, d_in, q, d_vtab, g.m2n, d_deconv,
-                               d_spec, d_twm, occ.bin_start, occ.nk, g.w);
+                               d_spec, d_twm, occ.bin_start, occ.nk, g.w, log2i(bin_group(g)));
         });
     });
 }
@@ -2119,7 +2128,8 @@ hipError_t launch_fft_z_product(const Geom& g, const float2* d_in, int S, int q,
             constexpr int COLS = decltype(cc)::value;
             hipLaunchKernelGGL((k_fft_z_product<M, COLS>), dim3(C::H / COLS, C::N, S), dim3(kThreads),
                                sizeof(float2) * ((size_t)M * COLS + M + C::N), st, d_in, q, d_vtab, g.m2n,
-                               d_phase, d_fa, d_out, d_twm, d_twn, occ.bin_start, occ.nk, g.w);
+                               d_phase, d_fa, d_out, d_twm, d_twn, occ.bin_start, occ.nk, g.w,
+                               log2i(bin_group(g)));
         });
     });
 }
@@ -2154,7 +2164,7 @@ hipError_t launch_fft_z_components(const Geom& g, const float2* d_in, int S, int
             constexpr int COLS = decltype(cc)::value;
             hipLaunchKernelGGL((k_fft_z_components<M, COLS>), dim3(C::H / COLS, C::N, S), dim3(kThreads),
                                sizeof(float2) * ((size_t)M * COLS + M), st, d_in, q, d_deconv, d_out, d_twm,
-                               occ.bin_start, occ.nk, g.w);
+                               occ.bin_start, occ.nk, g.w, log2i(bin_group(g)));
         });
     });
 }
@@ -2213,6 +2223,15 @@ int ifft_x_blocks_max(const Geom& g) {
         nb = C::N * C::N / (2 * C::IX::DN);
     });
     return nb;
+}
+
+int bin_choices(int m, int out[3]) {
+    const int g0 = bin_ygroup(m);
+    int k = 0;
+    out[k++] = g0;
+    if (g0 > 1 && m * m / (g0 / 2) <= 32768) out[k++] = g0 / 2;
+    if (2 * g0 <= m && m * m / (2 * g0) >= 1024) out[k++] = 2 * g0;
+    return k;
 }
 
 int col_choices(int m, int pass, int out[3]) {

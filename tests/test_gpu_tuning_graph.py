@@ -90,6 +90,14 @@ def test_every_launch_shape_gives_the_same_bits(n):
             _same(_eval(c, q, out), ref, "%s = %d" % (f, w))
             _say("  %s = %d: bitwise equal" % (f, w))
         c.set_tuning(**{f: base[f]})
+    # the spreading pass's bins: y-groups of the sort keys
+    bins = pkg.corr_tuning_choices(c.ctx, 4)
+    assert bins[0] == base["bin_group"] and len(bins) >= 2
+    for gsz in bins[1:]:
+        c.set_tuning(bin_group=gsz)
+        _same(_eval(c, q, out), ref, "bin_group = %d" % gsz)
+        _say("  bin_group = %d: bitwise equal" % gsz)
+    c.set_tuning(bin_group=base["bin_group"])
     cus = base["spread_wgs"] // 2
     for v in (1, cus):
         c.set_tuning(spread_wgs=v)
@@ -106,6 +114,8 @@ def test_every_launch_shape_gives_the_same_bits(n):
         c.set_tuning(spread_wgs=0)
     with pytest.raises(pkg.CorrError):
         c.set_tuning(slots=257)
+    with pytest.raises(pkg.CorrError):
+        c.set_tuning(bin_group=3)
     c.close()
 
 
@@ -121,7 +131,7 @@ def test_autotune_keeps_a_valid_tuning_and_the_results():
     t = c.autotune(q, reps=1)
     _say("  kept:", t)
     assert t == c.tuning()
-    for p, f in enumerate(("cols_y", "cols_z", "cols_iy", "pairs_ix")):
+    for p, f in enumerate(("cols_y", "cols_z", "cols_iy", "pairs_ix", "bin_group")):
         assert t[f] in pkg.corr_tuning_choices(c.ctx, p)
     assert 1 <= t["slots"] <= 256 and t["graph"] == 0
     _same(_eval(c, q, out), ref, "after autotune")
@@ -248,8 +258,9 @@ def test_batch_graph_replays_match_the_eager_batch():
 
 
 def test_batch_autotune_keeps_every_bit():
-    # the batch autotuner tries every spreading workgroup count and every width
-    # rank of every column pass on all pairs; whatever it keeps, and every
+    # the batch autotuner tries every spreading workgroup count, every width
+    # rank of every column pass and every bin-group rank on all pairs; whatever
+    # it keeps, and every
     # candidate it ran (the outputs hold the last), the results stay bitwise
     from paper_1711_05075_amd import Batch
     pairs, quats = [], []
@@ -273,6 +284,7 @@ def test_batch_autotune_keeps_every_bit():
     kept = b.autotune(quats, (s, pv, pi), reps=1)
     torch.cuda.synchronize()
     _say("  kept %s" % kept)
+    assert 0 <= kept["rank_bin_group"] <= 2
     off = 0
     for x, q, n in zip(ref_s, quats, b.ns):
         assert torch.equal(s[off:off + len(q) * n ** 3].view(len(q), n, n, n), x)
