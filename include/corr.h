@@ -362,6 +362,9 @@ typedef struct {
     int32_t bin_group;   /* y cells per sort key of the spreading pass's binning (keys
                             are z-cell x y-group): the grid's default, half or twice
                             it, as corr_tuning_choices(pass 4) lists                 */
+    int32_t tile_rows;   /* y rows of a spreading tile (one z row each): the grid's
+                            default or half of it, as corr_tuning_choices(pass 5)
+                            lists                                                    */
 } corr_tuning;
 
 /* The context's current tuning. */
@@ -377,7 +380,8 @@ int corr_set_tuning(corr_ctx* ctx, const corr_tuning* tuning);
  * 3 pairs_ix) on this context's grid: the default first, then half and twice
  * it where the pass's shape allows; pass 4: the bin_group values (the default
  * first, then half and twice it where the grid's key count stays within
- * 1024 .. 32768).  out3 receives *count (1..3) values. */
+ * 1024 .. 32768); pass 5: the tile_rows values (the default, then half of it).
+ * out3 receives *count (1..3) values. */
 int corr_tuning_choices(const corr_ctx* ctx, int32_t pass, int32_t* out3, int32_t* count);
 
 /* flags of corr_autotune */
@@ -389,7 +393,8 @@ int corr_tuning_choices(const corr_ctx* ctx, int32_t pass, int32_t* out3, int32_
  * Autotuner.  Evaluates these rotations (arguments as for corr_eval) under
  * candidate tunings and keeps the fastest: coordinate descent over slots
  * (powers of two up to n_rot, workspace <= 8 GiB), spread_wgs (one, one and a
- * half or two per CU), the four column widths and the bin group, each candidate timed by HIP
+ * half or two per CU), the four column widths, the bin group and the tile
+ * height, each candidate timed by HIP
  * events as the least of `reps` (1..100) runs after an untimed one.  A run is
  * corr_eval, or with CORR_TUNE_WITH_A corr_prepare_a + corr_eval.  The graph
  * setting is kept as it is.  Synchronous; the outputs hold the last
@@ -450,18 +455,19 @@ int corr_batch_info(const corr_batch* b, int32_t pair, corr_info_t* out);
  * Autotuner of a batch: runs corr_batch_eval (these arguments) under candidate
  * launch shapes applied to every pair and keeps the fastest, by coordinate
  * descent: spread_wgs (one, one and a half or two per CU), then each column
- * pass's width and then the bin group, each by rank among each pair's own
- * choices (0 the pair's default, 1 and 2 the others of corr_tuning_choices
- * where its grid has them).  Rotations per pass stay as planned at create.
- * Each candidate is timed by HIP events as the least of `reps` (1..100) runs
- * after an untimed one.  No tuning changes a bit of the outputs, which hold
- * the last evaluation.  Synchronous.  out6 (host int32 [6], or NULL):
- * spread_wgs, the four column ranks and the bin-group rank kept.  After an
- * error the pairs' previous tunings are restored.
+ * pass's width, the bin group and the tile height, each by rank among each
+ * pair's own choices (0 the pair's default, 1 and 2 the others of
+ * corr_tuning_choices where its grid has them).  Rotations per pass stay as
+ * planned at create.  Each candidate is timed by HIP events as the least of
+ * `reps` (1..100) runs after an untimed one.  No tuning changes a bit of the
+ * outputs, which hold the last evaluation.  Synchronous.  out7 (host int32
+ * [7], or NULL): spread_wgs, the four column ranks, the bin-group rank and
+ * the tile-height rank kept.  After an error the pairs' previous tunings are
+ * restored.
  */
 int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* rot_offsets, float* scores_dev,
                         const int64_t* score_offsets, float* peak_val_dev, int64_t* peak_idx_dev, int32_t reps,
-                        int32_t* out6);
+                        int32_t* out7);
 
 /* corr_profile / corr_profile_read over every pair of the batch (the read
  * sums the pairs' stage times and launch counts), and corr_spread_work of the

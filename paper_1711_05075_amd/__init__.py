@@ -73,7 +73,7 @@ class corr_slices_out(ctypes.Structure):
 class corr_tuning(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("spread_wgs", ctypes.c_int32), ("cols_y", ctypes.c_int32),
                 ("cols_z", ctypes.c_int32), ("cols_iy", ctypes.c_int32), ("pairs_ix", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("bin_group", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("bin_group", ctypes.c_int32), ("tile_rows", ctypes.c_int32)]
 
 
 TUNING_FIELDS = tuple(k for k, _ in corr_tuning._fields_)
@@ -729,19 +729,20 @@ class Batch:
         """Run corr_batch_autotune on these rotations with the caller's output
         tensors out = (packed scores or None, peak_val, peak_idx); returns the
         kept choice {spread_wgs, rank of each column pass's width, rank of the
-        bin group}."""
+        bin group, rank of the tile height}."""
         counts = [len(q) for q in quats_per_pair]
         offs = np.ascontiguousarray(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64))
         q = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64).reshape(-1, 4)
                                                  for x in quats_per_pair]))
         s, pv, pi = out
-        res = np.zeros(6, dtype=np.int32)
+        res = np.zeros(7, dtype=np.int32)
         with self.torch.cuda.device(self.device):
             _bcheck(_batch_lib().corr_batch_autotune(self.b, q.ctypes.data, offs.ctypes.data,
                                                      s.data_ptr() if s is not None else None, None, pv.data_ptr(),
                                                      pi.data_ptr(), int(reps), res.ctypes.data), self.b)
         return {"spread_wgs": int(res[0]), "rank_cols_y": int(res[1]), "rank_cols_z": int(res[2]),
-                "rank_cols_iy": int(res[3]), "rank_pairs_ix": int(res[4]), "rank_bin_group": int(res[5])}
+                "rank_cols_iy": int(res[3]), "rank_pairs_ix": int(res[4]), "rank_bin_group": int(res[5]),
+                "rank_tile_rows": int(res[6])}
 
     def info(self, pair):
         return corr_batch_info(self.b, pair)

@@ -1029,7 +1029,7 @@ corr::WsReq ws_req(const corr_ctx* c) {
     r.counts = (size_t)corr::bin_keys_max(g.m);
     r.bins = (size_t)corr::bin_keys_max(g.m) + 1;
     r.blocks = (size_t)corr::ifft_x_blocks_max(g);  // any inverse-x width
-    r.tiles = (size_t)g.m * corr::spread_tiles(g);
+    r.tiles = (size_t)g.m * corr::spread_tiles_max(g);
     r.list = (size_t)corr::plan_buckets() * r.tiles;
     return r;
 }
@@ -1408,6 +1408,11 @@ corr_tuning get_tuning(const corr_ctx* c) {
     t.pairs_ix = c->g.pairs_ix ? c->g.pairs_ix : (corr::col_choices(c->g.m, 3, def), def[0]);
     t.graph = c->graph ? 1 : 0;
     t.bin_group = corr::bin_group(c->g);
+    {
+        int tr[2];
+        corr::tile_choices(c->g.m, tr);
+        t.tile_rows = c->g.tile_rows ? c->g.tile_rows : tr[0];
+    }
     return t;
 }
 
@@ -1435,6 +1440,12 @@ void set_tuning(corr_ctx* c, const corr_tuning& t) {
         bool ok = false;
         for (int i = 0; i < k; ++i) ok = ok || bg[i] == t.bin_group;
         if (!ok) fail(CORR_EINVAL, "bin_group = %d is not one of this grid's groups (corr_tuning_choices)", t.bin_group);
+        int tr[2];
+        const int kt = corr::tile_choices(c->g.m, tr);
+        ok = false;
+        for (int i = 0; i < kt; ++i) ok = ok || tr[i] == t.tile_rows;
+        if (!ok) fail(CORR_EINVAL, "tile_rows = %d is not one of this grid's tile heights (corr_tuning_choices)",
+                      t.tile_rows);
     }
     if (t.slots != c->ws->slots) {
         if (!c->own_ws) fail(CORR_EUNSUPPORTED, "the pairs of a batch share their workspace: slots are fixed");
@@ -1442,9 +1453,10 @@ void set_tuning(corr_ctx* c, const corr_tuning& t) {
     }
     Geom& g = c->g;
     if (g.cols_y != t.cols_y || g.cols_z != t.cols_z || g.cols_iy != t.cols_iy || g.pairs_ix != t.pairs_ix ||
-        g.spread_wgs != t.spread_wgs || corr::bin_group(g) != t.bin_group)
+        g.spread_wgs != t.spread_wgs || corr::bin_group(g) != t.bin_group || get_tuning(c).tile_rows != t.tile_rows)
         c->shape_gen++;
     g.bin_group = t.bin_group;
+    g.tile_rows = t.tile_rows;
     g.cols_y = t.cols_y;
     g.cols_z = t.cols_z;
     g.cols_iy = t.cols_iy;
@@ -1528,6 +1540,9 @@ corr_tuning autotune(corr_ctx* c, const double* q, int64_t n_rot, float* scores,
         int bg[3];
         const int kb = corr::bin_choices(c->g.m, bg);
         try_field(&corr_tuning::bin_group, std::vector<int>(bg, bg + kb));
+        int tr[2];
+        const int kt = corr::tile_choices(c->g.m, tr);
+        try_field(&corr_tuning::tile_rows, std::vector<int>(tr, tr + kt));
         set_tuning(c, cur);
     } catch (...) {
         (void)hipStreamSynchronize(c->stream);
@@ -1577,9 +1592,10 @@ int corr_tuning_choices(const corr_ctx* c, int32_t pass, int32_t* out3, int32_t*
     int ch[3];
     const int k = (pass >= 0 && pass < 4) ? corr::col_choices(c->g.m, pass, ch)
                   : pass == 4             ? corr::bin_choices(c->g.m, ch)
+                  : pass == 5             ? corr::tile_choices(c->g.m, ch)
                                           : 0;
     if (k == 0) {
-        g_thread_error = "corr_tuning_choices: pass must be 0..4";
+        g_thread_error = "corr_tuning_choices: pass must be 0..5";
         return CORR_EINVAL;
     }
     for (int i = 0; i < k; ++i) out3[i] = ch[i];
@@ -2256,7 +2272,7 @@ int corr_batch_profile_read(corr_batch* b, double* ms, int64_t* launches, int32_
 
 int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* rot_offsets, float* scores_dev,
                         const int64_t* score_offsets, float* peak_val_dev, int64_t* peak_idx_dev, int32_t reps,
-                        int32_t* out6) {
+                        int32_t* out7) {
     if (!b) {
         g_thread_error = "corr_batch_autotune: NULL batch";
         return CORR_EINVAL;
@@ -2265,12 +2281,12 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
         b->err = "corr_batch_autotune: reps must be in 1..100";
         return CORR_EINVAL;
     }
-    // a candidate: spread_wgs and, per column pass and for the bin group, the
-    // rank of the value among each pair's choices (0 its default, 1 and 2 the
-    // others where they exist)
+    // a candidate: spread_wgs and, per column pass, for the bin group and for
+    // the tile height, the rank of the value among each pair's choices (0 its
+    // default, 1 and 2 the others where they exist)
     struct Cand {
         int wgs;
-        int rank[5];
+        int rank[6];
     };
     std::vector<corr_tuning> start;
     for (corr_ctx* c : b->pairs) start.push_back(get_tuning(c));
@@ -2298,11 +2314,14 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
             int bg[3];
             const int nb = corr::bin_choices(c->g.m, bg);
             t.bin_group = bg[k.rank[4] < nb ? k.rank[4] : 0];
+            int tr[2];
+            const int nt = corr::tile_choices(c->g.m, tr);
+            t.tile_rows = tr[k.rank[5] < nt ? k.rank[5] : 0];
             set_tuning(c, t);
         }
     };
     float best_ms = INFINITY;
-    Cand cur{start.empty() ? 1 : start[0].spread_wgs, {0, 0, 0, 0, 0}};
+    Cand cur{start.empty() ? 1 : start[0].spread_wgs, {0, 0, 0, 0, 0, 0}};
     auto timed = [&](const Cand& k) -> float {
         apply(k);
         auto unit = [&] {
@@ -2336,8 +2355,8 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
                 cur = k;
             }
         }
-        for (int p = 0; p < 5; ++p)
-            for (int r = 1; r < 3; ++r) {
+        for (int p = 0; p < 6; ++p)
+            for (int r = 1; r < (p == 5 ? 2 : 3); ++r) {
                 Cand k = cur;
                 k.rank[p] = r;
                 const float ms = timed(k);
@@ -2365,9 +2384,9 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
         b->err = g_thread_error;
         return rc;
     }
-    if (out6) {
-        out6[0] = cur.wgs;
-        for (int p = 0; p < 5; ++p) out6[1 + p] = cur.rank[p];
+    if (out7) {
+        out7[0] = cur.wgs;
+        for (int p = 0; p < 6; ++p) out7[1 + p] = cur.rank[p];
     }
     return CORR_OK;
 }

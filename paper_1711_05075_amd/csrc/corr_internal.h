@@ -27,6 +27,9 @@ struct Geom {
     // y-group of the sort keys (the bins of spreading), in cells: 0 for
     // bin_ygroup(m), else one of bin_choices(m)
     int bin_group = 0;
+    // rows of a spreading tile: 0 for the default at m, else one of
+    // tile_choices(m)
+    int tile_rows = 0;
 };
 
 // Widths a column pass may take at spreading-grid size m: out[0] is the
@@ -45,8 +48,13 @@ struct Occupancy {
     unsigned char* tile_live = nullptr;     // [S][m][spread_tiles(g)]
     int64_t nk = 0;                         // knots per rotation
 };
-// y tiles per z row of the spreading pass.
+// y tiles per z row of the spreading pass, and the most any tile height of
+// tile_choices gives (the size the tile arrays are allocated for).
 int spread_tiles(const Geom& g);
+int spread_tiles_max(const Geom& g);
+// Rows a spreading tile may take at m: out[0] the default, out[1] half of it.
+// Returns the count.
+int tile_choices(int m, int out[2]);
 // ints of a spreading pass's plan counters; its live-tile list holds
 // plan_buckets() * S * m * spread_tiles(g) ints.
 int plan_words();

@@ -477,9 +477,10 @@ __device__ __forceinline__ void bin_scatter(int64_t j, int s, const int4* __rest
 // sum can overflow.  A tile that no knot reaches only records that in
 // tile_live.
 // ---------------------------------------------------------------------------
-template <int M>
+// TY_ = 0: the default tile height of the spreading pass at this M
+template <int M, int TY_ = 0>
 struct SpreadShape {
-    static constexpr int TY = cmin<2048 / M, M>();
+    static constexpr int TY = TY_ ? TY_ : cmin<2048 / M, M>();
     static constexpr int SC = M + 1;  // padded FFT line (float2)
     static constexpr int NPTS = TY * M;
     // fixed-point sums: a plane of int64 real parts and one of imaginary parts,
@@ -498,9 +499,9 @@ constexpr int kSpreadThreads = 512;
 // tiles that span every row of the plane (TY = M) keep the knot's cell, since
 // their rows wrap inside the tile.
 constexpr int kWinMax = 8;
-template <int M>
+template <int M, int TYP>
 __device__ __forceinline__ bool use_win(int w) {
-    return SpreadShape<M>::TY < M && w <= kWinMax;
+    return SpreadShape<M, TYP>::TY < M && w <= kWinMax;
 }
 
 // z row z0 is live iff some knot's z-cell lies in z0-w/2 .. z0+w/2-1 on the
@@ -532,22 +533,22 @@ struct SpreadStage {
 // z-cell j/2 of the z row's window and, of the y-groups that hold y-cells whose
 // windows reach rows y0 .. y0+TY-1, the piece j%2 (the groups wrap around the
 // periodic axis at most once).
-template <int M>
+template <int M, int TYP>
 __device__ __forceinline__ void tile_range(const int* __restrict__ bs, int w, int y0, int z0, int j, int ygs,
                                            int& start, int& len) {
-    using SS = SpreadShape<M>;
+    using SS = SpreadShape<M, TYP>;
     constexpr int TY = SS::TY;
-    const int G = 1 << ygs, NYB = M >> ygs;
+    const int NYB = M >> ygs;  // groups of 2^ygs y-cells; every numerator below is >= 0
     const int zc = (z0 - w / 2 + (j >> 1) + M) & (M - 1);
     const int ylo = y0 - w / 2, yhi = y0 + TY + w / 2 - 2;
     int ga[2] = {0, 0}, gb[2] = {NYB - 1, -1};  // inclusive group ranges; gb < ga is empty
     if (TY + w - 1 < M) {
         if (ylo < 0) {
-            ga[0] = (ylo + M) / G; gb[1] = yhi / G;
+            ga[0] = (ylo + M) >> ygs; gb[1] = yhi >> ygs;
         } else if (yhi >= M) {
-            ga[0] = ylo / G; gb[1] = (yhi - M) / G;
+            ga[0] = ylo >> ygs; gb[1] = (yhi - M) >> ygs;
         } else {
-            ga[0] = ylo / G; gb[0] = yhi / G;
+            ga[0] = ylo >> ygs; gb[0] = yhi >> ygs;
         }
         if (gb[1] >= ga[0]) {  // the two pieces meet: every group
             ga[0] = 0; gb[0] = NYB - 1; gb[1] = -1;
@@ -564,12 +565,12 @@ __device__ __forceinline__ void tile_range(const int* __restrict__ bs, int w, in
 
 // All key ranges of a tile, by wave 0: rstart[r], and the prefix sums
 // rpre[0..2w] of their lengths.
-template <int M>
+template <int M, int TYP>
 __device__ void tile_ranges(const int* __restrict__ bs, int w, int y0, int z0, int ygs, int* rstart, int* rpre) {
     const int lane = threadIdx.x & 63;
     if (threadIdx.x >= 64) return;
     int start = 0, len = 0;
-    if (lane < 2 * w) tile_range<M>(bs, w, y0, z0, lane, ygs, start, len);
+    if (lane < 2 * w) tile_range<M, TYP>(bs, w, y0, z0, lane, ygs, start, len);
     int incl = len;
 #pragma unroll
     for (int d = 1; d < 32; d <<= 1) {
@@ -595,11 +596,11 @@ __device__ void tile_ranges(const int* __restrict__ bs, int w, int y0, int z0, i
 // ---------------------------------------------------------------------------
 constexpr int kPlanBuckets = plan_buckets();
 
-template <int M>
+template <int M, int TYP>
 __device__ __forceinline__ void tile_plan(int tile, int s, const int* __restrict__ bin_start, int w, int ygs,
                                           unsigned char* __restrict__ tile_live, int* __restrict__ plan,
                                           int* __restrict__ list, int list_cap) {
-    using SS = SpreadShape<M>;
+    using SS = SpreadShape<M, TYP>;
     constexpr int TY = SS::TY, NTY = M / TY, TILES = M * NTY;
     const int lane = threadIdx.x & 63;
     int bucket = -1;
@@ -609,7 +610,7 @@ __device__ __forceinline__ void tile_plan(int tile, int s, const int* __restrict
         int ncand = 0;
         for (int j = 0; j < 2 * w; ++j) {
             int st0, len;
-            tile_range<M>(bs, w, y0, z0, j, ygs, st0, len);
+            tile_range<M, TYP>(bs, w, y0, z0, j, ygs, st0, len);
             ncand += len;
         }
         if (ncand == 0) tile_live[(size_t)s * TILES + tile] = 0;
@@ -631,7 +632,7 @@ __device__ __forceinline__ void tile_plan(int tile, int s, const int* __restrict
 
 // The scatter of the sorted records (workgroups x < nscatter) and the live-tile
 // plan (the others) of one spreading pass, both reading the key starts.
-template <int M>
+template <int M, int TYP>
 __global__ __launch_bounds__(256) void k_scatter_plan(const int4* __restrict__ rec,
                                                       const float* __restrict__ wts, const int* __restrict__ rank,
                                                       const int* __restrict__ bin_start, int64_t nk, int yshift,
@@ -644,11 +645,11 @@ __global__ __launch_bounds__(256) void k_scatter_plan(const int4* __restrict__ r
     if ((int)blockIdx.x < nscatter) {
         const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
         if (j < nk)
-            bin_scatter(j, s, rec, wts, rank, bin_start, nk, SpreadShape<M>::KEYS, yshift, nyb, w, beta, inv_i0beta,
+            bin_scatter(j, s, rec, wts, rank, bin_start, nk, SpreadShape<M, TYP>::KEYS, yshift, nyb, w, beta, inv_i0beta,
                         q, scell, skbw, swts);
         return;
     }
-    tile_plan<M>(((int)blockIdx.x - nscatter) * 256 + threadIdx.x, s, bin_start, w, yshift, tile_live, plan, list,
+    tile_plan<M, TYP>(((int)blockIdx.x - nscatter) * 256 + threadIdx.x, s, bin_start, w, yshift, tile_live, plan, list,
                  list_cap);
 }
 
@@ -666,12 +667,12 @@ __global__ __launch_bounds__(256) void k_scatter_plan(const int4* __restrict__ r
 // holds more than the staging area, so a tile of many candidates is spread
 // block by block and no candidate is ever scanned twice for one component
 // pair.  Entered and left by the whole workgroup.
-template <int M, int W>
+template <int M, int TYP, int W>
 __device__ int stage_block(const int* __restrict__ sc_, const float* __restrict__ kb_,
                            const float* __restrict__ wq_, int q, int cp, float fix_scale, int y0,
                            const int* rstart, const int* rpre, int nr, int cbeg, int cnt, SpreadStage st,
                            int* wave_tot) {
-    constexpr int TY = SpreadShape<M>::TY, LO = W / 2 - 1;
+    constexpr int TY = SpreadShape<M, TYP>::TY, LO = W / 2 - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int p = 0, packed = 0;
     bool keep = false;
@@ -712,14 +713,14 @@ __device__ int stage_block(const int* __restrict__ sc_, const float* __restrict_
     }
     if (keep) {
         const int rk = off + before;
-        if (use_win<M>(W)) {
+        if (use_win<M, TYP>(W)) {
             // window origin relative to the tile: first row by (signed), first
             // column bx; point (dy, dx) adds at row by + dy, column bx + dx
             const int cy = (packed >> 10) & 1023, cx = packed & 1023;
             const int ry = (cy - LO - y0 + 2 * M) & (M - 1);
             const int by = ry < TY ? ry : ry - M;
             const int bx = (cx - LO + M) & (M - 1);
-            st.cell[rk] = ((by * SpreadShape<M>::LS + bx) & 0xffff) | (by << 16);
+            st.cell[rk] = ((by * SpreadShape<M, TYP>::LS + bx) & 0xffff) | (by << 16);
         } else {
             st.cell[rk] = packed;
         }
@@ -752,10 +753,10 @@ __device__ __forceinline__ float fixed_to_float(unsigned long long u, float inv)
 // are issued together, then the atomic adds of the lanes that land in the
 // tile.  Used where w^2 fills whole waves (w = 8) or nearly (w = 10).  The sums
 // are exact integers, so the order of the adds does not matter.
-template <int M>
+template <int M, int TYP>
 __device__ __forceinline__ void spread_staged_rows(const SpreadStage& st, int nst, int w, int y0,
                                                    unsigned long long* __restrict__ acc) {
-    using SS = SpreadShape<M>;
+    using SS = SpreadShape<M, TYP>;
     constexpr int TY = SS::TY, LS = SS::LS, NW = kSpreadThreads / 64, U = 4;
     const int lo = w / 2 - 1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -805,10 +806,10 @@ __device__ __forceinline__ int win_off(int word) { return (int)(short)(word & 0x
 // (row lane / 8, column lane % 8).  Each wave takes U staged knots at a time
 // (every NW-th); their LDS reads are issued together, then the atomic adds of
 // the lanes whose row lies in the tile.
-template <int M>
+template <int M, int TYP>
 __device__ __forceinline__ void spread_staged_w8(const SpreadStage& st, int nst,
                                                  unsigned long long* __restrict__ acc) {
-    using SS = SpreadShape<M>;
+    using SS = SpreadShape<M, TYP>;
     constexpr int TY = SS::TY, LS = SS::LS, NW = kSpreadThreads / 64, U = 4, W = 8;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ddy = lane >> 3, ddx = lane & 7, loff = ddy * LS + ddx;
@@ -840,10 +841,10 @@ __device__ __forceinline__ void spread_staged_w8(const SpreadStage& st, int nst,
 // (l % 18) / 6 (and that + 3 in the second instruction), column l % 6.  A
 // knot's weights are read once for both halves.  Each wave takes U triples at
 // a time (every NW-th).
-template <int M>
+template <int M, int TYP>
 __device__ __forceinline__ void spread_staged_w6(const SpreadStage& st, int nst,
                                                  unsigned long long* __restrict__ acc) {
-    using SS = SpreadShape<M>;
+    using SS = SpreadShape<M, TYP>;
     constexpr int TY = SS::TY, LS = SS::LS, NW = kSpreadThreads / 64, U = 2, W = 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = lane / 18, r = lane - slot * 18, ddy = r / W, ddx = r - ddy * W;
@@ -887,14 +888,14 @@ __device__ __forceinline__ void spread_staged_w6(const SpreadStage& st, int nst,
 // One spreading tile (z row z0, y rows y0 .. y0+TY-1 of rotation s), for the
 // components c0 .. c1-1 (c0 even).  Entered by the whole workgroup; the LDS
 // regions are laid out by the caller.
-template <int M>
+template <int M, int TYP>
 __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const int* __restrict__ bin_start,
                             unsigned char* __restrict__ tile_live, const int* __restrict__ scell,
                             const float* __restrict__ skbw, const float* __restrict__ swts, int64_t nk, int q, int w,
                             int cap, float fix_scale, float fix_inv, float2* __restrict__ out, float2* lds,
                             int* wave_tot, int* rstart, int* rpre, int ygs) {
     constexpr int H = M / 4;  // half of the n = M/2 kept modes along x
-    using SS = SpreadShape<M>;
+    using SS = SpreadShape<M, TYP>;
     constexpr int TY = SS::TY, SC = SS::SC, NPTS = SS::NPTS, LS = SS::LS;
     constexpr int NT = kSpreadThreads;
     static_assert(NPTS % NT == 0, "tile must split evenly over the workgroup");
@@ -913,7 +914,7 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
     const float* kb_ = skbw + (int64_t)s * nk * 3 * w;
     const float* wq_ = swts + (int64_t)s * nk * q;
     if (c0 >= c1) return false;  // no component to spread (never staged: weights would be read past q)
-    tile_ranges<M>(bin_start + (size_t)s * (SS::KEYS + 1), w, y0, z0, ygs, rstart, rpre);
+    tile_ranges<M, TYP>(bin_start + (size_t)s * (SS::KEYS + 1), w, y0, z0, ygs, rstart, rpre);
     __syncthreads();
     const int ncand = rpre[nr];
     // candidates are spread in blocks of `cap` (one staging each): a tile of one
@@ -923,11 +924,11 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
     auto stage = [&](int b, int cp) {
         const int c0b = b * cap, cnt = min(cap, ncand - b * cap);
         switch (w) {  // the width as a constant: the loaded weights stay in registers
-        case 6: return stage_block<M, 6>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st, wave_tot);
-        case 8: return stage_block<M, 8>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st, wave_tot);
-        case 10: return stage_block<M, 10>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st,
+        case 6: return stage_block<M, TYP, 6>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st, wave_tot);
+        case 8: return stage_block<M, TYP, 8>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st, wave_tot);
+        case 10: return stage_block<M, TYP, 10>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st,
                                            wave_tot);
-        default: return stage_block<M, 12>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st,
+        default: return stage_block<M, TYP, 12>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st,
                                            wave_tot);
         }
     };
@@ -953,9 +954,9 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
                 const float f = st.wz[threadIdx.x] * fix_scale;
                 nxt = make_float2(wp[0] * f, cp + 3 < q ? wp[1] * f : 0.0f);
             }
-            if (use_win<M>(w) && w == 6) spread_staged_w6<M>(st, kept, acc);
-            else if (use_win<M>(w) && w == 8) spread_staged_w8<M>(st, kept, acc);
-            else spread_staged_rows<M>(st, kept, w, y0, acc);
+            if (use_win<M, TYP>(w) && w == 6) spread_staged_w6<M, TYP>(st, kept, acc);
+            else if (use_win<M, TYP>(w) && w == 8) spread_staged_w8<M, TYP>(st, kept, acc);
+            else spread_staged_rows<M, TYP>(st, kept, w, y0, acc);
             __syncthreads();
         }
         if (cp == c0) {
@@ -972,18 +973,17 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
         {
             constexpr int NB0 = M / 8, WORK0 = TY * NB0;
             static_assert(WORK0 <= NT, "one first-pass butterfly per thread");
-            static_assert(!(SS::TY < M) || NB0 >= kWinMax - 1, "edge columns within the first butterflies");
             const int c = threadIdx.x % TY, jb = threadIdx.x / TY;
-            const bool fold = use_win<M>(w) && jb < w - 1;
+            const bool fold = use_win<M, TYP>(w);
             float2 v0[8];
             if ((int)threadIdx.x < WORK0) {
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const int e = c * LS + jb + r * NB0;
                     unsigned long long re = acc[e], im = acc[TY * LS + e];
-                    if (r == 0 && fold) {
-                        re += acc[c * LS + M + jb];
-                        im += acc[TY * LS + c * LS + M + jb];
+                    if (fold && jb + r * NB0 < w - 1) {
+                        re += acc[c * LS + M + jb + r * NB0];
+                        im += acc[TY * LS + c * LS + M + jb + r * NB0];
                     }
                     v0[r] = make_float2(fixed_to_float(re, fix_inv), fixed_to_float(im, fix_inv));
                 }
@@ -1027,7 +1027,7 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
 constexpr int kSplitBucket = 5;  // candidate sets of 256 knots or more
 constexpr int kSplitParts = 5;   // items per cut tile (at most the component pairs)
 
-template <int M>
+template <int M, int TYP>
 __global__ __launch_bounds__(kSpreadThreads, 4) void k_spread_fftx(const int* __restrict__ bin_start,
                                                                 unsigned char* __restrict__ tile_live,
                                                                 int* __restrict__ plan, const int* __restrict__ list,
@@ -1039,7 +1039,7 @@ __global__ __launch_bounds__(kSpreadThreads, 4) void k_spread_fftx(const int* __
                                                                 const float2* __restrict__ twm,
                                                                 unsigned long long* __restrict__ work,
                                                                 unsigned long long rec_bytes, int ygs) {
-    using SS = SpreadShape<M>;
+    using SS = SpreadShape<M, TYP>;
     constexpr int NTY = M / SS::TY, TILES = M * NTY;
     unsigned long long wrote = 0;  // bytes of kept x modes this workgroup wrote
     extern __shared__ float2 lds[];
@@ -1076,7 +1076,7 @@ __global__ __launch_bounds__(kSpreadThreads, 4) void k_spread_fftx(const int* __
         const int s = id / TILES, tile = id % TILES;
         const int ppp = ((q + 1) / 2 + parts[b] - 1) / parts[b];  // component pairs per part
         const int c0 = 2 * part * ppp, c1 = min(c0 + 2 * ppp, q);  // c0 < q: no part is empty
-        if (spread_tile<M>(s, tile / NTY, (tile % NTY) * SS::TY, tile % NTY, c0, c1, bin_start, tile_live, scell,
+        if (spread_tile<M, TYP>(s, tile / NTY, (tile % NTY) * SS::TY, tile % NTY, c0, c1, bin_start, tile_live, scell,
                            skbw, swts, nk, q, w, cap, fix_scale, fix_inv, out, lds, wave_tot, rstart, rpre, ygs))
             wrote += (unsigned long long)SS::TY * (M / 4) * sizeof(float2) * (c1 - c0);
     }
@@ -1168,14 +1168,14 @@ __device__ __forceinline__ void fft_cols_regs(float2 (&v)[NBF][8], float2* a, co
 // slab = rotation * q + component.  A workgroup takes YZB z rows of one
 // rotation and column block, every component of them; dead z rows are skipped
 // (their output is never read) and rows of dead y tiles are zero.
-template <int M, int COLS>
+template <int M, int COLS, int TYP>
 __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ in, float2* __restrict__ out,
                                                     const float2* __restrict__ twm, int q, int cg,
                                                     const int* __restrict__ bin_start,
                                                     const unsigned char* __restrict__ tile_live, int64_t nk, int w,
                                                     int ygs) {
     constexpr int N = ColShape<M>::N, H = ColShape<M>::H, YZB = ColShape<M>::YZB;
-    constexpr int TY = SpreadShape<M>::TY, NT = M / TY;
+    constexpr int TY = SpreadShape<M, TYP>::TY, NT = M / TY;
     using P = RegPass<M, COLS>;
     extern __shared__ float2 lds[];
     __shared__ unsigned char live[NT];
@@ -1187,7 +1187,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ i
     // transformed
     const int ng = (q + cg - 1) / cg;
     const int s = blockIdx.z / ng, cbeg = (blockIdx.z % ng) * cg, cend = min(q, cbeg + cg);
-    const int* bs = bin_start + (size_t)s * (SpreadShape<M>::KEYS + 1);
+    const int* bs = bin_start + (size_t)s * (SpreadShape<M, TYP>::KEYS + 1);
     const int c0 = blockIdx.x * COLS;
     load_table<M>(twl, twm);
     for (int z = blockIdx.y * YZB; z < blockIdx.y * YZB + YZB; ++z) {
@@ -1951,16 +1951,19 @@ hipError_t with_m(int m, F&& f) {
 // of a pass whose widths are C; an unlisted width is an error.
 template <class C, class F>
 hipError_t with_cols(int want, F&& f) {
-    if (want == 0 || want == C::DEF) {
-        f(std::integral_constant<int, C::DEF>{});
-    } else if (want == C::DN) {
-        f(std::integral_constant<int, C::DN>{});
-    } else if (want == C::UP) {
-        f(std::integral_constant<int, C::UP>{});
-    } else {
-        return hipErrorInvalidValue;
-    }
-    return hipSuccess;
+    // f may return the error of a dispatch of its own (with_ty)
+    auto call = [&](auto cc) -> hipError_t {
+        if constexpr (std::is_same_v<decltype(f(cc)), hipError_t>) {
+            return f(cc);
+        } else {
+            f(cc);
+            return hipSuccess;
+        }
+    };
+    if (want == 0 || want == C::DEF) return call(std::integral_constant<int, C::DEF>{});
+    if (want == C::DN) return call(std::integral_constant<int, C::DN>{});
+    if (want == C::UP) return call(std::integral_constant<int, C::UP>{});
+    return hipErrorInvalidValue;
 }
 
 // two spreading workgroups per CU: dynamic LDS plus the kernel's static arrays
@@ -1970,18 +1973,27 @@ constexpr size_t kSpreadLds = 79 * 1024;
 // bytes of one staged knot: component pair, cell, position, z weight, x and y weights
 inline size_t staged_bytes(int w) { return 20 + 8 * (size_t)w; }
 
-template <int M>
+template <int M, int TYP>
 int spread_cap_t(int w) {
-    const size_t fixed = SpreadShape<M>::FIXED;
+    const size_t fixed = SpreadShape<M, TYP>::FIXED;
     const size_t room = fixed < kSpreadLds ? kSpreadLds - fixed : 0;
     int cap = (int)std::min<size_t>(512, room / staged_bytes(w));
     cap &= ~63;
     return cap < 64 ? 64 : cap;
 }
 
-template <int M>
+template <int M, int TYP>
 size_t spread_lds_t(int w) {
-    return SpreadShape<M>::FIXED + (size_t)spread_cap_t<M>(w) * staged_bytes(w);
+    return SpreadShape<M, TYP>::FIXED + (size_t)spread_cap_t<M, TYP>(w) * staged_bytes(w);
+}
+
+// Calls f with the spreading pass's tile height as a constant: the default at
+// M, or half of it when the tuning chose that (tile_choices).
+template <int M, class F>
+auto with_ty(const Geom& g, F&& f) {
+    constexpr int T0 = SpreadShape<M>::TY;
+    if (g.tile_rows == T0 / 2) return f(std::integral_constant<int, T0 / 2>{});
+    return f(std::integral_constant<int, T0>{});
 }
 
 }  // namespace
@@ -2030,12 +2042,17 @@ hipError_t launch_scatter_plan(const Geom& g, int S, int q, const Occupancy& occ
     if (occ.nk == 0 || S == 0) return hipSuccess;
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
-        constexpr int tiles = M * (M / SpreadShape<M>::TY);
-        const int G = bin_group(g);
-        const int nscatter = bin_blocks(occ.nk);
-        hipLaunchKernelGGL(k_scatter_plan<M>, dim3(nscatter + (tiles + 255) / 256, S), dim3(256), 0, st, d_rec,
-                           d_wts, d_rank, occ.bin_start, occ.nk, log2i(G), M / G, g.w, g.beta, g.inv_i0beta, q,
-                           d_scell, d_skbw, d_swts, nscatter, occ.tile_live, d_plan, d_list, S * tiles);
+        return with_ty<M>(g, [&](auto tc) {
+            constexpr int TY = decltype(tc)::value;
+            constexpr int tiles = M * (M / TY);
+            const int G = bin_group(g);
+            const int nscatter = bin_blocks(occ.nk);
+            hipLaunchKernelGGL((k_scatter_plan<M, TY>), dim3(nscatter + (tiles + 255) / 256, S), dim3(256), 0, st,
+                               d_rec, d_wts, d_rank, occ.bin_start, occ.nk, log2i(G), M / G, g.w, g.beta,
+                               g.inv_i0beta, q, d_scell, d_skbw, d_swts, nscatter, occ.tile_live, d_plan, d_list,
+                               S * tiles);
+            return hipGetLastError();
+        });
     });
 }
 
@@ -2045,7 +2062,8 @@ size_t max_lds_bytes(const Geom& g, int qmax) {
         constexpr int M = decltype(mc)::value;
         constexpr int N = M / 2;
         using C = ColShape<M>;
-        need = std::max(need, spread_lds_t<M>(g.w));
+        constexpr int T0 = SpreadShape<M>::TY;
+        need = std::max(need, std::max(spread_lds_t<M, T0>(g.w), spread_lds_t<M, T0 / 2>(g.w)));
         // the widest width of each pass
         need = std::max(need, sizeof(float2) * ((size_t)M * std::max(C::Y::UP, C::Z::UP) + M + N));
         need = std::max(need, sizeof(float2) * ((size_t)N * C::IY::UP + N));
@@ -2058,9 +2076,28 @@ int spread_tiles(const Geom& g) {
     int t = 0;
     (void)with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
-        t = M / SpreadShape<M>::TY;
+        with_ty<M>(g, [&](auto tc) { t = M / decltype(tc)::value; });
     });
     return t;
+}
+
+int spread_tiles_max(const Geom& g) {
+    int t = 0;
+    (void)with_m(g.m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        t = M / (SpreadShape<M>::TY / 2);
+    });
+    return t;
+}
+
+int tile_choices(int m, int out[2]) {
+    int k = 0;
+    (void)with_m(m, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        out[k++] = SpreadShape<M>::TY;
+        out[k++] = SpreadShape<M>::TY / 2;
+    });
+    return k;
 }
 
 hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, int* d_plan, const int* d_list,
@@ -2069,13 +2106,18 @@ hipError_t launch_spread_fftx(const Geom& g, int S, const Occupancy& occ, int* d
     if (S == 0 || occ.nk == 0) return hipSuccess;
     return with_m(g.m, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
-        constexpr int tiles = M * (M / SpreadShape<M>::TY);
-        hipLaunchKernelGGL(k_spread_fftx<M>, dim3(std::max(1, g.spread_wgs)), dim3(kSpreadThreads),
-                           spread_lds_t<M>(g.w), st, occ.bin_start, occ.tile_live, d_plan, d_list, S * tiles, d_scell,
-                           d_skbw, d_swts, occ.nk, q, g.w, spread_cap_t<M>(g.w), fix_scale, 1.0f / fix_scale, d_out,
-                           d_twm, d_work,
-                           (unsigned long long)occ.nk * S * (sizeof(int) + 3 * sizeof(float) * g.w + sizeof(float) * q),
-                           log2i(bin_group(g)));
+        return with_ty<M>(g, [&](auto tc) {
+            constexpr int TY = decltype(tc)::value;
+            constexpr int tiles = M * (M / TY);
+            hipLaunchKernelGGL((k_spread_fftx<M, TY>), dim3(std::max(1, g.spread_wgs)), dim3(kSpreadThreads),
+                               (spread_lds_t<M, TY>(g.w)), st, occ.bin_start, occ.tile_live, d_plan, d_list,
+                               S * tiles, d_scell, d_skbw, d_swts, occ.nk, q, g.w, (spread_cap_t<M, TY>(g.w)), fix_scale,
+                               1.0f / fix_scale, d_out, d_twm, d_work,
+                               (unsigned long long)occ.nk * S *
+                                   (sizeof(int) + 3 * sizeof(float) * g.w + sizeof(float) * q),
+                               log2i(bin_group(g)));
+            return hipGetLastError();
+        });
     });
 }
 
@@ -2096,9 +2138,13 @@ hipError_t launch_fft_y(const Geom& g, int S, int q, const Occupancy& occ, const
             const long rows = (long)(C::H / COLS) * (M / C::YZB) * S;
             int cg = q;
             while (cg > 1 && rows * ((q + cg - 1) / cg) < kYMinBlocks) cg = (cg + 1) / 2;
-            hipLaunchKernelGGL((k_fft_y<M, COLS>), dim3(C::H / COLS, M / C::YZB, S * ((q + cg - 1) / cg)),
-                               dim3(kThreads), sizeof(float2) * ((size_t)M * COLS + M), st, d_in, d_out, d_twm, q,
-                               cg, occ.bin_start, occ.tile_live, occ.nk, g.w, log2i(bin_group(g)));
+            return with_ty<M>(g, [&](auto tc) {
+                constexpr int TY = decltype(tc)::value;
+                hipLaunchKernelGGL((k_fft_y<M, COLS, TY>), dim3(C::H / COLS, M / C::YZB, S * ((q + cg - 1) / cg)),
+                                   dim3(kThreads), sizeof(float2) * ((size_t)M * COLS + M), st, d_in, d_out, d_twm,
+                                   q, cg, occ.bin_start, occ.tile_live, occ.nk, g.w, log2i(bin_group(g)));
+                return hipGetLastError();
+            });
         });
     });
 }

@@ -98,6 +98,15 @@ def test_every_launch_shape_gives_the_same_bits(n):
         _same(_eval(c, q, out), ref, "bin_group = %d" % gsz)
         _say("  bin_group = %d: bitwise equal" % gsz)
     c.set_tuning(bin_group=base["bin_group"])
+    # the spreading pass's tile height
+    rows = pkg.corr_tuning_choices(c.ctx, 5)
+    assert rows[0] == base["tile_rows"] and rows[1] == base["tile_rows"] // 2
+    c.set_tuning(tile_rows=rows[1])
+    _same(_eval(c, q, out), ref, "tile_rows = %d" % rows[1])
+    _say("  tile_rows = %d: bitwise equal" % rows[1])
+    c.set_tuning(tile_rows=rows[1], bin_group=bins[-1])
+    _same(_eval(c, q, out), ref, "tile_rows = %d, bin_group = %d" % (rows[1], bins[-1]))
+    c.set_tuning(tile_rows=base["tile_rows"], bin_group=base["bin_group"])
     cus = base["spread_wgs"] // 2
     for v in (1, cus):
         c.set_tuning(spread_wgs=v)
@@ -116,6 +125,8 @@ def test_every_launch_shape_gives_the_same_bits(n):
         c.set_tuning(slots=257)
     with pytest.raises(pkg.CorrError):
         c.set_tuning(bin_group=3)
+    with pytest.raises(pkg.CorrError):
+        c.set_tuning(tile_rows=3)
     c.close()
 
 
@@ -131,7 +142,7 @@ def test_autotune_keeps_a_valid_tuning_and_the_results():
     t = c.autotune(q, reps=1)
     _say("  kept:", t)
     assert t == c.tuning()
-    for p, f in enumerate(("cols_y", "cols_z", "cols_iy", "pairs_ix", "bin_group")):
+    for p, f in enumerate(("cols_y", "cols_z", "cols_iy", "pairs_ix", "bin_group", "tile_rows")):
         assert t[f] in pkg.corr_tuning_choices(c.ctx, p)
     assert 1 <= t["slots"] <= 256 and t["graph"] == 0
     _same(_eval(c, q, out), ref, "after autotune")
@@ -284,7 +295,7 @@ def test_batch_autotune_keeps_every_bit():
     kept = b.autotune(quats, (s, pv, pi), reps=1)
     torch.cuda.synchronize()
     _say("  kept %s" % kept)
-    assert 0 <= kept["rank_bin_group"] <= 2
+    assert 0 <= kept["rank_bin_group"] <= 2 and 0 <= kept["rank_tile_rows"] <= 1
     off = 0
     for x, q, n in zip(ref_s, quats, b.ns):
         assert torch.equal(s[off:off + len(q) * n ** 3].view(len(q), n, n, n), x)
