@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <new>
 #include <string>
@@ -640,6 +641,46 @@ void setup_shape(corr_ctx* c, Shape& s, const corr_ball* balls, int64_t n, doubl
     s.ex = build_expansion(rlo, rhi, dk, c->g.m2n, c->tol, c->sc_r0, c->sc_lam);
 }
 
+// Storage order of a shape's balls on the device: Morton order of their
+// centres (10 bits per axis over the centres' bounding box, ties by index).
+// Balls near in space are then near in memory, so after a rotation the knots
+// of one wave mostly share their sort keys (one counter increment per key and
+// wave in the binning) and the scatter writes runs of the sorted order.  The
+// spreading sums are exact integers, so the scores do not depend on it.
+std::vector<int64_t> morton_order(const corr_ball* balls, int64_t n) {
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = std::numeric_limits<double>::infinity();
+        hi[d] = -lo[d];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const double x[3] = {balls[i].x, balls[i].y, balls[i].z};
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], x[d]);
+            hi[d] = std::max(hi[d], x[d]);
+        }
+    }
+    auto spread = [](uint64_t v) {  // bit b of v to bit 3b
+        uint64_t r = 0;
+        for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1u) << (3 * b);
+        return r;
+    };
+    std::vector<std::pair<uint64_t, int64_t>> key((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        const double x[3] = {balls[i].x, balls[i].y, balls[i].z};
+        uint64_t k = 0;
+        for (int d = 0; d < 3; ++d) {
+            const double t = hi[d] > lo[d] ? (x[d] - lo[d]) / (hi[d] - lo[d]) : 0.0;
+            k |= spread((uint64_t)std::min(1023.0, std::max(0.0, std::floor(t * 1024.0)))) << d;
+        }
+        key[(size_t)i] = {k, i};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int64_t> order((size_t)n);
+    for (int64_t i = 0; i < n; ++i) order[(size_t)i] = key[(size_t)i].second;
+    return order;
+}
+
 void upload_shape(corr_ctx* c, DevMem& mem, Shape& s, const corr_ball* balls, double dk) {
     const Expansion& e = s.ex;
     const int64_t n = s.n;
@@ -651,23 +692,25 @@ void upload_shape(corr_ctx* c, DevMem& mem, Shape& s, const corr_ball* balls, do
         std::vector<double> pos((size_t)3 * n);
         std::vector<float> w((size_t)e.q * n);
         std::vector<double> lrow(e.p);
+        const std::vector<int64_t> order = morton_order(balls, n);
         for (int64_t i = 0; i < n; ++i) {
-            pos[3 * i] = balls[i].x;
-            pos[3 * i + 1] = balls[i].y;
-            pos[3 * i + 2] = balls[i].z;
-            lagrange_row(e, std::min(std::max(balls[i].r, e.rlo), e.rhi), lrow.data());
+            const corr_ball& b = balls[order[(size_t)i]];
+            pos[3 * i] = b.x;
+            pos[3 * i + 1] = b.y;
+            pos[3 * i + 2] = b.z;
+            lagrange_row(e, std::min(std::max(b.r, e.rlo), e.rhi), lrow.data());
             // equal radii: exact volume ratio (with an offset the two terms scale
             // differently; the lifted kernel is tabulated at the radius itself)
-            if (e.p == 1 && e.r0 == 0.0 && !c->lifted) lrow[0] = std::pow(balls[i].r / e.rhi, 3.0);
+            if (e.p == 1 && e.r0 == 0.0 && !c->lifted) lrow[0] = std::pow(b.r / e.rhi, 3.0);
             for (int q = 0; q < e.q; ++q) {
                 double u = 0;
-                for (int b = 0; b < e.p; ++b) u += lrow[b] * e.basis[(size_t)b * e.q + q];
-                w[(size_t)q * n + i] = (float)(balls[i].w * u);
+                for (int k = 0; k < e.p; ++k) u += lrow[k] * e.basis[(size_t)k * e.q + q];
+                w[(size_t)q * n + i] = (float)(b.w * u);
             }
         }
         upload(s.pos, pos.data(), sizeof(double) * pos.size(), c->stream);
         std::vector<double> rad((size_t)n);
-        for (int64_t i = 0; i < n; ++i) rad[i] = balls[i].r;
+        for (int64_t i = 0; i < n; ++i) rad[i] = balls[order[(size_t)i]].r;
         upload(s.rad, rad.data(), sizeof(double) * rad.size(), c->stream);
         upload(s.wts, w.data(), sizeof(float) * w.size(), c->stream);
         // fixed-point scale: one knot adds w_ic times window values <= 1 to a

@@ -370,7 +370,8 @@ __device__ __forceinline__ void scan_counts(int* __restrict__ cs, int* __restric
 // Rotate + place + counts per key: each knot's record is its packed cell and
 // its offsets from that cell along x, y and z (FP32, in [0, 1)), from which the
 // scatter evaluates the window weights.  Workgroup (0, 0) also clears the tile
-// plan's counters.
+// plan's counters.  The rank of a knot within its key depends on the order
+// of the increments; the spreading sums do not (they are exact integers).
 __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restrict__ quats,
                                                           const double* __restrict__ pos, int64_t nk, double inv_hf,
                                                           int m, int yshift, int nyb, int kstride,
@@ -380,6 +381,7 @@ __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restri
     const int64_t j = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
     const int s = blockIdx.y;
     if (blockIdx.x == 0 && s == 0 && (int)threadIdx.x < nplan) plan[threadIdx.x] = 0;
+    int key = -1;
     if (j < nk) {
         const double* q = quats + 4 * s;
         double nn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
@@ -395,20 +397,35 @@ __global__ __launch_bounds__(kBinBlock) void k_rotate_bin(const double* __restri
         for (int d = 0; d < 3; ++d) {
             double fl = floor(u[d]);
             float f = (float)(u[d] - fl);
-            long long ci = (long long)fl % m;
-            if (ci < 0) ci += m;
-            c[d] = (int)ci;
+            c[d] = (int)((long long)fl & (long long)(m - 1));  // m is a power of two
             if (f >= 1.0f) {
                 f = 0.0f;
-                c[d] = (c[d] + 1) % m;
+                c[d] = (c[d] + 1) & (m - 1);
             }
             f3[d] = f;
         }
         rec[(int64_t)s * nk + j] = make_int4(c[0] | (c[1] << 10) | (c[2] << 20), __float_as_int(f3[0]),
                                              __float_as_int(f3[1]), __float_as_int(f3[2]));
-        const int key = c[2] * nyb + (c[1] >> yshift);
-        rank[(int64_t)s * nk + j] = atomicAdd(&counts[(size_t)s * kstride + key], 1);
+        key = c[2] * nyb + (c[1] >> yshift);
     }
+    // the lanes of a wave that share a key take one counter increment: the
+    // lowest of them adds the group's size, and each gets the base plus its
+    // place among the group's lanes.  Every lane runs the loop (one pass per
+    // distinct key of the wave); lanes past nk have no key.
+    const int lane = threadIdx.x & 63;
+    int* cnt = counts + (size_t)s * kstride;
+    unsigned long long todo = __ballot(key >= 0), same = 0;
+    while (todo) {
+        const int lk = __builtin_amdgcn_readlane(key, __ffsll(todo) - 1);
+        const unsigned long long grp = __ballot(key == lk);
+        if (key == lk) same = grp;
+        todo &= ~grp;
+    }
+    const int first = same ? __ffsll(same) - 1 : lane;
+    int base = 0;
+    if (key >= 0 && first == lane) base = atomicAdd(cnt + key, __popcll(same));
+    base = __shfl(base, first, 64);
+    if (j < nk) rank[(int64_t)s * nk + j] = base + __popcll(same & ((1ull << lane) - 1ull));
 }
 
 // Key starts of each rotation from its counts (one workgroup per rotation,
