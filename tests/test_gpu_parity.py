@@ -290,6 +290,33 @@ def test_repeated_evaluation_is_bitwise_identical():
     c.close()
 
 
+def test_ball_order_does_not_change_scores():
+    # the library keeps balls in an order of its own (by position) and the
+    # spreading sums are exact integers: any input order gives the same bits.
+    # Balls sharing a centre (equal position keys) keep their input order
+    # among themselves, so the reversed input also reorders knots on the device.
+    A = synth.mixture_balls(2000, 1400)
+    B = synth.mixture_balls(1500, 2400)
+    twins = B[:400].copy()
+    twins[:, 3] *= 0.5
+    B = np.concatenate([B, twins])
+    g = synth.grid_for(A, B, 64)
+    q = synth.random_quaternions(3, 3400)
+    rng = np.random.default_rng(3401)
+    _say("case: ball order, 2000 + 1900 balls (400 sharing a centre), n=64")
+    outs = []
+    for pa, pb in ((np.arange(len(A)), np.arange(len(B))), (rng.permutation(len(A)), rng.permutation(len(B))),
+                   (np.arange(len(A))[::-1], np.arange(len(B))[::-1])):
+        c = _corr(A[pa], B[pb], g, batch=2)
+        s, p, i = c.eval(q)
+        torch.cuda.synchronize()
+        outs.append((s.clone(), p.clone(), i.clone()))
+        c.close()
+    for s, p, i in outs[1:]:
+        assert torch.equal(s, outs[0][0]) and torch.equal(p, outs[0][1]) and torch.equal(i, outs[0][2])
+    _check_scores("ball order", outs[0][0].cpu().numpy().astype(np.float64), _o2(A, B, q[:1], g))
+
+
 def _reached_tiles(balls, R, m, box, w, ty):
     """Tiles (z row, y tile) that some knot's window reaches, counted on the host
     from the rotated centres: a knot in cell c covers cells c - w/2 + 1 .. c + w/2."""
