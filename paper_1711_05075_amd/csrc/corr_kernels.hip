@@ -118,9 +118,12 @@ __device__ __forceinline__ void dft8(float2* v) {
 // done in place: in every pass each thread first reads the inputs of all its
 // butterflies into registers, the workgroup synchronises, and the outputs are
 // written back over the same buffer.  All sizes are compile-time powers of
-// two.  tw[j] = exp(-2 pi i j / LEN) is an LDS table.
+// two.  tw[j] = exp(-2 pi i j / LEN) is an LDS table.  With HALF only the
+// outputs of index < LEN/4 or >= 3 LEN/4 are written by the last pass (the
+// band the forward passes keep); the others are left unspecified, and the
+// arithmetic that only they need is not done.
 // ---------------------------------------------------------------------------
-template <int LEN, int NS, int SIGN, int COLS, int SI, int SC, int NT>
+template <int LEN, int NS, int SIGN, int COLS, int SI, int SC, int NT, bool HALF = false>
 __device__ __forceinline__ void fft_passes(float2* a, const float2* tw) {
     if constexpr (NS < LEN) {
         constexpr int REM = LEN / NS;
@@ -160,11 +163,22 @@ __device__ __forceinline__ void fft_passes(float2* a, const float2* tw) {
                 const int k = j % NS;
                 const int o = (j / NS) * NS * R + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) a[(o + r * NS) * SI + c * SC] = v[u][r];
+                for (int r = 0; r < R; ++r) {
+                    // last pass: output k + r LEN/R (k < LEN/R) is in the band iff
+                    // r < R/4 or r >= 3R/4 (R = 4, 8); for R = 2 it depends on k
+                    if constexpr (HALF && NS * R == LEN) {
+                        if constexpr (R >= 4) {
+                            if (r >= R / 4 && r < 3 * R / 4) continue;
+                        } else {
+                            if ((r == 0) != (k < LEN / 4)) continue;
+                        }
+                    }
+                    a[(o + r * NS) * SI + c * SC] = v[u][r];
+                }
             }
         }
         __syncthreads();
-        fft_passes<LEN, NS * R, SIGN, COLS, SI, SC, NT>(a, tw);
+        fft_passes<LEN, NS * R, SIGN, COLS, SI, SC, NT, HALF>(a, tw);
     }
 }
 
@@ -1013,7 +1027,7 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
             }
             __syncthreads();
         }
-        fft_passes<M, 8, -1, TY, 1, SC, NT>(a, twl);
+        fft_passes<M, 8, -1, TY, 1, SC, NT, true>(a, twl);  // only the kept band is read below
         constexpr int PER = TY * H;
         for (int t = threadIdx.x; t < 2 * PER; t += NT) {
             const int comp = t >= PER;
@@ -1163,8 +1177,30 @@ struct RegPass {
     static constexpr int NB = LEN / 8, WORK = NB * COLS, NBF = (WORK + NT - 1) / NT;
 };
 
-template <int LEN, int SIGN, int COLS, int NBF, int NT = kThreads>
-__device__ __forceinline__ void fft_cols_regs(float2 (&v)[NBF][8], float2* a, const float2* tw) {
+// Raw buffer view of one array of float2: the buffer unit checks every
+// offset against the array's size, and a load at or past the end returns zero
+// without touching memory.  A column read that skips dead rows then needs no
+// branch (offset kPastEnd), and the compiler can count the loads in flight
+// exactly, so they stay in flight across the transform that follows.
+constexpr uint32_t kPastEnd = 0x80000000u;
+struct ZeroPastEnd {
+    __amdgpu_buffer_rsrc_t r;
+    // dword 3 of the resource: 32-bit data format, no swizzle, no thread id
+    __device__ ZeroPastEnd(const float2* base, size_t count)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(base), 0, (int)(count * sizeof(float2)), 0x00020000)) {}
+    __device__ ZeroPastEnd(const float* base, size_t count)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)(count * sizeof(float)), 0x00020000)) {}
+    __device__ float2 load(uint32_t byte_off) const {
+        const auto d = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+        return make_float2(__uint_as_float(d[0]), __uint_as_float(d[1]));
+    }
+    __device__ float load1(uint32_t byte_off) const {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+    }
+};
+
+template <int LEN, int SIGN, int COLS, bool HALF, int NBF, int NT = kThreads>
+__device__ __forceinline__ void fft_cols_regs_impl(float2 (&v)[NBF][8], float2* a, const float2* tw) {
     using P = RegPass<LEN, COLS, NT>;
     static_assert(NBF == P::NBF, "one register row per first-pass butterfly");
 #pragma unroll
@@ -1178,7 +1214,17 @@ __device__ __forceinline__ void fft_cols_regs(float2 (&v)[NBF][8], float2* a, co
         }
     }
     __syncthreads();
-    fft_passes<LEN, 8, SIGN, COLS, COLS, 1, NT>(a, tw);
+    fft_passes<LEN, 8, SIGN, COLS, COLS, 1, NT, HALF>(a, tw);
+}
+template <int LEN, int SIGN, int COLS, int NBF>
+__device__ __forceinline__ void fft_cols_regs(float2 (&v)[NBF][8], float2* a, const float2* tw) {
+    fft_cols_regs_impl<LEN, SIGN, COLS, false>(v, a, tw);
+}
+// The same, with only the band of outputs the forward passes keep (index
+// < LEN/4 or >= 3 LEN/4) written; bit for bit the same values there.
+template <int LEN, int SIGN, int COLS, int NBF>
+__device__ __forceinline__ void fft_cols_regs_band(float2 (&v)[NBF][8], float2* a, const float2* tw) {
+    fft_cols_regs_impl<LEN, SIGN, COLS, true>(v, a, tw);
 }
 
 // a2: y pass over [slab][z][y][mx] -> [slab][z][my][mx], M points pruned to N,
@@ -1236,7 +1282,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_y(const float2* __restrict__ i
 #pragma unroll
                 for (int r = 0; r < 8; ++r) v[u][r] = nxt[u][r];
             if (c + 1 < cend) fetch(c + 1);
-            fft_cols_regs<M, -1, COLS>(v, a, twl);
+            fft_cols_regs_band<M, -1, COLS>(v, a, twl);
             float2* dst = out + ((size_t)(s * q + c) * M + z) * N * H + c0;
             for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
                 const int o = t / COLS, cc = t % COLS;
@@ -1268,11 +1314,32 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
     const int my = iy < N / 2 ? iy : iy - N;
 #pragma unroll
     for (int k = 0; k < PER; ++k) acc[k] = make_float2(0.f, 0.f);
-    // component c's columns are read into registers, in the order of the
-    // transform's first pass, while component c-1 is being transformed
-    float2 nxt[P::NBF][8];
-    auto fetch = [&](int c) {
-        const float2* src = in + (((size_t)s * q + c) * M) * N * H + (size_t)iy * H + c0;
+    // the kept outputs' ball-transform entries: index |m|^2, or -1
+    int vidx[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int t = threadIdx.x + k * kThreads;
+        const int o = t / COLS, cc = t % COLS;
+        const int mz = o < N / 2 ? o : o - N, mx = c0 + cc;
+        const bool kept = t < N * COLS && kept_source<N, M>(o) >= 0;
+        vidx[k] = kept ? mx * mx + my * my + mz * mz : -1;
+    }
+    // component c's columns (in the order of the transform's first pass) and
+    // its ball-transform entries are read into registers while component c-1
+    // is being transformed: two register sets in turn.  Every read is issued
+    // unconditionally (dead rows, outputs out of the band and components past
+    // the last one read zeros past the end of a buffer view), so the loads of
+    // the next component stay in flight through the whole transform.
+    float2 va[P::NBF][8], vb[P::NBF][8];
+    float wa[PER], wb[PER];
+    auto fetch = [&](float2 (&v)[P::NBF][8], float (&wt)[PER], int c) {
+        const bool ok = c < q;
+        const int cs = ok ? c : q - 1;
+        const ZeroPastEnd vt(vtab + (size_t)cs * m2n, ok ? (size_t)m2n : 0);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) wt[k] = vt.load1(vidx[k] >= 0 ? (uint32_t)vidx[k] * 4u : kPastEnd);
+        const ZeroPastEnd src(in + (((size_t)s * q + cs) * M) * N * H + (size_t)iy * H + c0,
+                              ok ? (size_t)M * N * H - (size_t)iy * H - c0 : 0);
 #pragma unroll
         for (int u = 0; u < P::NBF; ++u) {
             const int t = u * kThreads + (int)threadIdx.x;
@@ -1281,50 +1348,32 @@ __device__ __forceinline__ void z_accumulate(const float2* __restrict__ in, int 
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const int z = j + r * P::NB;
-                    nxt[u][r] = zlive[z] ? src[(size_t)z * N * H + cc] : make_float2(0.f, 0.f);
+                    v[u][r] = src.load(zlive[z] ? (uint32_t)(z * N * H + cc) * 8u : kPastEnd);
                 }
             }
         }
     };
-    // the ball-transform entries of every kept output, read one component ahead
-    int vidx[PER];
-    float vcur[PER], vnxt[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int t = threadIdx.x + k * kThreads;
-        const int o = t / COLS, cc = t % COLS;
-        const int mz = o < N / 2 ? o : o - N, mx = c0 + cc;
-        const bool kept = t < N * COLS && kept_source<N, M>(o) >= 0;
-        vidx[k] = kept ? mx * mx + my * my + mz * mz : -1;
-        vcur[k] = kept ? vtab[vidx[k]] : 0.f;
-        vnxt[k] = 0.f;
-    }
-    fetch(0);
-    for (int c = 0; c < q; ++c) {
-        float2 v[P::NBF][8];
-#pragma unroll
-        for (int u = 0; u < P::NBF; ++u)
-#pragma unroll
-            for (int r = 0; r < 8; ++r) v[u][r] = nxt[u][r];
-        if (c + 1 < q) {
-            fetch(c + 1);
-            const float* vt = vtab + (size_t)(c + 1) * m2n;
-#pragma unroll
-            for (int k = 0; k < PER; ++k) vnxt[k] = vidx[k] >= 0 ? vt[vidx[k]] : 0.f;
-        }
-        fft_cols_regs<M, -1, COLS>(v, a, twl);
+    auto transform = [&](float2 (&v)[P::NBF][8], const float (&wt)[PER]) {
+        fft_cols_regs_band<M, -1, COLS>(v, a, twl);
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             if (vidx[k] >= 0) {
                 const int t = threadIdx.x + k * kThreads;
                 const int o = t / COLS, cc = t % COLS;
                 const float2 g = a[kept_source<N, M>(o) * COLS + cc];
-                acc[k].x = fmaf(vcur[k], g.x, acc[k].x);
-                acc[k].y = fmaf(vcur[k], g.y, acc[k].y);
+                acc[k].x = fmaf(wt[k], g.x, acc[k].x);
+                acc[k].y = fmaf(wt[k], g.y, acc[k].y);
             }
-            vcur[k] = vnxt[k];
         }
         __syncthreads();
+    };
+    fetch(va, wa, 0);
+    for (int c = 0; c < q; c += 2) {
+        fetch(vb, wb, c + 1);
+        transform(va, wa);
+        if (c + 1 == q) break;
+        fetch(va, wa, c + 2);
+        transform(vb, wb);
     }
 }
 
@@ -1511,7 +1560,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_z_components(const float2* __r
                 }
             }
         }
-        fft_cols_regs<M, -1, COLS>(v, a, twl);
+        fft_cols_regs_band<M, -1, COLS>(v, a, twl);
         float2* d = dst(c);
         for (int t = threadIdx.x; t < N * COLS; t += kThreads) {
             const int o = t / COLS, cc = t % COLS;
