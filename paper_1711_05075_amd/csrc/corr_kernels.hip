@@ -512,7 +512,10 @@ __device__ __forceinline__ void bin_scatter(int64_t j, int s, const int4* __rest
 template <int M, int TY_ = 0>
 struct SpreadShape {
     static constexpr int TY = TY_ ? TY_ : cmin<2048 / M, M>();
-    static constexpr int SC = M + 1;  // padded FFT line (float2)
+    // padded FFT line (float2): lines 16 / TY float2 apart in the banks, so
+    // that the column passes' 16-lane groups (TY lines x 16 / TY points) hit
+    // distinct banks
+    static constexpr int SC = M + (TY < 16 ? 16 / TY : 1);
     static constexpr int NPTS = TY * M;
     // fixed-point sums: a plane of int64 real parts and one of imaginary parts,
     // lines padded by 8 words so that consecutive lines of a window use the
@@ -1004,7 +1007,15 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
         {
             constexpr int NB0 = M / 8, WORK0 = TY * NB0;
             static_assert(WORK0 <= NT, "one first-pass butterfly per thread");
-            const int c = threadIdx.x % TY, jb = threadIdx.x / TY;
+            int c = threadIdx.x % TY, jb = threadIdx.x / TY;
+            if constexpr (NB0 >= 8 && TY % 2 == 0) {
+                // a 16-lane group takes two rows and eight consecutive
+                // butterflies, so that its reads of the sums fall in distinct banks
+                constexpr int NRP = TY / 2;
+                const int l = threadIdx.x & 15, g = threadIdx.x >> 4;
+                c = 2 * (g % NRP) + (l >> 3);
+                jb = 8 * (g / NRP) + (l & 7);
+            }
             const bool fold = use_win<M, TYP>(w);
             float2 v0[8];
             if ((int)threadIdx.x < WORK0) {
