@@ -870,33 +870,34 @@ __device__ __forceinline__ void spread_staged_w8(const SpreadStage& st, int nst,
     }
 }
 
-// w = 6: a wave instruction takes three knots' half windows, 3 rows x 6
-// columns each (54 of 64 lanes): lane l serves knot l / 18 of a triple, row
-// (l % 18) / 6 (and that + 3 in the second instruction), column l % 6.  A
-// knot's weights are read once for both halves.  Each wave takes U triples at
-// a time (every NW-th).
+// w = 6: a wave instruction takes two window rows of five knots (2 rows x 6
+// columns each, 60 of 64 lanes): lane l serves knot l / 12 of a group, row
+// (l % 12) / 6 (then + 2 and + 4 in the next two instructions), column l % 6.
+// The two rows of one knot in an instruction are consecutive lines, which lie
+// in different halves of the LDS banks.  Each wave takes U groups at a time
+// (every NW-th).
 template <int M, int TYP>
 __device__ __forceinline__ void spread_staged_w6(const SpreadStage& st, int nst,
                                                  unsigned long long* __restrict__ acc) {
     using SS = SpreadShape<M, TYP>;
     constexpr int TY = SS::TY, LS = SS::LS, NW = kSpreadThreads / 64, U = 2, W = 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = lane / 18, r = lane - slot * 18, ddy = r / W, ddx = r - ddy * W;
+    const int slot = lane / 12, r = lane - slot * 12, ddy = r / W, ddx = r - ddy * W;
     const int loff = ddy * LS + ddx;
-    const int ntrip = (nst + 2) / 3;
-    for (int t0 = wave; t0 < ntrip; t0 += U * NW) {
+    const int ngrp = (nst + 4) / 5;
+    for (int g0 = wave; g0 < ngrp; g0 += U * NW) {
         int word[U];
         bool ok[U];
-        float wy0[U], wy1[U], wx[U];
+        float wy[U][3], wx[U];
         float2 c2[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = (t0 + u * NW) * 3 + slot;
-            ok[u] = slot < 3 && i < nst;
+            const int i = (g0 + u * NW) * 5 + slot;
+            ok[u] = slot < 5 && i < nst;
             const int ic = min(i, nst - 1);  // a valid index for the reads
             word[u] = st.cell[ic];
-            wy0[u] = st.wy[ic * W + ddy];
-            wy1[u] = st.wy[ic * W + ddy + 3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p) wy[u][p] = st.wy[ic * W + 2 * p + ddy];
             wx[u] = st.wx[ic * W + ddx];
             c2[u] = st.wq[ic];
         }
@@ -904,16 +905,14 @@ __device__ __forceinline__ void spread_staged_w6(const SpreadStage& st, int nst,
         for (int u = 0; u < U; ++u) {
             if (!ok[u]) continue;
             const int row = win_row(word[u]) + ddy, off = win_off(word[u]) + loff;
-            if ((unsigned)row < (unsigned)TY) {
-                const float f = wy0[u] * wx[u];
-                atomicAdd(acc + off, (unsigned long long)(long long)__float2int_rn(c2[u].x * f));
-                atomicAdd(acc + TY * LS + off, (unsigned long long)(long long)__float2int_rn(c2[u].y * f));
-            }
-            if ((unsigned)(row + 3) < (unsigned)TY) {
-                const float f = wy1[u] * wx[u];
-                atomicAdd(acc + off + 3 * LS, (unsigned long long)(long long)__float2int_rn(c2[u].x * f));
-                atomicAdd(acc + TY * LS + off + 3 * LS,
-                          (unsigned long long)(long long)__float2int_rn(c2[u].y * f));
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                if ((unsigned)(row + 2 * p) < (unsigned)TY) {
+                    const float f = wy[u][p] * wx[u];
+                    atomicAdd(acc + off + 2 * p * LS, (unsigned long long)(long long)__float2int_rn(c2[u].x * f));
+                    atomicAdd(acc + TY * LS + off + 2 * p * LS,
+                              (unsigned long long)(long long)__float2int_rn(c2[u].y * f));
+                }
             }
         }
     }
