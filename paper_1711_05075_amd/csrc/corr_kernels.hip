@@ -918,6 +918,13 @@ __device__ __forceinline__ void spread_staged_w6(const SpreadStage& st, int nst,
     }
 }
 
+// Zero both planes of fixed-point sums (2 * PAIRS 64-bit words), 16 bytes a store.
+template <int PAIRS, int NT>
+__device__ __forceinline__ void clear_sums(unsigned long long* acc) {
+    ulonglong2* p = reinterpret_cast<ulonglong2*>(acc);
+    for (int t = threadIdx.x; t < PAIRS; t += NT) p[t] = make_ulonglong2(0ull, 0ull);
+}
+
 // One spreading tile (z row z0, y rows y0 .. y0+TY-1 of rotation s), for the
 // components c0 .. c1-1 (c0 even).  Entered by the whole workgroup; the LDS
 // regions are laid out by the caller.
@@ -971,7 +978,7 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
         return false;  // no knot reaches the tile: its spectrum is zero and is not written
     }
     int kept_all = 0;  // knots of the tile (counted while spreading the first pair)
-    for (int t = threadIdx.x; t < 2 * TY * LS; t += NT) acc[t] = 0ull;
+    clear_sums<TY * LS, NT>(acc);
     for (int cp = c0; cp < c1; cp += 2) {
         // with one block, the next pair's weights are read (a thread per staged
         // knot) while this pair is spread
@@ -1038,21 +1045,20 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
             __syncthreads();
         }
         fft_passes<M, 8, -1, TY, 1, SC, NT, true>(a, twl);  // only the kept band is read below
+        // both half spectra of a mode from one read of its two entries
         constexpr int PER = TY * H;
-        for (int t = threadIdx.x; t < 2 * PER; t += NT) {
-            const int comp = t >= PER;
-            const int r = t - comp * PER;
-            const int l = r / H, mm = r % H;
-            if (cp + comp >= q) continue;
+        const bool second = cp + 1 < q;
+        for (int t = threadIdx.x; t < PER; t += NT) {
+            const int l = t / H, mm = t % H;
             const float2 z1 = a[l * SC + mm];
             const float2 z2 = a[l * SC + ((M - mm) & (M - 1))];
-            const float2 o = comp ? make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x))
-                                  : make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
-            out[((((size_t)s * q + cp + comp) * M + z0) * M + y0 + l) * H + mm] = o;
+            float2* o = out + ((((size_t)s * q + cp) * M + z0) * M + y0 + l) * H + mm;
+            o[0] = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
+            if (second) o[(size_t)M * M * H] = make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x));
         }
         if (cp + 2 < c1) {
             __syncthreads();
-            for (int t = threadIdx.x; t < 2 * TY * LS; t += NT) acc[t] = 0ull;
+            clear_sums<TY * LS, NT>(acc);
         }
     }
     return true;
