@@ -704,7 +704,7 @@ __global__ __launch_bounds__(256) void k_scatter_plan(const int4* __restrict__ r
 template <int M, int TYP, int W>
 __device__ int stage_block(const int* __restrict__ sc_, const float* __restrict__ kb_,
                            const float* __restrict__ wq_, int q, int cp, float fix_scale, int y0,
-                           const int* rstart, const int* rpre, int nr, int cbeg, int cnt, SpreadStage st,
+                           const int* rstart, const int* rpre, int cbeg, int cnt, SpreadStage st,
                            int* wave_tot) {
     constexpr int TY = SpreadShape<M, TYP>::TY, LO = W / 2 - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -714,12 +714,12 @@ __device__ int stage_block(const int* __restrict__ sc_, const float* __restrict_
     float wz = 0.f;
     if ((int)threadIdx.x < cnt) {
         const int ci = cbeg + (int)threadIdx.x;
-        int r0 = 0, r1 = nr;  // the range holding ci: rpre[r0] <= ci < rpre[r0 + 1]
-        while (r1 - r0 > 1) {
-            const int mid = (r0 + r1) >> 1;
-            if (rpre[mid] <= ci) r0 = mid;
-            else r1 = mid;
-        }
+        // the range holding ci, rpre[r0] <= ci < rpre[r0 + 1]: the count of the
+        // (nondecreasing) prefix sums past the first that are <= ci, from
+        // independent reads rather than a chain of dependent ones
+        int r0 = 0;
+#pragma unroll
+        for (int r = 1; r < 2 * W; ++r) r0 += rpre[r] <= ci ? 1 : 0;
         p = rstart[r0] + (ci - rpre[r0]);
         packed = sc_[p];
         const float2* kw = reinterpret_cast<const float2*>(kb_ + (int64_t)p * 3 * W);
@@ -964,11 +964,11 @@ __device__ bool spread_tile(int s, int z0, int y0, int yt, int c0, int c1, const
     auto stage = [&](int b, int cp) {
         const int c0b = b * cap, cnt = min(cap, ncand - b * cap);
         switch (w) {  // the width as a constant: the loaded weights stay in registers
-        case 6: return stage_block<M, TYP, 6>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st, wave_tot);
-        case 8: return stage_block<M, TYP, 8>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st, wave_tot);
-        case 10: return stage_block<M, TYP, 10>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st,
+        case 6: return stage_block<M, TYP, 6>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, c0b, cnt, st, wave_tot);
+        case 8: return stage_block<M, TYP, 8>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, c0b, cnt, st, wave_tot);
+        case 10: return stage_block<M, TYP, 10>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, c0b, cnt, st,
                                            wave_tot);
-        default: return stage_block<M, TYP, 12>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, nr, c0b, cnt, st,
+        default: return stage_block<M, TYP, 12>(sc_, kb_, wq_, q, cp, fix_scale, y0, rstart, rpre, c0b, cnt, st,
                                            wave_tot);
         }
     };
