@@ -880,7 +880,7 @@ template <int M, int TYP>
 __device__ __forceinline__ void spread_staged_w6(const SpreadStage& st, int nst,
                                                  unsigned long long* __restrict__ acc) {
     using SS = SpreadShape<M, TYP>;
-    constexpr int TY = SS::TY, LS = SS::LS, NW = kSpreadThreads / 64, U = 2, W = 6;
+    constexpr int TY = SS::TY, LS = SS::LS, NW = kSpreadThreads / 64, U = 1, W = 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = lane / 12, r = lane - slot * 12, ddy = r / W, ddx = r - ddy * W;
     const int loff = ddy * LS + ddx;
