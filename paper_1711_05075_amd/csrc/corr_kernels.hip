@@ -1193,7 +1193,7 @@ struct RegPass {
     static constexpr int NB = LEN / 8, WORK = NB * COLS, NBF = (WORK + NT - 1) / NT;
 };
 
-// Raw buffer view of one array of float2: the buffer unit checks every
+// Raw buffer view of one array (float2 or float): the buffer unit checks every
 // offset against the array's size, and a load at or past the end returns zero
 // without touching memory.  A column read that skips dead rows then needs no
 // branch (offset kPastEnd), and the compiler can count the loads in flight
