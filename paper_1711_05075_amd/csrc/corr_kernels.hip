@@ -1720,9 +1720,9 @@ __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ 
     // and a wave's 64 points are two whole mask words
     static_assert((2 * COLS * N) % kThreads == 0, "output loop must be whole");
     extern __shared__ float2 lds[];
-    __shared__ float red_v[kThreads];
-    __shared__ int red_i[kThreads];
-    __shared__ int red_c[kThreads];
+    __shared__ float red_v[kThreads / 64];
+    __shared__ int red_i[kThreads / 64];
+    __shared__ int red_c[kThreads / 64];
     float2* a = lds;
     float2* twl = a + COLS * SC;
     load_table<N>(twl, twn);
@@ -1780,26 +1780,37 @@ __global__ __launch_bounds__(kThreads) void k_ifft_x(const float2* __restrict__ 
             }
         }
     }
-    red_v[threadIdx.x] = best;
-    red_i[threadIdx.x] = besti;
-    red_c[threadIdx.x] = cnt;
-    __syncthreads();
-    for (int off = kThreads / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            const float v2 = red_v[threadIdx.x + off];
-            const int i2 = red_i[threadIdx.x + off];
-            if (v2 > red_v[threadIdx.x] || (v2 == red_v[threadIdx.x] && i2 < red_i[threadIdx.x])) {
-                red_v[threadIdx.x] = v2;
-                red_i[threadIdx.x] = i2;
-            }
-            red_c[threadIdx.x] += red_c[threadIdx.x + off];
+    // the largest value (lowest index among equals) and the count: within each
+    // wave by lane shuffles, then over the waves; the result does not depend
+    // on the order of the comparisons
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float v2 = __shfl_down(best, off, 64);
+        const int i2 = __shfl_down(besti, off, 64);
+        cnt += __shfl_down(cnt, off, 64);
+        if (v2 > best || (v2 == best && i2 < besti)) {
+            best = v2;
+            besti = i2;
         }
-        __syncthreads();
     }
+    const int wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red_v[wv] = best;
+        red_i[wv] = besti;
+        red_c[wv] = cnt;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        pval[(size_t)s * gridDim.x + blockIdx.x] = red_v[0];
-        pidx[(size_t)s * gridDim.x + blockIdx.x] = red_i[0];
-        if (pcnt) pcnt[(size_t)s * gridDim.x + blockIdx.x] = red_c[0];
+        for (int k = 1; k < kThreads / 64; ++k) {
+            if (red_v[k] > best || (red_v[k] == best && red_i[k] < besti)) {
+                best = red_v[k];
+                besti = red_i[k];
+            }
+            cnt += red_c[k];
+        }
+        pval[(size_t)s * gridDim.x + blockIdx.x] = best;
+        pidx[(size_t)s * gridDim.x + blockIdx.x] = besti;
+        if (pcnt) pcnt[(size_t)s * gridDim.x + blockIdx.x] = cnt;
     }
 }
 
