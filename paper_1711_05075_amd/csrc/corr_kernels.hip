@@ -1820,10 +1820,11 @@ __global__ __launch_bounds__(kThreads) void k_peak_final(const float* __restrict
                                                          const int* __restrict__ pcnt, int nblocks,
                                                          float* __restrict__ out_val, int64_t* __restrict__ out_idx,
                                                          int64_t* __restrict__ out_cnt) {
-    __shared__ float red_v[kThreads];
-    __shared__ int red_i[kThreads];
-    __shared__ long long red_c[kThreads];
-    const int s = blockIdx.x;
+    constexpr int NWV = kThreads / 64;
+    __shared__ float red_v[NWV];
+    __shared__ int red_i[NWV];
+    __shared__ long long red_c[NWV];
+    const int s = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float best = -INFINITY;
     int besti = 0x7fffffff;
     long long cnt = 0;
@@ -1836,31 +1837,37 @@ __global__ __launch_bounds__(kThreads) void k_peak_final(const float* __restrict
         }
         if (out_cnt) cnt += pcnt[(size_t)s * nblocks + t];
     }
-    red_c[threadIdx.x] = cnt;
-    __syncthreads();
-    for (int off = kThreads / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red_c[threadIdx.x] += red_c[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (out_cnt && threadIdx.x == 0) out_cnt[s] = red_c[0];
-    if (!out_val) return;
-    red_v[threadIdx.x] = best;
-    red_i[threadIdx.x] = besti;
-    __syncthreads();
-    for (int off = kThreads / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            const float v2 = red_v[threadIdx.x + off];
-            const int i2 = red_i[threadIdx.x + off];
-            if (v2 > red_v[threadIdx.x] || (v2 == red_v[threadIdx.x] && i2 < red_i[threadIdx.x])) {
-                red_v[threadIdx.x] = v2;
-                red_i[threadIdx.x] = i2;
-            }
+    // within each wave by lane shuffles, then over the waves (the largest value,
+    // lowest index among equals, and the count do not depend on the order)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float v2 = __shfl_down(best, off, 64);
+        const int i2 = __shfl_down(besti, off, 64);
+        cnt += __shfl_down(cnt, off, 64);
+        if (v2 > best || (v2 == best && i2 < besti)) {
+            best = v2;
+            besti = i2;
         }
-        __syncthreads();
     }
+    if (lane == 0) {
+        red_v[wv] = best;
+        red_i[wv] = besti;
+        red_c[wv] = cnt;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        out_val[s] = red_v[0];
-        out_idx[s] = red_i[0];
+        for (int k = 1; k < NWV; ++k) {
+            if (red_v[k] > best || (red_v[k] == best && red_i[k] < besti)) {
+                best = red_v[k];
+                besti = red_i[k];
+            }
+            cnt += red_c[k];
+        }
+        if (out_cnt) out_cnt[s] = cnt;
+        if (out_val) {
+            out_val[s] = best;
+            out_idx[s] = besti;
+        }
     }
 }
 
