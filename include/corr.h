@@ -453,17 +453,18 @@ int corr_batch_info(const corr_batch* b, int32_t pair, corr_info_t* out);
 
 /*
  * Autotuner of a batch: runs corr_batch_eval (these arguments) under candidate
- * launch shapes applied to every pair and keeps the fastest, by coordinate
- * descent: spread_wgs (one, one and a half or two per CU), then each column
- * pass's width, the bin group and the tile height, each by rank among each
- * pair's own choices (0 the pair's default, 1 and 2 the others of
+ * launch shapes and keeps the fastest, by coordinate descent: spread_wgs (one,
+ * one and a half or two per CU, for every pair), then, for each grid size of
+ * the batch in turn (largest first, applied to the pairs on that grid), each
+ * column pass's width, the bin group and the tile height, each by rank among
+ * each pair's own choices (0 the pair's default, 1 and 2 the others of
  * corr_tuning_choices where its grid has them).  Rotations per pass stay as
  * planned at create.  Each candidate is timed by HIP events as the least of
  * `reps` (1..100) runs after an untimed one.  No tuning changes a bit of the
  * outputs, which hold the last evaluation.  Synchronous.  out7 (host int32
- * [7], or NULL): spread_wgs, the four column ranks, the bin-group rank and
- * the tile-height rank kept.  After an error the pairs' previous tunings are
- * restored.
+ * [7], or NULL): spread_wgs, and the four column ranks, the bin-group rank
+ * and the tile-height rank kept for the batch's largest grid.  After an error
+ * the pairs' previous tunings are restored.
  */
 int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* rot_offsets, float* scores_dev,
                         const int64_t* score_offsets, float* peak_val_dev, int64_t* peak_idx_dev, int32_t reps,

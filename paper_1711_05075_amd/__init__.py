@@ -729,7 +729,8 @@ class Batch:
         """Run corr_batch_autotune on these rotations with the caller's output
         tensors out = (packed scores or None, peak_val, peak_idx); returns the
         kept choice {spread_wgs, rank of each column pass's width, rank of the
-        bin group, rank of the tile height}."""
+        bin group, rank of the tile height}, the ranks those of the largest
+        grid (each grid size of the batch is tuned on its own)."""
         counts = [len(q) for q in quats_per_pair]
         offs = np.ascontiguousarray(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64))
         q = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64).reshape(-1, 4)

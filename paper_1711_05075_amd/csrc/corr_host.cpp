@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -2324,15 +2325,28 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
         b->err = "corr_batch_autotune: reps must be in 1..100";
         return CORR_EINVAL;
     }
-    // a candidate: spread_wgs and, per column pass, for the bin group and for
-    // the tile height, the rank of the value among each pair's choices (0 its
-    // default, 1 and 2 the others where they exist)
+    // a candidate: spread_wgs and, for each grid size of the batch (largest
+    // first), per column pass, for the bin group and for the tile height, the
+    // rank of the value among each pair's choices (0 its default, 1 and 2 the
+    // others where they exist)
+    constexpr int kMaxGrids = 8;
     struct Cand {
         int wgs;
-        int rank[6];
+        int rank[kMaxGrids][6];
     };
     std::vector<corr_tuning> start;
     for (corr_ctx* c : b->pairs) start.push_back(get_tuning(c));
+    std::vector<int> grids;  // distinct spreading grids, largest first
+    for (corr_ctx* c : b->pairs)
+        if (std::find(grids.begin(), grids.end(), c->g.m) == grids.end()) grids.push_back(c->g.m);
+    std::sort(grids.begin(), grids.end(), std::greater<int>());
+    std::vector<int> grid_of(b->pairs.size());
+    for (size_t i = 0; i < b->pairs.size(); ++i)
+        grid_of[i] = (int)(std::find(grids.begin(), grids.end(), b->pairs[i]->g.m) - grids.begin());
+    if ((int)grids.size() > kMaxGrids) {  // grids are powers of two from 32 to 512: cannot happen
+        b->err = "corr_batch_autotune: too many grid sizes";
+        return CORR_EUNSUPPORTED;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = guarded(nullptr, [&] {
         hip_check(hipEventCreate(&e0), "hipEventCreate");
@@ -2345,6 +2359,7 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
     auto apply = [&](const Cand& k) {
         for (size_t i = 0; i < b->pairs.size(); ++i) {
             corr_ctx* c = b->pairs[i];
+            const int* rank = k.rank[grid_of[i]];
             corr_tuning t = start[i];
             t.spread_wgs = k.wgs;
             int32_t corr_tuning::*fields[4] = {&corr_tuning::cols_y, &corr_tuning::cols_z, &corr_tuning::cols_iy,
@@ -2352,19 +2367,20 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
             for (int p = 0; p < 4; ++p) {
                 int ch[3];
                 const int n = corr::col_choices(c->g.m, p, ch);
-                t.*fields[p] = ch[k.rank[p] < n ? k.rank[p] : 0];
+                t.*fields[p] = ch[rank[p] < n ? rank[p] : 0];
             }
             int bg[3];
             const int nb = corr::bin_choices(c->g.m, bg);
-            t.bin_group = bg[k.rank[4] < nb ? k.rank[4] : 0];
+            t.bin_group = bg[rank[4] < nb ? rank[4] : 0];
             int tr[2];
             const int nt = corr::tile_choices(c->g.m, tr);
-            t.tile_rows = tr[k.rank[5] < nt ? k.rank[5] : 0];
+            t.tile_rows = tr[rank[5] < nt ? rank[5] : 0];
             set_tuning(c, t);
         }
     };
     float best_ms = INFINITY;
-    Cand cur{start.empty() ? 1 : start[0].spread_wgs, {0, 0, 0, 0, 0, 0}};
+    Cand cur{};
+    cur.wgs = start.empty() ? 1 : start[0].spread_wgs;
     auto timed = [&](const Cand& k) -> float {
         apply(k);
         auto unit = [&] {
@@ -2398,16 +2414,17 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
                 cur = k;
             }
         }
-        for (int p = 0; p < 6; ++p)
-            for (int r = 1; r < (p == 5 ? 2 : 3); ++r) {
-                Cand k = cur;
-                k.rank[p] = r;
-                const float ms = timed(k);
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    cur = k;
+        for (size_t gi = 0; gi < grids.size(); ++gi)
+            for (int p = 0; p < 6; ++p)
+                for (int r = 1; r < (p == 5 ? 2 : 3); ++r) {
+                    Cand k = cur;
+                    k.rank[gi][p] = r;
+                    const float ms = timed(k);
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        cur = k;
+                    }
                 }
-            }
         apply(cur);
         // the outputs hold an evaluation under the kept tuning
         const int r = corr_batch_eval(b, quat_wxyz, rot_offsets, scores_dev, score_offsets, peak_val_dev, peak_idx_dev);
@@ -2429,7 +2446,7 @@ int corr_batch_autotune(corr_batch* b, const double* quat_wxyz, const int64_t* r
     }
     if (out7) {
         out7[0] = cur.wgs;
-        for (int p = 0; p < 6; ++p) out7[1 + p] = cur.rank[p];
+        for (int p = 0; p < 6; ++p) out7[1 + p] = cur.rank[0][p];  // the largest grid's
     }
     return CORR_OK;
 }

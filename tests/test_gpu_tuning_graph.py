@@ -269,10 +269,10 @@ def test_batch_graph_replays_match_the_eager_batch():
 
 
 def test_batch_autotune_keeps_every_bit():
-    # the batch autotuner tries every spreading workgroup count, every width
-    # rank of every column pass and every bin-group rank on all pairs; whatever
-    # it keeps, and every
-    # candidate it ran (the outputs hold the last), the results stay bitwise
+    # the batch autotuner tries every spreading workgroup count, and for each
+    # grid size in turn every width rank of every column pass, every bin-group
+    # rank and every tile height; whatever it keeps, and every candidate it ran
+    # (the outputs hold the last), the results stay bitwise
     from paper_1711_05075_amd import Batch
     pairs, quats = [], []
     for p, (n, na, nb) in enumerate(((32, 700, 300), (64, 1500, 900), (128, 400, 500), (32, 2500, 1200))):
