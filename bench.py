@@ -522,10 +522,11 @@ def measure_uneven(args, torch, pkg, cpu=True, kb_width=None):
     b.set_graph(False)
     tuned = None
     if not args.no_autotune:
-        # the library's batch autotuner (launch shapes of every pair), then timed
+        # the library's batch autotuner (launch shapes of every pair, each grid
+        # size apart; the least of two timed runs per candidate), then timed
         # launch by launch and as a graph under the kept tuning
         t0 = time.perf_counter()
-        tuned = b.autotune(quats, (s, pv, pi), reps=1)
+        tuned = b.autotune(quats, (s, pv, pi), reps=2)
         tuned["seconds"] = time.perf_counter() - t0
         rows["autotuned"] = _timed(torch, step, args.warmup, args.steps)
         b.set_graph(True)
