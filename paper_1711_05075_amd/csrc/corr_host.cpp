@@ -2243,6 +2243,8 @@ int corr_batch_eval(corr_batch* b, const double* quat_wxyz, const int64_t* rot_o
         for (int p = 0; p <= np; ++p) key.push_back((uint64_t)rot_offsets[p]);
         if (score_offsets)
             for (int p = 0; p < np; ++p) key.push_back((uint64_t)score_offsets[p]);
+        // a pair's launch shapes (its tuning) are part of what the graph holds
+        for (corr_ctx* c : b->pairs) key.push_back(c->shape_gen);
         graph_launch(b->gs, b->stream, std::move(key), b->pairs, nullptr, [&] { run(dq); });
     });
     if (rc != CORR_OK) b->err = cur && cur->err != "no error" ? cur->err : g_thread_error;
